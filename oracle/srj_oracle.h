@@ -1,0 +1,98 @@
+/*
+ * srj_oracle.h - CPU reference implementation of the Scheduled Relaxation
+ * Jacobi (SRJ) method with the data-driven scheme selector of Islam & Wang,
+ * "A data driven heuristic for rapid convergence of Scheduled Relaxation
+ * Jacobi schemes" (arXiv 2011.06636).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and srj_oracle.c are the slow,
+ * plain reference that the GPU library is checked against.  They share no
+ * code, header, table or constant with the GPU library, and the library never
+ * links, loads or calls them.
+ *
+ * Grid convention: interior grid n[0] x n[1] x n[2] (unused axes = 1), axis 0
+ * contiguous, flat index p = i0 + n0*(i1 + n1*i2).  Homogeneous Dirichlet:
+ * the ghost layer is zero and not stored.
+ */
+#ifndef SRJ_ORACLE_H
+#define SRJ_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A = D + L + U (section 2, Eq. 1) as a symmetric stencil.
+ * A[p][p] = diag ? diag[p] : dconst.
+ * A[p][p+e_d] = A[p+e_d][p] = -(face[d] ? face[d][p] : c[d]). */
+typedef struct {
+    int32_t ndim;
+    int64_t n[3];
+    double c[3];
+    const double *face[3];
+    double dconst;
+    const double *diag;
+    const double *b;
+} srjo_problem;
+
+enum { SRJO_RULE_HEURISTIC = 0, SRJO_RULE_INCREASING = 1, SRJO_RULE_FIXED = 2,
+       SRJO_RULE_JACOBI = 3 };
+enum { SRJO_TOL_RELATIVE = 0, SRJO_TOL_ABSOLUTE = 1 };
+enum { SRJO_PREC_F64 = 0, SRJO_PREC_F32 = 1, SRJO_PREC_F16 = 2, SRJO_PREC_BF16 = 3 };
+enum { SRJO_OK = 0, SRJO_INVALID = 1, SRJO_NOT_CONVERGED = 4, SRJO_NONFINITE = 5 };
+
+typedef struct {
+    int32_t rule;           /* SRJO_RULE_* */
+    int32_t fixed_level;    /* level used by SRJO_RULE_FIXED */
+    int32_t tol_mode;       /* SRJO_TOL_* */
+    double tol;
+    int32_t max_cycles;
+    int64_t max_sweeps;
+    int32_t stop_per_sweep; /* 1: test the residual after every sweep (F64 only) */
+    int32_t precision;      /* SRJO_PREC_*: inner-cycle precision of the refinement */
+    int32_t start_level;
+    int32_t max_level;      /* highest selectable level (<= 24) */
+    double scale_target;    /* refinement: target RMS of the scaled residual */
+} srjo_opts;
+
+typedef struct {
+    int32_t status;
+    int32_t converged;
+    int32_t cycles;
+    int32_t final_level;
+    int64_t sweeps;
+    double r0;
+    double r_final;
+    double min_margin;      /* min |ratio - 0.2|, |ratio - 0.4| over selector calls */
+} srjo_result;
+
+int32_t srjo_num_levels(void);
+int32_t srjo_level_M(int32_t level);
+/* Eq. (17): relaxation factors of the length-M scheme in natural root order. */
+void srjo_omega_natural(int32_t M, double *w);
+/* Execution order of a scheme: a permutation of 0..M-1 (section 2, last paragraph). */
+void srjo_leja_order(int32_t M, const double *w, int32_t *order);
+/* Factors of a level in execution order; returns M. */
+int32_t srjo_scheme(int32_t level, double *w_out);
+
+/* One relaxed Jacobi sweep (Eq. 3, residual form), x_out must not alias x. */
+void srjo_sweep(const srjo_problem *p, const double *x, double w, double *x_out);
+/* ||b - A x||_2 with the sum taken sequentially in index order. */
+double srjo_residual_norm(const srjo_problem *p, const double *x);
+/* y = A x */
+void srjo_apply(const srjo_problem *p, const double *x, double *y);
+
+/* Solve to tolerance.  levels_out[max_cycles] and norms_out[max_cycles+1]
+ * may be NULL.  norms_out[0] is the initial residual norm. */
+int32_t srjo_solve(const srjo_problem *p, double *x, const srjo_opts *o,
+                   srjo_result *res, int32_t *levels_out, double *norms_out);
+
+/* Storage roundings used by the 16-bit refinement modes. */
+float srjo_round_f16(float v);
+float srjo_round_bf16(float v);
+int32_t srjo_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

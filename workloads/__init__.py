@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs for the SRJ solver and for its CPU reference.
+
+This module builds problems only: grid sizes, stencil couplings, diagonals and
+right-hand sides, drawn from ``numpy.random.default_rng(seed)`` in a fixed
+order.  It contains none of the solver's arithmetic (no relaxation factors, no
+sweeps, no residuals, no scheme selection), so both the GPU library's tests and
+the CPU reference can take their inputs from here without sharing any of the
+method's code.
+
+Array convention (used by every consumer): a problem on an ``n0 x n1 x n2``
+interior grid stores each field as a float64 NumPy array of C-order shape
+``(n2, n1, n0)``, i.e. axis 0 is the contiguous one and the flat index of
+point ``(i0, i1, i2)`` is ``i0 + n0 * (i1 + n1 * i2)``.  Unused axes have
+size 1.  Boundary conditions are homogeneous Dirichlet: the ghost layer around
+the grid is zero and is not stored.
+
+The matrix is ``A = D + L + U`` (section 2, Eq. 1) with
+
+* ``A[p, p] = D_p`` (``dconst`` or ``diag[p]``);
+* ``A[p, p + e_d] = A[p + e_d, p] = -coupling_d(p)``, where
+  ``coupling_d(p) = c[d]`` for a constant stencil or ``face[d][p]`` (the
+  coupling between point ``p`` and ``p + e_d``) for a variable one.
+
+Recipes (the paper's own problems, section 3 and section 4, plus the
+benchmark workloads built in their image):
+
+* ``poisson``: finite-difference Poisson on the unit interval / square / cube
+  with ``h_d = 1/(n_d + 1)``, coupling ``1/h_d^2`` and diagonal
+  ``sum_d 2/h_d^2`` (the 1D matrix of section 3, the 3D problem of
+  section 4.2.3).
+* ``c1``: 1D, N = 255, b ~ U(-1, 1) (seed 0).
+* ``c2``: 2D 2048 x 2048, b = sum of 8 random-amplitude low sine modes plus
+  U(-1e-3, 1e-3) noise (seed 0).
+* ``c3``: 3D 256^3 variable coefficient -div(k grad u) = 1, with k
+  log-normal (sigma = 1, Gaussian correlation length 8 cells), harmonic-mean
+  faces and ``D_p`` equal to the sum of the six face couplings (seed 0).
+* ``c4``: 512 2D Poisson squares with log-uniform sides in [64, 1024] and
+  b ~ U(-1, 1) (instance i uses seed 1000 + i).
+* ``c5``: 128 3D anisotropic boxes, sides uniform in [32, 128], couplings
+  (1, a, b) with a, b log-uniform in [0.01, 1], unit spacing, b ~ U(-1, 1)
+  (instance i uses seed 2000 + i).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Problem", "poisson", "poisson_1d", "sine_mode", "c1", "c2", "c3",
+    "c4_instance", "c4", "c5_instance", "c5", "lognormal_field",
+    "variable_coefficient", "anisotropic",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """A symmetric stencil matrix A = D + L + U and a right-hand side b."""
+
+    ndim: int
+    n: Tuple[int, int, int]
+    c: Tuple[float, float, float]
+    dconst: float
+    b: np.ndarray
+    faces: Optional[List[Optional[np.ndarray]]] = None
+    diag: Optional[np.ndarray] = None
+    name: str = ""
+
+    @property
+    def npoints(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        """NumPy shape of every field: (n2, n1, n0)."""
+        return (int(self.n[2]), int(self.n[1]), int(self.n[0]))
+
+    def zeros(self) -> np.ndarray:
+        return np.zeros(self.shape, dtype=np.float64)
+
+    def check(self) -> None:
+        assert self.ndim in (1, 2, 3)
+        for d in range(3):
+            assert self.n[d] >= 1
+            if d >= self.ndim:
+                assert self.n[d] == 1
+        assert self.b.shape == self.shape and self.b.dtype == np.float64
+        if self.faces is not None:
+            assert len(self.faces) == 3
+            for f in self.faces:
+                if f is not None:
+                    assert f.shape == self.shape and f.dtype == np.float64
+        if self.diag is not None:
+            assert self.diag.shape == self.shape and self.diag.dtype == np.float64
+
+
+def _dims(n: Sequence[int]) -> Tuple[int, Tuple[int, int, int]]:
+    n = [int(v) for v in n]
+    ndim = len(n)
+    assert 1 <= ndim <= 3
+    return ndim, tuple(n + [1] * (3 - ndim))  # type: ignore[return-value]
+
+
+def poisson(n: Sequence[int], b: Optional[np.ndarray] = None, name: str = "") -> Problem:
+    """Finite-difference Poisson -Laplace(u) = f on the unit box, Dirichlet zero.
+
+    Spacing ``h_d = 1/(n_d + 1)`` on every axis; coupling ``1/h_d^2``; diagonal
+    ``sum_d 2/h_d^2`` (the tridiagonal matrix (1/dx^2) tridiag(-1, 2, -1) of
+    section 3 in 1D).  ``b`` defaults to all ones (f = 1).
+    """
+    ndim, n3 = _dims(n)
+    c = [0.0, 0.0, 0.0]
+    for d in range(ndim):
+        c[d] = float((n3[d] + 1) ** 2)
+    dconst = 2.0 * sum(c)
+    shape = (n3[2], n3[1], n3[0])
+    if b is None:
+        b = np.ones(shape, dtype=np.float64)
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(shape))
+    return Problem(ndim, n3, tuple(c), dconst, b, name=name or f"poisson{ndim}d")
+
+
+def poisson_1d(N: int, b: Optional[np.ndarray] = None) -> Problem:
+    return poisson([N], b=b, name=f"poisson1d_N{N}")
+
+
+def anisotropic(n: Sequence[int], coup: Sequence[float], b: np.ndarray, name: str = "") -> Problem:
+    """-(u_xx + a u_yy + b u_zz) = f on unit spacing: couplings ``coup``, D = 2 sum(coup)."""
+    ndim, n3 = _dims(n)
+    c = [0.0, 0.0, 0.0]
+    for d in range(ndim):
+        c[d] = float(coup[d])
+    shape = (n3[2], n3[1], n3[0])
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(shape))
+    return Problem(ndim, n3, tuple(c), 2.0 * sum(c), b, name=name or "anisotropic")
+
+
+def sine_mode(n: Sequence[int], k: Sequence[int]) -> np.ndarray:
+    """Discrete Dirichlet sine mode prod_d sin(k_d pi i_d / (n_d + 1)), i_d = 1..n_d."""
+    ndim, n3 = _dims(n)
+    k3 = list(k) + [1] * (3 - len(k))
+    out = np.ones((n3[2], n3[1], n3[0]), dtype=np.float64)
+    for d in range(ndim):
+        i = np.arange(1, n3[d] + 1, dtype=np.float64)
+        v = np.sin(k3[d] * np.pi * i / (n3[d] + 1))
+        shp = [1, 1, 1]
+        shp[2 - d] = n3[d]
+        out = out * v.reshape(shp)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Benchmark workloads
+# --------------------------------------------------------------------------
+
+def c1(seed: int = 0, N: int = 255) -> Problem:
+    """1D Poisson, N = 255, b ~ U(-1, 1).  h = 1/256 so 1/h^2 = 2^16 exactly."""
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(-1.0, 1.0, size=(1, 1, N))
+    return poisson([N], b=b, name=f"c1_poisson1d_N{N}")
+
+
+def c2(seed: int = 0, n: int = 2048) -> Problem:
+    """2D Poisson on an n x n grid; b = 8 low sine modes + U(-1e-3, 1e-3) noise.
+
+    Draw order: 8 amplitudes a_m ~ U(-1, 1), then 8 wavenumbers k_m, then 8
+    wavenumbers l_m (each uniform on {1..8}), then the noise field in storage
+    order.  Mode m is a_m sin(k_m pi x) sin(l_m pi y) with x along axis 0.
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=8)
+    kx = rng.integers(1, 9, size=8)
+    ly = rng.integers(1, 9, size=8)
+    noise = rng.uniform(-1e-3, 1e-3, size=(n, n))
+    h = 1.0 / (n + 1)
+    xs = np.arange(1, n + 1, dtype=np.float64) * h
+    b = np.zeros((n, n), dtype=np.float64)
+    for m in range(8):
+        b += a[m] * np.outer(np.sin(ly[m] * np.pi * xs), np.sin(kx[m] * np.pi * xs))
+    b += noise
+    return poisson([n, n], b=b.reshape(1, n, n), name=f"c2_poisson2d_{n}")
+
+
+def lognormal_field(shape: Tuple[int, int, int], rng: np.random.Generator,
+                    corr_len: float = 8.0, sigma: float = 1.0) -> np.ndarray:
+    """k = exp(sigma g) with g a zero-mean, unit-variance Gaussian field.
+
+    g is white noise filtered on the periodic box by exp(-l^2 |kappa|^2 / 4),
+    the square root of the spectrum of the covariance exp(-d^2 / (2 l^2)).
+    """
+    noise = rng.standard_normal(size=shape)
+    spec = np.fft.rfftn(noise)
+    kz = 2.0 * np.pi * np.fft.fftfreq(shape[0])
+    ky = 2.0 * np.pi * np.fft.fftfreq(shape[1])
+    kx = 2.0 * np.pi * np.fft.rfftfreq(shape[2])
+    k2 = (kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    spec *= np.exp(-(corr_len ** 2) * k2 / 4.0)
+    del k2
+    g = np.fft.irfftn(spec, s=shape, axes=(0, 1, 2))
+    del spec
+    g -= g.mean()
+    g /= g.std()
+    return np.exp(sigma * g)
+
+
+def variable_coefficient(n: int, seed: int, corr_len: float = 8.0, sigma: float = 1.0,
+                         name: str = "") -> Problem:
+    """-div(k grad u) = 1 on the unit cube, n^3 interior nodes, Dirichlet zero.
+
+    k lives on all (n+2)^3 nodes (boundary nodes included).  The coupling
+    across the face between nodes p and q is the harmonic mean
+    2 k_p k_q / (k_p + k_q) divided by h^2; D_p is the sum of the couplings of
+    its six faces, boundary faces included.
+    """
+    rng = np.random.default_rng(seed)
+    m = n + 2
+    k = lognormal_field((m, m, m), rng, corr_len=corr_len, sigma=sigma)
+    inv_h2 = float((n + 1) ** 2)
+    inner = k[1:-1, 1:-1, 1:-1]
+
+    def hmean(a, b):
+        return 2.0 * a * b / (a + b)
+
+    # upper faces along each axis (axis 0 = last numpy axis)
+    up0 = hmean(inner, k[1:-1, 1:-1, 2:]) * inv_h2
+    up1 = hmean(inner, k[1:-1, 2:, 1:-1]) * inv_h2
+    up2 = hmean(inner, k[2:, 1:-1, 1:-1]) * inv_h2
+    lo0 = hmean(inner, k[1:-1, 1:-1, :-2]) * inv_h2
+    lo1 = hmean(inner, k[1:-1, :-2, 1:-1]) * inv_h2
+    lo2 = hmean(inner, k[:-2, 1:-1, 1:-1]) * inv_h2
+    diag = up0 + lo0
+    diag += up1
+    diag += lo1
+    diag += up2
+    diag += lo2
+    del lo0, lo1, lo2
+    b = np.ones((n, n, n), dtype=np.float64)
+    faces = [np.ascontiguousarray(up0), np.ascontiguousarray(up1), np.ascontiguousarray(up2)]
+    return Problem(3, (n, n, n), (0.0, 0.0, 0.0), 0.0, b, faces=faces,
+                   diag=np.ascontiguousarray(diag), name=name or f"varcoef3d_{n}")
+
+
+def c3(seed: int = 0, n: int = 256) -> Problem:
+    return variable_coefficient(n, seed, name=f"c3_varcoef3d_{n}")
+
+
+def c4_instance(i: int, lo: int = 64, hi: int = 1024) -> Problem:
+    """Instance i of the 2D batch: side n = round(exp(U(ln lo, ln hi))), b ~ U(-1, 1)."""
+    rng = np.random.default_rng(1000 + i)
+    n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+    b = rng.uniform(-1.0, 1.0, size=(1, n, n))
+    return poisson([n, n], b=b, name=f"c4_{i}_poisson2d_{n}")
+
+
+def c4(count: int = 512, lo: int = 64, hi: int = 1024) -> List[Problem]:
+    return [c4_instance(i, lo, hi) for i in range(count)]
+
+
+def c5_instance(i: int, lo: int = 32, hi: int = 128) -> Problem:
+    """Instance i of the 3D anisotropic batch.
+
+    Draw order: the three sides (uniform on {lo..hi}), then a and b
+    (log-uniform on [0.01, 1]), then the right-hand side U(-1, 1).
+    """
+    rng = np.random.default_rng(2000 + i)
+    n = [int(v) for v in rng.integers(lo, hi + 1, size=3)]
+    ab = np.exp(rng.uniform(math.log(0.01), math.log(1.0), size=2))
+    rhs = rng.uniform(-1.0, 1.0, size=(n[2], n[1], n[0]))
+    return anisotropic(n, (1.0, float(ab[0]), float(ab[1])), rhs,
+                       name=f"c5_{i}_aniso3d_{n[0]}x{n[1]}x{n[2]}")
+
+
+def c5(count: int = 128, lo: int = 32, hi: int = 128) -> List[Problem]:
+    return [c5_instance(i, lo, hi) for i in range(count)]
