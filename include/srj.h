@@ -1,0 +1,199 @@
+/*
+ * srj.h - C ABI of an MI355X (gfx950) solver for A x = b by Scheduled
+ * Relaxation Jacobi (SRJ) with a data-driven choice of scheme per cycle.
+ *
+ * Method: Islam & Wang, "A data driven heuristic for rapid convergence of
+ * Scheduled Relaxation Jacobi schemes", arXiv 2011.06636.
+ *   - matrix splitting A = D + L + U: section 2, Eq. 1;
+ *   - relaxed Jacobi sweep x <- x + w D^-1 (b - A x): section 2, Eq. 3
+ *     (residual form of the same update);
+ *   - SRJ cycle = M sweeps with the factors of one scheme: section 2, Eq. 7;
+ *   - scheme family w_j = (l* + 1) / (2 (l* - x_j)), x_j the roots of the
+ *     Chebyshev polynomial T_M and T_M(l*) = 3: section 2, Eq. (17);
+ *   - scheme level -> M: Appendix B (25 levels, M = 1 ... 2362);
+ *   - next level from the ratio of the residual norms after and before a
+ *     cycle: section 3, Algorithm 1 (ratio > 0.4: up one level; 0.2 < ratio
+ *     < 0.4: down one level; otherwise keep);
+ *   - stopping: L2 residual norm (section 4.1) or relative L2 residual
+ *     (section 4.2.3, Eq. (27)), tested at the end of each cycle.
+ *
+ * Problems are symmetric stencil matrices on a structured n0 x n1 x n2
+ * interior grid (unused axes have size 1) with homogeneous Dirichlet ghosts:
+ *   A[p][p]       = diag ? diag[p] : dconst              (> 0)
+ *   A[p][p + e_d] = A[p + e_d][p] = -(face[d] ? face[d][p] : cconst[d])
+ * Every field is a dense array of n0*n1*n2 binary64 values with axis 0
+ * contiguous: point (i0, i1, i2) is element i0 + n0*(i1 + n1*i2).  A
+ * non-zero Dirichlet boundary is folded into b by the caller.
+ *
+ * Arithmetic: binary64, round to nearest even, with no contraction into
+ * fused multiply-add, in the fixed per-point order
+ *   s = D_p x_p;  for d = 0..ndim-1: s -= c_lo * x[p - e_d]; s -= c_hi * x[p + e_d];
+ *   x'_p = x_p + w * ((1 / D_p) * (b_p - s))
+ * (ghost neighbours contribute nothing), so iterates do not depend on tiling
+ * or on the number of sweeps fused into one kernel.  The refinement modes
+ * run the inner cycles on the correction equation in binary32 arithmetic.
+ *
+ * Memory and streams.  All array pointers passed to setup/solve calls are
+ * DEVICE pointers owned by the caller and borrowed by the library: they must
+ * stay valid, and b/faces/diag unchanged, until the context is destroyed.
+ * The library owns its workspaces (ping-pong buffers, reduction scratch,
+ * scheme tables).  All device work is enqueued on the hipStream_t given at
+ * setup (NULL = the null stream).  Calls that return host values block until
+ * those values are valid.  A context must not be used by two threads at once.
+ *
+ * Errors.  Every call returns an srj_status; no exception crosses the ABI.
+ * Arguments are validated before any device work (SRJ_ERR_INVALID).
+ * srj_last_error() returns a thread-local description of the last non-OK
+ * status.
+ */
+#ifndef SRJ_H
+#define SRJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srj_ctx srj_ctx;
+typedef struct srj_batch srj_batch;
+
+typedef enum {
+    SRJ_OK = 0,
+    SRJ_ERR_INVALID = 1,       /* bad argument; nothing was run */
+    SRJ_ERR_NOMEM = 2,         /* device or host allocation failed */
+    SRJ_ERR_HIP = 3,           /* a HIP runtime call failed */
+    SRJ_ERR_NOT_CONVERGED = 4, /* a cap was reached; results are filled */
+    SRJ_ERR_NONFINITE = 5,     /* a residual norm was NaN/Inf; x holds the last iterate */
+    SRJ_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+} srj_status;
+
+typedef enum {
+    SRJ_PREC_F64 = 0,        /* plain binary64 SRJ */
+    SRJ_PREC_F32_REFINE = 1, /* binary32 inner cycles, binary64 outer refinement */
+    SRJ_PREC_F16_REFINE = 2, /* binary16 storage of the correction, binary32 math */
+    SRJ_PREC_BF16_REFINE = 3 /* bfloat16 storage of the correction, binary32 math */
+} srj_precision;
+
+typedef enum {
+    SRJ_RULE_HEURISTIC = 0,  /* Algorithm 1 */
+    SRJ_RULE_INCREASING = 1, /* level + 1 every cycle (comparison rule of section 4) */
+    SRJ_RULE_FIXED = 2       /* fixed_level every cycle */
+} srj_rule;
+
+typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1 } srj_tol_mode;
+
+#define SRJ_NUM_LEVELS 25
+#define SRJ_MAX_M 2362
+
+typedef struct {
+    int32_t ndim;          /* 1, 2 or 3 */
+    int64_t n[3];          /* interior sizes, >= 1; n[d] == 1 for d >= ndim */
+    double cconst[3];      /* coupling on axis d when face[d] == NULL */
+    const double *face[3]; /* optional device array: coupling between p and p + e_d */
+    double dconst;         /* diagonal when diag == NULL; must be > 0 */
+    const double *diag;    /* optional device array: diagonal D (> 0) */
+    const double *b;       /* device array: right-hand side (required) */
+} srj_problem;
+
+typedef struct {
+    srj_rule rule;
+    int32_t fixed_level;      /* SRJ_RULE_FIXED only, 0..24 */
+    srj_tol_mode tol_mode;
+    double tol;               /* > 0 */
+    int32_t max_cycles;       /* >= 1 */
+    int64_t max_sweeps;       /* >= 1 */
+    srj_precision precision;
+    int32_t start_level;      /* first cycle's level, 0..max_level */
+    int32_t max_level;        /* highest level the rules may choose, 0..24 */
+    double scale_target;      /* refinement: target RMS of the scaled residual (0 = default) */
+    double r0;                /* resume: reference norm for SRJ_TOL_RELATIVE (<= 0: computed) */
+} srj_solve_opts;
+
+typedef struct {
+    int32_t converged;
+    int32_t cycles;
+    int32_t final_level;      /* level of the last cycle run */
+    int32_t reserved;
+    int64_t sweeps;           /* relaxation sweeps run (sum of M over cycles) */
+    double r0;                /* initial (or resumed reference) residual norm */
+    double r_final;           /* residual norm after the last cycle */
+    double min_margin;        /* min |ratio - 0.2|, |ratio - 0.4| over selector calls */
+} srj_solve_result;
+
+/* Fill opts with defaults: heuristic rule, relative tolerance 1e-10,
+ * max_cycles 10000, max_sweeps 5e7, binary64, start level 0, max level 24. */
+void srj_default_opts(srj_solve_opts *opts);
+
+/* Relaxation factors of scheme `level` (Appendix B level, Eq. (17)
+ * factors) in the order a cycle applies them: Leja order of the roots
+ * 1 - 1/w_j of the amplification polynomial, largest factor first (section 2,
+ * last paragraph, which cycles the factors for robustness to round-off).
+ * Writes min(M, cap) values to omega_out (host memory) and M to *M_out.
+ * SRJ_ERR_INVALID if level is outside 0..24 or a pointer is NULL. */
+srj_status srj_scheme(int32_t level, double *omega_out, int32_t cap, int32_t *M_out);
+
+/* Create a solver context for problem *p (section 2, Eq. 1).  Validates
+ * the description (ndim, sizes, dconst > 0 when diag is NULL, b != NULL),
+ * allocates workspaces and precomputes 1/D on the device.  hip_stream is a
+ * hipStream_t (NULL: null stream).  On success *out owns the workspaces. */
+srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out);
+
+/* One SRJ cycle (section 2, Eq. 7) of scheme `level` on the device array x
+ * (in/out, n0*n1*n2 binary64), followed by the L2 norm of b - A x written to
+ * *resnorm_out (host).  Blocks until *resnorm_out is valid. */
+srj_status srj_run_cycle(srj_ctx *ctx, double *x, int32_t level, double *resnorm_out);
+
+/* L2 norm of b - A x for the device array x (host result, blocking). */
+srj_status srj_residual_norm(srj_ctx *ctx, const double *x, double *norm_out);
+
+/* Solve A x = b from the initial guess in x (device, in/out) with cycles
+ * whose schemes the rule picks (Algorithm 1 by default), until the cycle-end
+ * residual norm is below tol (times r0 for SRJ_TOL_RELATIVE) or a cap is
+ * reached.  levels_out (host, max_cycles entries) receives the level of each
+ * cycle and norms_out (host, max_cycles + 1 entries) the initial norm and
+ * each cycle-end norm; either may be NULL.  Returns SRJ_OK when converged,
+ * SRJ_ERR_NOT_CONVERGED at a cap and SRJ_ERR_NONFINITE on a NaN/Inf norm,
+ * with *res filled in every one of these cases. */
+srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_solve_result *res,
+                     int32_t *levels_out, double *norms_out);
+
+/* Kernel plan of a context (tuning only; every plan gives bit-identical
+ * iterates).  kind 0: one sweep per launch, any problem.  kind 1: 2D
+ * constant-coefficient register tiles of 64 columns x tile_rows rows (32, 48
+ * or 64) that fuse up to sweeps_per_launch sweeps (<= 4, 6 or 8) per launch.
+ * SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
+srj_status srj_set_plan(srj_ctx *ctx, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch);
+srj_status srj_get_plan(srj_ctx *ctx, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch);
+
+/* Profiling aid.  While enabled, the relaxation launches of every cycle
+ * are bracketed by HIP events recorded on the context's stream; the elapsed
+ * times (ms), the number of sweep launches and of sweeps are accumulated.
+ * Enabling (or re-enabling) clears the totals. */
+srj_status srj_set_profiling(srj_ctx *ctx, int32_t enable);
+srj_status srj_get_profile(srj_ctx *ctx, double *sweep_ms, int64_t *launches, int64_t *sweeps);
+
+/* Release a context and its workspaces (NULL is accepted). */
+srj_status srj_destroy(srj_ctx *ctx);
+
+/* Batched solves: `count` independent problems (each as in srj_setup), all
+ * run by the same launches with per-instance scheme choice (Algorithm 1)
+ * and per-instance stopping.  probs[i].b etc. are borrowed device pointers. */
+srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_stream,
+                           srj_batch **out);
+
+/* xs[i] is instance i's device solution array (in/out).  res[count] and
+ * levels_out[count * max_cycles] (may be NULL) are host arrays.  Returns
+ * SRJ_OK if every instance converged, else the first non-OK status. */
+srj_status srj_batch_solve(srj_batch *batch, double *const *xs, const srj_solve_opts *opts,
+                           srj_solve_result *res, int32_t *levels_out);
+
+srj_status srj_batch_destroy(srj_batch *batch);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char *srj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRJ_H */

@@ -1,0 +1,206 @@
+"""ctypes binding of libsrj.so (the C ABI declared in include/srj.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions keep the C names (srj_setup, srj_run_cycle, srj_solve, ...).
+If libsrj.so has not been built, load() raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsrj.so")
+
+SRJ_OK = 0
+SRJ_ERR_INVALID = 1
+SRJ_ERR_NOMEM = 2
+SRJ_ERR_HIP = 3
+SRJ_ERR_NOT_CONVERGED = 4
+SRJ_ERR_NONFINITE = 5
+SRJ_ERR_UNSUPPORTED = 6
+STATUS_NAMES = {0: "ok", 1: "invalid", 2: "nomem", 3: "hip", 4: "not_converged",
+                5: "nonfinite", 6: "unsupported"}
+
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+RULE = {"heuristic": 0, "increasing": 1, "fixed": 2}
+TOL_MODE = {"relative": 0, "absolute": 1}
+NUM_LEVELS = 25
+MAX_M = 2362
+
+# Public entry points of include/srj.h (checked by the tests).
+EXPORTS = [
+    "srj_default_opts", "srj_scheme", "srj_setup", "srj_run_cycle", "srj_residual_norm",
+    "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_set_profiling",
+    "srj_get_profile", "srj_batch_setup",
+    "srj_batch_solve", "srj_batch_destroy", "srj_last_error",
+]
+
+
+class SrjProblem(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("cconst", ctypes.c_double * 3), ("face", ctypes.c_void_p * 3),
+                ("dconst", ctypes.c_double), ("diag", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+
+
+class SrjSolveOpts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("fixed_level", ctypes.c_int32),
+                ("tol_mode", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int32), ("max_sweeps", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("start_level", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("scale_target", ctypes.c_double),
+                ("r0", ctypes.c_double)]
+
+
+class SrjSolveResult(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("final_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sweeps", ctypes.c_int64), ("r0", ctypes.c_double),
+                ("r_final", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsrj.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "srj_default_opts": (None, [P(SrjSolveOpts)]),
+        "srj_scheme": (i32, [i32, P(f64), i32, P(i32)]),
+        "srj_setup": (i32, [P(SrjProblem), vp, P(vp)]),
+        "srj_run_cycle": (i32, [vp, vp, i32, P(f64)]),
+        "srj_residual_norm": (i32, [vp, vp, P(f64)]),
+        "srj_solve": (i32, [vp, vp, P(SrjSolveOpts), P(SrjSolveResult), P(i32), P(f64)]),
+        "srj_destroy": (i32, [vp]),
+        "srj_set_plan": (i32, [vp, i32, i32, i32]),
+        "srj_get_plan": (i32, [vp, P(i32), P(i32), P(i32)]),
+        "srj_set_profiling": (i32, [vp, i32]),
+        "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
+        "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
+        "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
+        "srj_batch_destroy": (i32, [vp]),
+        "srj_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().srj_last_error().decode()
+
+
+class SrjError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.name}: {last_error()}")
+
+
+def check(status: int, where: str, ok=(SRJ_OK,)) -> int:
+    if status not in ok:
+        raise SrjError(status, where)
+    return status
+
+
+# Thin wrappers with the C names ------------------------------------------------
+
+def srj_default_opts() -> SrjSolveOpts:
+    o = SrjSolveOpts()
+    load().srj_default_opts(ctypes.byref(o))
+    return o
+
+
+def srj_scheme(level: int):
+    buf = (ctypes.c_double * MAX_M)()
+    M = ctypes.c_int32()
+    check(load().srj_scheme(level, buf, MAX_M, ctypes.byref(M)), "srj_scheme")
+    return [buf[i] for i in range(M.value)]
+
+
+def srj_setup(prob: SrjProblem, stream: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(load().srj_setup(ctypes.byref(prob), ctypes.c_void_p(stream), ctypes.byref(h)),
+          "srj_setup")
+    return h
+
+
+def srj_run_cycle(ctx, x_ptr: int, level: int) -> float:
+    nrm = ctypes.c_double()
+    check(load().srj_run_cycle(ctx, ctypes.c_void_p(x_ptr), level, ctypes.byref(nrm)),
+          "srj_run_cycle")
+    return nrm.value
+
+
+def srj_residual_norm(ctx, x_ptr: int) -> float:
+    nrm = ctypes.c_double()
+    check(load().srj_residual_norm(ctx, ctypes.c_void_p(x_ptr), ctypes.byref(nrm)),
+          "srj_residual_norm")
+    return nrm.value
+
+
+def srj_solve(ctx, x_ptr: int, opts: SrjSolveOpts, levels=None, norms=None):
+    res = SrjSolveResult()
+    st = load().srj_solve(ctx, ctypes.c_void_p(x_ptr), ctypes.byref(opts), ctypes.byref(res),
+                          levels, norms)
+    return st, res
+
+
+def srj_set_plan(ctx, kind: int, tile_rows: int = 0, sweeps: int = 1) -> int:
+    return load().srj_set_plan(ctx, kind, tile_rows, sweeps)
+
+
+def srj_get_plan(ctx):
+    k, r, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(load().srj_get_plan(ctx, ctypes.byref(k), ctypes.byref(r), ctypes.byref(t)),
+          "srj_get_plan")
+    return k.value, r.value, t.value
+
+
+def srj_set_profiling(ctx, enable: bool) -> None:
+    check(load().srj_set_profiling(ctx, 1 if enable else 0), "srj_set_profiling")
+
+
+def srj_get_profile(ctx):
+    ms, la, sw = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    check(load().srj_get_profile(ctx, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(sw)),
+          "srj_get_profile")
+    return ms.value, la.value, sw.value
+
+
+def srj_destroy(ctx) -> None:
+    if ctx:
+        load().srj_destroy(ctx)
+
+
+def srj_batch_setup(probs, stream: int = 0):
+    arr = (SrjProblem * len(probs))(*probs)
+    h = ctypes.c_void_p()
+    st = load().srj_batch_setup(len(probs), arr, ctypes.c_void_p(stream), ctypes.byref(h))
+    return st, h
+
+
+def srj_batch_solve(batch, x_ptrs, opts: SrjSolveOpts, levels=None):
+    n = len(x_ptrs)
+    xs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(p) for p in x_ptrs])
+    res = (SrjSolveResult * n)()
+    st = load().srj_batch_solve(batch, xs, ctypes.byref(opts), res, levels)
+    return st, res
+
+
+def srj_batch_destroy(batch) -> None:
+    if batch:
+        load().srj_batch_destroy(batch)

@@ -1,0 +1,444 @@
+// C ABI entry points and the host side of the solve loop.
+//
+// Method: Islam & Wang, arXiv 2011.06636.  A cycle is M relaxed Jacobi
+// sweeps with the factors of one scheme level (section 2, Eq. 7 and
+// Eq. (17); levels from Appendix B).  After each cycle the L2 residual norm
+// is reduced on the device and read back; Algorithm 1 (section 3) picks the
+// next level from the ratio of the norms after and before the cycle.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.h"
+
+namespace srj {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+srj_status fail(srj_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+}  // namespace srj
+
+using namespace srj;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct srj_ctx {
+    DevProblem P{};
+    hipStream_t stream = nullptr;
+    int64_t npoints = 0;
+    double *ws = nullptr;         // ping-pong partner of the caller's x
+    double *dinv = nullptr;       // 1/diag when diag is given
+    double *omega_dev = nullptr;  // all levels, execution order
+    std::vector<int32_t> offsets; // level -> first factor in omega_dev
+    ReduceScratch rs;
+    SweepPlan plan;
+    struct Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
+    // Profiling: HIP events around the sweep launches of each cycle.
+    bool profiling = false;
+    bool prof_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0, prof_sweeps = 0, prof_pending_launches = 0, prof_pending_sweeps = 0;
+};
+
+namespace srj {
+// Refinement entry point (refine.hip).
+srj_status refine_solve(srj_ctx *ctx, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                        int32_t *levels_out, double *norms_out);
+void refine_free(srj_ctx *ctx);
+}  // namespace srj
+
+namespace {
+
+srj_status validate_problem(const srj_problem *p)
+{
+    if (!p) return fail(SRJ_ERR_INVALID, "problem is NULL");
+    if (p->ndim < 1 || p->ndim > 3) return fail(SRJ_ERR_INVALID, "ndim must be 1, 2 or 3");
+    for (int d = 0; d < 3; ++d) {
+        if (p->n[d] < 1) return fail(SRJ_ERR_INVALID, "every n[d] must be >= 1");
+        if (d >= p->ndim && p->n[d] != 1) return fail(SRJ_ERR_INVALID, "n[d] must be 1 for d >= ndim");
+        if (d < p->ndim && !p->face[d] && !(p->cconst[d] >= 0.0) )
+            return fail(SRJ_ERR_INVALID, "cconst[d] must be finite and >= 0");
+    }
+    if (p->n[1] > 65535 || p->n[2] > 65535)
+        return fail(SRJ_ERR_INVALID, "n[1] and n[2] must be <= 65535");
+    if (!p->b) return fail(SRJ_ERR_INVALID, "b is NULL");
+    if (!p->diag && !(p->dconst > 0.0) ) return fail(SRJ_ERR_INVALID, "dconst must be > 0");
+    if (!p->diag && !isfinite(p->dconst)) return fail(SRJ_ERR_INVALID, "dconst must be finite");
+    return SRJ_OK;
+}
+
+srj_status validate_opts(const srj_solve_opts *o)
+{
+    if (!o) return fail(SRJ_ERR_INVALID, "opts is NULL");
+    if (o->rule < SRJ_RULE_HEURISTIC || o->rule > SRJ_RULE_FIXED)
+        return fail(SRJ_ERR_INVALID, "unknown rule");
+    if (o->rule == SRJ_RULE_FIXED && (o->fixed_level < 0 || o->fixed_level >= SRJ_NUM_LEVELS))
+        return fail(SRJ_ERR_INVALID, "fixed_level outside 0..24");
+    if (o->tol_mode != SRJ_TOL_RELATIVE && o->tol_mode != SRJ_TOL_ABSOLUTE)
+        return fail(SRJ_ERR_INVALID, "unknown tol_mode");
+    if (!(o->tol > 0.0)) return fail(SRJ_ERR_INVALID, "tol must be > 0");
+    if (o->max_cycles < 1) return fail(SRJ_ERR_INVALID, "max_cycles must be >= 1");
+    if (o->max_sweeps < 1) return fail(SRJ_ERR_INVALID, "max_sweeps must be >= 1");
+    if (o->max_level < 0 || o->max_level >= SRJ_NUM_LEVELS)
+        return fail(SRJ_ERR_INVALID, "max_level outside 0..24");
+    if (o->start_level < 0 || o->start_level > o->max_level)
+        return fail(SRJ_ERR_INVALID, "start_level outside 0..max_level");
+    if (o->precision < SRJ_PREC_F64 || o->precision > SRJ_PREC_BF16_REFINE)
+        return fail(SRJ_ERR_INVALID, "unknown precision");
+    if (!(o->scale_target >= 0.0)) return fail(SRJ_ERR_INVALID, "scale_target must be >= 0");
+    return SRJ_OK;
+}
+
+SweepPlan default_plan(const DevProblem &P)
+{
+    SweepPlan pl;
+    pl.kind = 0;
+    pl.T = 1;
+    if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
+        pl.kind = 1;
+        pl.by = 48;
+        pl.T = 6;
+    }
+    return pl;
+}
+
+}  // namespace
+
+namespace srj {
+
+// Sweeps of one cycle.  *cur holds the iterate; the pointers are swapped
+// after every launch so that *cur always names the latest iterate.
+srj_status run_sweeps(srj_ctx *c, double **cur, double **nxt, int level)
+{
+    const std::vector<double> &w = level_factors(level);
+    const int M = static_cast<int>(w.size());
+    const double *wdev = c->omega_dev + c->offsets[level];
+    int64_t launches = 0;
+    if (c->profiling) SRJ_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
+    if (c->plan.kind != 0 && fused_supported(c->P, c->plan)) {
+        for (int done = 0; done < M;) {
+            const int T = std::min(c->plan.T, M - done);
+            SRJ_HIP_CHECK(launch_sweep_fused(c->P, c->plan, *cur, *nxt, wdev + done, T, c->stream));
+            std::swap(*cur, *nxt);
+            done += T;
+            ++launches;
+        }
+    } else {
+        for (int k = 0; k < M; ++k) {
+            SRJ_HIP_CHECK(launch_sweep_generic(c->P, *cur, *nxt, w[k], c->stream));
+            std::swap(*cur, *nxt);
+            ++launches;
+        }
+    }
+    if (c->profiling) {
+        SRJ_HIP_CHECK(hipEventRecord(c->ev1, c->stream));
+        c->prof_pending = true;
+        c->prof_pending_launches = launches;
+        c->prof_pending_sweeps = M;
+    }
+    return SRJ_OK;
+}
+
+// Folds the last cycle's event pair into the profile (after a stream sync).
+srj_status collect_profile(srj_ctx *c)
+{
+    if (!c->profiling || !c->prof_pending) return SRJ_OK;
+    float ms = 0.f;
+    SRJ_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->prof_ms += ms;
+    c->prof_launches += c->prof_pending_launches;
+    c->prof_sweeps += c->prof_pending_sweeps;
+    c->prof_pending = false;
+    return SRJ_OK;
+}
+
+srj_status residual_norm(srj_ctx *c, const double *x, double *out)
+{
+    SRJ_HIP_CHECK(launch_residual_sumsq(c->P, x, c->rs, c->stream));
+    SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    *out = sqrt(*c->rs.host_sum);
+    return collect_profile(c);
+}
+
+int next_level(srj_rule rule, int level, double ratio, int max_level)
+{
+    int nl = level;
+    if (rule == SRJ_RULE_HEURISTIC) {
+        if (ratio > 0.4)
+            nl = level + 1;
+        else if (ratio < 0.4 && ratio > 0.2)
+            nl = level - 1;
+    } else if (rule == SRJ_RULE_INCREASING) {
+        nl = level + 1;
+    }
+    return std::max(0, std::min(nl, max_level));
+}
+
+}  // namespace srj
+
+extern "C" {
+
+void srj_default_opts(srj_solve_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->rule = SRJ_RULE_HEURISTIC;
+    o->fixed_level = 0;
+    o->tol_mode = SRJ_TOL_RELATIVE;
+    o->tol = 1e-10;
+    o->max_cycles = 10000;
+    o->max_sweeps = 50000000;
+    o->precision = SRJ_PREC_F64;
+    o->start_level = 0;
+    o->max_level = SRJ_NUM_LEVELS - 1;
+    o->scale_target = 0.0;
+    o->r0 = 0.0;
+}
+
+const char *srj_last_error(void) { return g_last_error.c_str(); }
+
+srj_status srj_scheme(int32_t level, double *omega_out, int32_t cap, int32_t *M_out)
+{
+    if (level < 0 || level >= SRJ_NUM_LEVELS) return fail(SRJ_ERR_INVALID, "level outside 0..24");
+    if (!M_out || (cap > 0 && !omega_out)) return fail(SRJ_ERR_INVALID, "NULL output pointer");
+    const std::vector<double> &w = level_factors(level);
+    *M_out = static_cast<int32_t>(w.size());
+    const int n = std::min<int>(cap, static_cast<int>(w.size()));
+    for (int i = 0; i < n; ++i) omega_out[i] = w[i];
+    return SRJ_OK;
+}
+
+srj_status srj_destroy(srj_ctx *c)
+{
+    if (!c) return SRJ_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    refine_free(c);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    (void)hipFree(c->ws);
+    (void)hipFree(c->dinv);
+    (void)hipFree(c->omega_dev);
+    (void)hipFree(c->rs.partials);
+    (void)hipFree(c->rs.sum);
+    (void)hipHostFree(c->rs.host_sum);
+    delete c;
+    return SRJ_OK;
+}
+
+srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
+{
+    if (!out) return fail(SRJ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    srj_status st = validate_problem(p);
+    if (st != SRJ_OK) return st;
+
+    srj_ctx *c = new srj_ctx();
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    DevProblem &P = c->P;
+    P.ndim = p->ndim;
+    P.n0 = p->n[0];
+    P.n1 = p->n[1];
+    P.n2 = p->n[2];
+    for (int d = 0; d < 3; ++d) {
+        P.c[d] = d < p->ndim ? p->cconst[d] : 0.0;
+        P.face[d] = d < p->ndim ? p->face[d] : nullptr;
+    }
+    P.dconst = p->diag ? 0.0 : p->dconst;
+    P.dinvconst = p->diag ? 0.0 : 1.0 / p->dconst;
+    P.diag = p->diag;
+    P.b = p->b;
+    c->npoints = P.n0 * P.n1 * P.n2;
+    const size_t bytes = sizeof(double) * (size_t)c->npoints;
+
+    auto nomem = [&](const char *what) {
+        srj_destroy(c);
+        return fail(SRJ_ERR_NOMEM, std::string("hipMalloc failed for ") + what);
+    };
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) return nomem("ping-pong buffer");
+    if (p->diag) {
+        if (hipMalloc(&c->dinv, bytes) != hipSuccess) return nomem("1/D");
+        hipError_t e = compute_dinv(p->diag, c->dinv, c->npoints, c->stream);
+        if (e != hipSuccess) {
+            srj_destroy(c);
+            return fail(SRJ_ERR_HIP, std::string("1/D kernel: ") + hipGetErrorString(e));
+        }
+        P.dinv = c->dinv;
+    }
+    std::vector<double> table;
+    full_table(table, c->offsets);
+    if (hipMalloc(&c->omega_dev, sizeof(double) * table.size()) != hipSuccess)
+        return nomem("scheme table");
+    hipError_t e = hipMemcpyAsync(c->omega_dev, table.data(), sizeof(double) * table.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    c->rs.capacity = residual_blocks(P);
+    if (e == hipSuccess && hipMalloc(&c->rs.partials, sizeof(double) * c->rs.capacity) != hipSuccess)
+        return nomem("reduction partials");
+    if (e == hipSuccess && hipMalloc(&c->rs.sum, sizeof(double)) != hipSuccess) return nomem("sum");
+    if (e == hipSuccess && hipHostMalloc(&c->rs.host_sum, sizeof(double), 0) != hipSuccess)
+        return nomem("pinned scalar");
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        srj_destroy(c);
+        return fail(SRJ_ERR_HIP, std::string("setup: ") + hipGetErrorString(e));
+    }
+    c->plan = default_plan(P);
+    *out = c;
+    return SRJ_OK;
+}
+
+srj_status srj_set_plan(srj_ctx *c, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch)
+{
+    if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
+    SweepPlan pl;
+    pl.kind = kind;
+    pl.by = tile_rows;
+    pl.T = sweeps_per_launch;
+    if (kind == 0) {
+        pl.T = 1;
+        c->plan = pl;
+        return SRJ_OK;
+    }
+    if (!fused_supported(c->P, pl)) return fail(SRJ_ERR_UNSUPPORTED, "plan not supported for this problem");
+    c->plan = pl;
+    return SRJ_OK;
+}
+
+srj_status srj_get_plan(srj_ctx *c, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch)
+{
+    if (!c || !kind || !tile_rows || !sweeps_per_launch) return fail(SRJ_ERR_INVALID, "NULL argument");
+    *kind = c->plan.kind;
+    *tile_rows = c->plan.by;
+    *sweeps_per_launch = c->plan.T;
+    return SRJ_OK;
+}
+
+srj_status srj_set_profiling(srj_ctx *c, int32_t enable)
+{
+    if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
+    if (enable && !c->ev0) {
+        SRJ_HIP_CHECK(hipEventCreate(&c->ev0));
+        SRJ_HIP_CHECK(hipEventCreate(&c->ev1));
+    }
+    c->profiling = enable != 0;
+    c->prof_pending = false;
+    c->prof_ms = 0.0;
+    c->prof_launches = c->prof_sweeps = 0;
+    return SRJ_OK;
+}
+
+srj_status srj_get_profile(srj_ctx *c, double *sweep_ms, int64_t *launches, int64_t *sweeps)
+{
+    if (!c || !sweep_ms || !launches || !sweeps) return fail(SRJ_ERR_INVALID, "NULL argument");
+    *sweep_ms = c->prof_ms;
+    *launches = c->prof_launches;
+    *sweeps = c->prof_sweeps;
+    return SRJ_OK;
+}
+
+srj_status srj_residual_norm(srj_ctx *c, const double *x, double *norm_out)
+{
+    if (!c || !x || !norm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
+    return residual_norm(c, x, norm_out);
+}
+
+srj_status srj_run_cycle(srj_ctx *c, double *x, int32_t level, double *resnorm_out)
+{
+    if (!c || !x || !resnorm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
+    if (level < 0 || level >= SRJ_NUM_LEVELS) return fail(SRJ_ERR_INVALID, "level outside 0..24");
+    double *cur = x, *nxt = c->ws;
+    srj_status st = run_sweeps(c, &cur, &nxt, level);
+    if (st != SRJ_OK) return st;
+    if (cur != x)
+        SRJ_HIP_CHECK(hipMemcpyAsync(x, cur, sizeof(double) * (size_t)c->npoints,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    return residual_norm(c, x, resnorm_out);
+}
+
+srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                     int32_t *levels_out, double *norms_out)
+{
+    if (!c || !x || !res) return fail(SRJ_ERR_INVALID, "NULL argument");
+    srj_status st = validate_opts(o);
+    if (st != SRJ_OK) return st;
+    memset(res, 0, sizeof(*res));
+    res->min_margin = INFINITY;
+    if (o->precision != SRJ_PREC_F64) return refine_solve(c, x, o, res, levels_out, norms_out);
+
+    double *cur = x, *nxt = c->ws;
+    double norm0 = 0.0;
+    st = residual_norm(c, x, &norm0);
+    if (st != SRJ_OK) return st;
+    const double r0 = o->r0 > 0.0 ? o->r0 : norm0;
+    res->r0 = r0;
+    res->r_final = norm0;
+    if (norms_out) norms_out[0] = norm0;
+    const double target = o->tol_mode == SRJ_TOL_RELATIVE ? o->tol * r0 : o->tol;
+    srj_status status = SRJ_ERR_NOT_CONVERGED;
+    int level = o->start_level;
+    double prev = norm0;
+    if (!isfinite(norm0)) {
+        status = fail(SRJ_ERR_NONFINITE, "initial residual norm is not finite");
+    } else if (norm0 == 0.0 || norm0 < target) {
+        res->converged = 1;
+        status = SRJ_OK;
+    } else {
+        for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
+            const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
+            const int M = level_m(lv);
+            if (res->sweeps + M > o->max_sweeps) break;
+            st = run_sweeps(c, &cur, &nxt, lv);
+            if (st != SRJ_OK) return st;
+            res->sweeps += M;
+            double norm = 0.0;
+            st = residual_norm(c, cur, &norm);
+            if (st != SRJ_OK) return st;
+            res->cycles = cycle + 1;
+            res->r_final = norm;
+            res->final_level = lv;
+            if (levels_out) levels_out[cycle] = lv;
+            if (norms_out) norms_out[cycle + 1] = norm;
+            if (!isfinite(norm)) {
+                status = fail(SRJ_ERR_NONFINITE, "residual norm is not finite");
+                break;
+            }
+            if (norm < target) {
+                res->converged = 1;
+                status = SRJ_OK;
+                break;
+            }
+            const double ratio = norm / prev;
+            prev = norm;
+            if (o->rule == SRJ_RULE_HEURISTIC) {
+                const double m = std::min(fabs(ratio - 0.2), fabs(ratio - 0.4));
+                res->min_margin = std::min(res->min_margin, m);
+            }
+            level = next_level(o->rule, level, ratio, o->max_level);
+        }
+        if (status == SRJ_ERR_NOT_CONVERGED) set_error("cycle or sweep cap reached");
+    }
+    if (cur != x)
+        SRJ_HIP_CHECK(hipMemcpyAsync(x, cur, sizeof(double) * (size_t)c->npoints,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return status;
+}
+
+}  // extern "C"

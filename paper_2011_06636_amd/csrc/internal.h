@@ -1,0 +1,93 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "srj.h"
+
+namespace srj {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+srj_status fail(srj_status st, const std::string &msg);
+
+#define SRJ_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            return ::srj::fail(SRJ_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Scheme family (host): Appendix B levels, Eq. (17) factors, Leja order.
+// ---------------------------------------------------------------------------
+int level_m(int level);                      // -1 if outside 0..24
+const std::vector<double> &level_factors(int level);  // execution order, cached
+// Concatenated table of all levels in execution order; offsets[l]..offsets[l+1].
+void full_table(std::vector<double> &omega, std::vector<int32_t> &offsets);
+
+// ---------------------------------------------------------------------------
+// Device view of a problem
+// ---------------------------------------------------------------------------
+struct DevProblem {
+    int32_t ndim;
+    int32_t pad_;
+    int64_t n0, n1, n2;
+    double c[3];
+    const double *face[3];  // nullptr: constant coupling c[d]
+    double dconst, dinvconst;
+    const double *diag;     // nullptr: constant diagonal
+    const double *dinv;     // 1/diag (library-owned) when diag != nullptr
+    const double *b;
+};
+
+// Binary32 operator used by the refinement inner cycles.
+struct DevProblem32 {
+    int32_t ndim;
+    int32_t pad_;
+    int64_t n0, n1, n2;
+    float c[3];
+    const float *face[3];
+    float dconst, dinvconst;
+    const float *diag;
+    const float *dinv;
+};
+
+// Reduction scratch: per-block partial sums and the final sum.
+struct ReduceScratch {
+    double *partials = nullptr;
+    int64_t capacity = 0;
+    double *sum = nullptr;       // device scalar
+    double *host_sum = nullptr;  // pinned host scalar
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (sweep.hip, reduce.hip, refine.hip)
+// ---------------------------------------------------------------------------
+hipError_t compute_dinv(const double *diag, double *dinv, int64_t n, hipStream_t s);
+
+// One binary64 sweep x -> xo with factor w, T sweeps fused when possible.
+struct SweepPlan {
+    int kind = 0;   // 0 = generic one-sweep kernel, 1 = 2D tiled, 2 = 3D streaming
+    int T = 1;      // sweeps fused per launch
+    int bx = 0, by = 0;
+};
+hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo, double w,
+                                hipStream_t s);
+// Fused sweeps: applies w[0..T-1] (device pointer into the scheme table).
+hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
+                              double *xo, const double *w_dev, int T, hipStream_t s);
+bool fused_supported(const DevProblem &P, const SweepPlan &plan);
+
+// Sum of (b - A x)^2 into scratch.sum (device); blocks needed for scratch sizing.
+int64_t residual_blocks(const DevProblem &P);
+hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
+                                 hipStream_t s);
+
+}  // namespace srj

@@ -1,0 +1,110 @@
+// Cycle-end residual r = b - A x and its squared L2 norm (Islam & Wang,
+// arXiv 2011.06636: the L2 residual norm drives the scheme choice of
+// section 3 and the stopping tests of section 4, e.g. Eq. (27)).
+//
+// The per-point residual uses the same expression order as the sweeps.  The
+// sum of squares is deterministic: wave shuffles and an LDS tree inside each
+// block, one partial per block, then one block folds the partials in a fixed
+// order.  No floating-point atomics.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace srj {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kFinal = 1024;
+
+// Fixed-order sum over the 64 lanes of a wave, result in lane 0.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        t = lds[0];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) t += lds[i];
+    }
+    return t;
+}
+
+template <int ND>
+__global__ __launch_bounds__(kBlock) void k_residual_sumsq(DevProblem P,
+                                                           const double *__restrict__ x,
+                                                           double *__restrict__ partials)
+{
+    __shared__ double lds[kBlock / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i1 = blockIdx.y, i2 = blockIdx.z;
+    double rr = 0.0;
+    if (i0 < P.n0) {
+        const int64_t s1 = P.n0, s2 = P.n0 * P.n1;
+        const int64_t p = i0 + s1 * i1 + s2 * i2;
+        double s = (P.diag ? P.diag[p] : P.dconst) * x[p];
+        if (i0 > 0) s = s - (P.face[0] ? P.face[0][p - 1] : P.c[0]) * x[p - 1];
+        if (i0 < P.n0 - 1) s = s - (P.face[0] ? P.face[0][p] : P.c[0]) * x[p + 1];
+        if (ND >= 2) {
+            if (i1 > 0) s = s - (P.face[1] ? P.face[1][p - s1] : P.c[1]) * x[p - s1];
+            if (i1 < P.n1 - 1) s = s - (P.face[1] ? P.face[1][p] : P.c[1]) * x[p + s1];
+        }
+        if (ND >= 3) {
+            if (i2 > 0) s = s - (P.face[2] ? P.face[2][p - s2] : P.c[2]) * x[p - s2];
+            if (i2 < P.n2 - 1) s = s - (P.face[2] ? P.face[2][p] : P.c[2]) * x[p + s2];
+        }
+        const double r = P.b[p] - s;
+        rr = r * r;
+    }
+    const double t = block_sum<kBlock / 64>(rr, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+}
+
+// One block: thread i sums partials i, i + 1024, ... in order, then a fixed tree.
+__global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ partials, int64_t n,
+                                                 double *__restrict__ out)
+{
+    __shared__ double lds[kFinal / 64];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kFinal) v += partials[i];
+    const double t = block_sum<kFinal / 64>(v, lds);
+    if (threadIdx.x == 0) *out = t;
+}
+
+}  // namespace
+
+int64_t residual_blocks(const DevProblem &P)
+{
+    return ((P.n0 + kBlock - 1) / kBlock) * P.n1 * P.n2;
+}
+
+hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
+                                 hipStream_t s)
+{
+    const dim3 grid((unsigned)((P.n0 + kBlock - 1) / kBlock), (unsigned)P.n1, (unsigned)P.n2);
+    const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
+    if (nb > rs.capacity) return hipErrorInvalidValue;
+    switch (P.ndim) {
+    case 1: hipLaunchKernelGGL(k_residual_sumsq<1>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
+    case 2: hipLaunchKernelGGL(k_residual_sumsq<2>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
+    default: hipLaunchKernelGGL(k_residual_sumsq<3>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFinal), 0, s, rs.partials, nb, rs.sum);
+    return hipGetLastError();
+}
+
+}  // namespace srj

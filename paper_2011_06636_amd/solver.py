@@ -1,0 +1,139 @@
+"""PyTorch-facing wrapper of the C ABI: device memory and streams only.
+
+torch supplies device buffers (``data_ptr()``) and the current HIP stream;
+every arithmetic step runs in libsrj.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def _dev(a, device) -> torch.Tensor:
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64))
+    return t.to(device=device, non_blocking=False).contiguous()
+
+
+def make_problem(ndim: int, n: Sequence[int], c: Sequence[float], dconst: float,
+                 b: torch.Tensor, faces: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                 diag: Optional[torch.Tensor] = None) -> abi.SrjProblem:
+    """srj_problem from device tensors (the tensors must outlive the context)."""
+    p = abi.SrjProblem()
+    p.ndim = ndim
+    for d in range(3):
+        p.n[d] = int(n[d])
+        p.cconst[d] = float(c[d])
+        f = faces[d] if faces is not None else None
+        p.face[d] = f.data_ptr() if f is not None else None
+    p.dconst = float(dconst)
+    p.diag = diag.data_ptr() if diag is not None else None
+    p.b = b.data_ptr()
+    return p
+
+
+class Solver:
+    """One problem on one GPU: wraps srj_setup / srj_solve / srj_run_cycle.
+
+    ``problem`` has the attributes ndim, n, c, dconst, b and optionally faces
+    and diag as host NumPy arrays of shape (n2, n1, n0) (axis 0 contiguous).
+    """
+
+    def __init__(self, problem, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        abi.load()
+        self.device = torch.device(device)
+        self.shape = tuple(problem.b.shape)
+        self.npoints = int(np.prod(self.shape))
+        self.ndim = int(problem.ndim)
+        self.b = _dev(problem.b, self.device)
+        faces = getattr(problem, "faces", None)
+        self.faces = [(_dev(f, self.device) if f is not None else None) for f in faces] \
+            if faces is not None else None
+        diag = getattr(problem, "diag", None)
+        self.diag = _dev(diag, self.device) if diag is not None else None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._prob = make_problem(self.ndim, problem.n, problem.c, problem.dconst, self.b,
+                                  self.faces, self.diag)
+        torch.cuda.synchronize(self.device)
+        self.ctx = abi.srj_setup(self._prob, self.stream.cuda_stream)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            abi.srj_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def to_device(self, a) -> torch.Tensor:
+        return _dev(np.asarray(a).reshape(self.shape), self.device)
+
+    def set_plan(self, kind: int, tile_rows: int = 0, sweeps: int = 1) -> int:
+        return abi.srj_set_plan(self.ctx, kind, tile_rows, sweeps)
+
+    def get_plan(self):
+        return abi.srj_get_plan(self.ctx)
+
+    def set_profiling(self, enable: bool = True) -> None:
+        abi.srj_set_profiling(self.ctx, enable)
+
+    def profile(self):
+        """(sweep-launch milliseconds, launches, sweeps) since profiling was enabled."""
+        return abi.srj_get_profile(self.ctx)
+
+    def residual_norm(self, x: torch.Tensor) -> float:
+        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
+        return abi.srj_residual_norm(self.ctx, x.data_ptr())
+
+    def run_cycle(self, x: torch.Tensor, level: int) -> float:
+        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
+        return abi.srj_run_cycle(self.ctx, x.data_ptr(), level)
+
+    @staticmethod
+    def opts(rule: str = "heuristic", fixed_level: int = 0, tol: float = 1e-10,
+             tol_mode: str = "relative", max_cycles: int = 10000, max_sweeps: int = 50_000_000,
+             precision: str = "f64", start_level: int = 0, max_level: int = 24,
+             scale_target: float = 0.0, r0: float = 0.0) -> abi.SrjSolveOpts:
+        o = abi.srj_default_opts()
+        o.rule = abi.RULE[rule]
+        o.fixed_level = fixed_level
+        o.tol = tol
+        o.tol_mode = abi.TOL_MODE[tol_mode]
+        o.max_cycles = max_cycles
+        o.max_sweeps = max_sweeps
+        o.precision = abi.PREC[precision]
+        o.start_level = start_level
+        o.max_level = max_level
+        o.scale_target = scale_target
+        o.r0 = r0
+        return o
+
+    def solve(self, x: Optional[torch.Tensor] = None, **kw) -> Dict:
+        """Solve in place on x (zeros if None); returns counters, levels and norms."""
+        if x is None:
+            x = self.zeros()
+        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
+        o = self.opts(**kw)
+        levels = (ctypes.c_int32 * o.max_cycles)()
+        norms = (ctypes.c_double * (o.max_cycles + 1))()
+        st, res = abi.srj_solve(self.ctx, x.data_ptr(), o, levels, norms)
+        if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
+            raise abi.SrjError(st, "srj_solve")
+        nc = res.cycles
+        return {
+            "status": abi.STATUS_NAMES[st], "x": x, "converged": bool(res.converged),
+            "cycles": nc, "sweeps": int(res.sweeps), "final_level": res.final_level,
+            "r0": res.r0, "r_final": res.r_final, "min_margin": res.min_margin,
+            "levels": np.array(levels[:nc], dtype=np.int32),
+            "norms": np.array(norms[:nc + 1], dtype=np.float64),
+        }
