@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2048, help="grid side (default 2048)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-cycles", type=int, default=200)
-    ap.add_argument("--plan", type=str, default="", help="kind:rows:T kernel plan override")
+    ap.add_argument("--plan", type=str, default="", help="kind:rows:T:occ kernel plan override")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample (0 = skip)")
     return ap.parse_args()
@@ -80,8 +80,7 @@ def main():
     prob = workloads.c2(n=args.n)
     s = Solver(prob)
     if args.plan:
-        k, r, t = (int(v) for v in args.plan.split(":"))
-        assert s.set_plan(k, r, t) == 0, "plan not supported"
+        assert s.set_plan(*(int(v) for v in args.plan.split(":"))) == 0, "plan not supported"
     plan = s.get_plan()
     x = s.zeros()
     kw = dict(tol=args.tol, max_cycles=args.max_cycles)

@@ -33,35 +33,6 @@ srj_status fail(srj_status st, const std::string &msg)
 
 using namespace srj;
 
-// ---------------------------------------------------------------------------
-// Context
-// ---------------------------------------------------------------------------
-struct srj_ctx {
-    DevProblem P{};
-    hipStream_t stream = nullptr;
-    int64_t npoints = 0;
-    double *ws = nullptr;         // ping-pong partner of the caller's x
-    double *dinv = nullptr;       // 1/diag when diag is given
-    double *omega_dev = nullptr;  // all levels, execution order
-    std::vector<int32_t> offsets; // level -> first factor in omega_dev
-    ReduceScratch rs;
-    SweepPlan plan;
-    struct Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
-    // Profiling: HIP events around the sweep launches of each cycle.
-    bool profiling = false;
-    bool prof_pending = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double prof_ms = 0.0;
-    int64_t prof_launches = 0, prof_sweeps = 0, prof_pending_launches = 0, prof_pending_sweeps = 0;
-};
-
-namespace srj {
-// Refinement entry point (refine.hip).
-srj_status refine_solve(srj_ctx *ctx, double *x, const srj_solve_opts *o, srj_solve_result *res,
-                        int32_t *levels_out, double *norms_out);
-void refine_free(srj_ctx *ctx);
-}  // namespace srj
-
 namespace {
 
 srj_status validate_problem(const srj_problem *p)
@@ -111,8 +82,9 @@ SweepPlan default_plan(const DevProblem &P)
     pl.T = 1;
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
         pl.kind = 1;
-        pl.by = 48;
-        pl.T = 6;
+        pl.by = 24;
+        pl.T = 4;
+        pl.occ = 1;
     }
     return pl;
 }
@@ -236,6 +208,7 @@ srj_status srj_destroy(srj_ctx *c)
     (void)hipFree(c->ws);
     (void)hipFree(c->dinv);
     (void)hipFree(c->omega_dev);
+    (void)hipFree(c->omega32_dev);
     (void)hipFree(c->rs.partials);
     (void)hipFree(c->rs.sum);
     (void)hipHostFree(c->rs.host_sum);
@@ -286,8 +259,15 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     full_table(table, c->offsets);
     if (hipMalloc(&c->omega_dev, sizeof(double) * table.size()) != hipSuccess)
         return nomem("scheme table");
+    std::vector<float> table32(table.size());
+    for (size_t i = 0; i < table.size(); ++i) table32[i] = static_cast<float>(table[i]);
+    if (hipMalloc(&c->omega32_dev, sizeof(float) * table.size()) != hipSuccess)
+        return nomem("scheme table (binary32)");
     hipError_t e = hipMemcpyAsync(c->omega_dev, table.data(), sizeof(double) * table.size(),
                                   hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->omega32_dev, table32.data(), sizeof(float) * table32.size(),
+                           hipMemcpyHostToDevice, c->stream);
     c->rs.capacity = residual_blocks(P);
     if (e == hipSuccess && hipMalloc(&c->rs.partials, sizeof(double) * c->rs.capacity) != hipSuccess)
         return nomem("reduction partials");
@@ -304,13 +284,15 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     return SRJ_OK;
 }
 
-srj_status srj_set_plan(srj_ctx *c, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch)
+srj_status srj_set_plan(srj_ctx *c, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch,
+                        int32_t waves_per_simd)
 {
     if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
     SweepPlan pl;
     pl.kind = kind;
     pl.by = tile_rows;
     pl.T = sweeps_per_launch;
+    pl.occ = waves_per_simd;
     if (kind == 0) {
         pl.T = 1;
         c->plan = pl;
@@ -321,12 +303,22 @@ srj_status srj_set_plan(srj_ctx *c, int32_t kind, int32_t tile_rows, int32_t swe
     return SRJ_OK;
 }
 
-srj_status srj_get_plan(srj_ctx *c, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch)
+srj_status srj_get_plan(srj_ctx *c, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch,
+                        int32_t *waves_per_simd)
 {
-    if (!c || !kind || !tile_rows || !sweeps_per_launch) return fail(SRJ_ERR_INVALID, "NULL argument");
+    if (!c || !kind || !tile_rows || !sweeps_per_launch || !waves_per_simd)
+        return fail(SRJ_ERR_INVALID, "NULL argument");
     *kind = c->plan.kind;
     *tile_rows = c->plan.by;
     *sweeps_per_launch = c->plan.T;
+    *waves_per_simd = c->plan.occ;
+    return SRJ_OK;
+}
+
+srj_status srj_plan_variants(int32_t *out, int32_t cap, int32_t *count)
+{
+    if (!count || (cap > 0 && !out)) return fail(SRJ_ERR_INVALID, "NULL argument");
+    *count = plan_variants(out, cap);
     return SRJ_OK;
 }
 

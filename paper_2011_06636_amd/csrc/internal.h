@@ -11,6 +11,8 @@
 
 namespace srj {
 
+struct Refine;
+
 // ---------------------------------------------------------------------------
 // Errors
 // ---------------------------------------------------------------------------
@@ -74,9 +76,10 @@ hipError_t compute_dinv(const double *diag, double *dinv, int64_t n, hipStream_t
 
 // One binary64 sweep x -> xo with factor w, T sweeps fused when possible.
 struct SweepPlan {
-    int kind = 0;   // 0 = generic one-sweep kernel, 1 = 2D tiled, 2 = 3D streaming
+    int kind = 0;   // 0 = one sweep per launch; 1 = 2D register tiles; 2 = 2D tiles, b in LDS
     int T = 1;      // sweeps fused per launch
     int bx = 0, by = 0;
+    int occ = 1;    // kernel's minimum waves per SIMD (register budget)
 };
 hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo, double w,
                                 hipStream_t s);
@@ -84,10 +87,56 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s);
 bool fused_supported(const DevProblem &P, const SweepPlan &plan);
+// Lists the fused variants as (kind, rows, halo, occ); returns how many exist.
+int plan_variants(int32_t *out, int cap);
 
 // Sum of (b - A x)^2 into scratch.sum (device); blocks needed for scratch sizing.
 int64_t residual_blocks(const DevProblem &P);
 hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
                                  hipStream_t s);
+// Folds rs.partials[0..nblocks) into rs.sum in a fixed order.
+hipError_t launch_fold(ReduceScratch &rs, int64_t nblocks, hipStream_t s);
+// Block-level fixed-order sums used by every reduction kernel.
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
 
 }  // namespace srj
+
+// ---------------------------------------------------------------------------
+// Solver context (the opaque srj_ctx of the C ABI)
+// ---------------------------------------------------------------------------
+struct srj_ctx {
+    srj::DevProblem P{};
+    hipStream_t stream = nullptr;
+    int64_t npoints = 0;
+    double *ws = nullptr;          // ping-pong partner of the caller's x
+    double *dinv = nullptr;        // 1/diag when diag is given
+    double *omega_dev = nullptr;   // all levels, execution order (binary64)
+    float *omega32_dev = nullptr;  // the same table rounded to binary32
+    std::vector<int32_t> offsets;  // level -> first factor in the tables
+    srj::ReduceScratch rs;
+    srj::SweepPlan plan;
+    struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
+    // Profiling: HIP events around the sweep launches of each cycle.
+    bool profiling = false;
+    bool prof_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0, prof_sweeps = 0, prof_pending_launches = 0, prof_pending_sweeps = 0;
+};
+
+namespace srj {
+srj_status run_sweeps(srj_ctx *c, double **cur, double **nxt, int level);
+srj_status residual_norm(srj_ctx *c, const double *x, double *out);
+srj_status collect_profile(srj_ctx *c);
+int next_level(srj_rule rule, int level, double ratio, int max_level);
+// Refinement (refine.hip).
+srj_status refine_solve(srj_ctx *ctx, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                        int32_t *levels_out, double *norms_out);
+void refine_free(srj_ctx *ctx);
+}  // namespace srj
+

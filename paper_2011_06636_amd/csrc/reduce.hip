@@ -85,6 +85,13 @@ __global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ part
 
 }  // namespace
 
+hipError_t launch_fold(ReduceScratch &rs, int64_t nblocks, hipStream_t s)
+{
+    if (nblocks > rs.capacity) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFinal), 0, s, rs.partials, nblocks, rs.sum);
+    return hipGetLastError();
+}
+
 int64_t residual_blocks(const DevProblem &P)
 {
     return ((P.n0 + kBlock - 1) / kBlock) * P.n1 * P.n2;

@@ -1,16 +1,453 @@
-// Mixed-precision iterative refinement (binary32 / 16-bit inner SRJ cycles).
+// Mixed-precision iterative refinement around the SRJ cycles.
+//
+// Not part of the paper (Islam & Wang, arXiv 2011.06636); it keeps the
+// paper's cycle and selector and changes only where the cycle runs.  One
+// outer step is one SRJ cycle on the correction equation A d = r:
+//   r = b - A x in binary64 and its L2 norm (drives Algorithm 1 as in
+//   section 3), rhat = storage(binary32(s * r)) with s a power of two,
+//   d = 0, then the M sweeps of the cycle's scheme (Eq. 3, Eq. (17) factors
+//   rounded to binary32) on A d = rhat in binary32 arithmetic, the iterate
+//   rounded to the storage format (binary32, binary16 or bfloat16) after every
+//   sweep, and finally x = x + d / s in binary64.
+// With d starting at zero, one inner cycle gives d = (I - B_SRJ) A^-1 rhat,
+// so in exact arithmetic the error moves as e' = B_SRJ e, exactly like a
+// binary64 cycle (section 2, Eq. 7): the selector sees the same ratios.
+//
+// The scale applied to the residual of a pass comes from the last norm known
+// before that pass (r0 for the first two passes, then the norm of the cycle
+// before the previous one), so the update, the residual, its norm and the
+// scaled cast are one fused pass over the grid.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
 #include "internal.h"
 
-struct srj_ctx;
+#pragma clang fp contract(off)
 
 namespace srj {
 
-srj_status refine_solve(srj_ctx *, double *, const srj_solve_opts *, srj_solve_result *,
-                        int32_t *, double *)
+// ---------------------------------------------------------------------------
+// Storage formats of the correction
+// ---------------------------------------------------------------------------
+struct StF32 {
+    using T = float;
+    static constexpr int bytes = 4;
+    __device__ static float load(T v) { return v; }
+    __device__ static T store(float v) { return v; }
+};
+
+struct StF16 {
+    using T = _Float16;
+    static constexpr int bytes = 2;
+    __device__ static float load(T v) { return static_cast<float>(v); }
+    // hardware conversion: round to nearest even, subnormals kept, overflow to inf
+    __device__ static T store(float v) { return static_cast<_Float16>(v); }
+};
+
+struct StBF16 {
+    using T = uint16_t;
+    static constexpr int bytes = 2;
+    __device__ static float load(T v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+    // round to nearest even on the upper 16 bits: add 0x7fff plus the lowest kept
+    // bit, then truncate; a carry into the exponent gives the next binade or inf
+    __device__ static T store(float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7f800000u) == 0x7f800000u)  // inf or nan: keep (quiet the nan)
+            return static_cast<T>((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return static_cast<T>(u >> 16);
+    }
+};
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kFinal = 1024;
+
+__device__ __forceinline__ double block_sum256(double v, double *lds)
 {
-    return fail(SRJ_ERR_UNSUPPORTED, "refinement modes are not built yet");
+    v = wave_sum64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+    return t;
 }
 
-void refine_free(srj_ctx *) {}
+// One inner sweep on A d = rhat in binary32 (generic: any dimension,
+// constant or per-face couplings).  Same expression order as binary64.
+template <int ND, class St>
+__global__ __launch_bounds__(kBlock) void k_inner_generic(DevProblem32 Q,
+                                                          const typename St::T *__restrict__ d,
+                                                          typename St::T *__restrict__ dout,
+                                                          const typename St::T *__restrict__ rhat,
+                                                          float w)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i0 >= Q.n0) return;
+    const int64_t i1 = blockIdx.y, i2 = blockIdx.z;
+    const int64_t s1 = Q.n0, s2 = Q.n0 * Q.n1;
+    const int64_t p = i0 + s1 * i1 + s2 * i2;
+    const float dc = St::load(d[p]);
+    float s = (Q.diag ? Q.diag[p] : Q.dconst) * dc;
+    if (i0 > 0) s = s - (Q.face[0] ? Q.face[0][p - 1] : Q.c[0]) * St::load(d[p - 1]);
+    if (i0 < Q.n0 - 1) s = s - (Q.face[0] ? Q.face[0][p] : Q.c[0]) * St::load(d[p + 1]);
+    if (ND >= 2) {
+        if (i1 > 0) s = s - (Q.face[1] ? Q.face[1][p - s1] : Q.c[1]) * St::load(d[p - s1]);
+        if (i1 < Q.n1 - 1) s = s - (Q.face[1] ? Q.face[1][p] : Q.c[1]) * St::load(d[p + s1]);
+    }
+    if (ND >= 3) {
+        if (i2 > 0) s = s - (Q.face[2] ? Q.face[2][p - s2] : Q.c[2]) * St::load(d[p - s2]);
+        if (i2 < Q.n2 - 1) s = s - (Q.face[2] ? Q.face[2][p] : Q.c[2]) * St::load(d[p + s2]);
+    }
+    const float r = St::load(rhat[p]) - s;
+    const float t = (Q.diag ? Q.dinv[p] : Q.dinvconst) * r;
+    dout[p] = St::store(dc + w * t);
+}
+
+// Outer pass: x' = x + d / s_prev (UPDATE), r = b - A x' in binary64 with the
+// neighbours' x' formed on the fly, partial sums of r^2, and
+// rhat = storage(binary32(s_next * r)).
+template <int ND, class St, bool UPDATE>
+__global__ __launch_bounds__(kBlock) void k_outer(DevProblem P, const double *__restrict__ x,
+                                                  const typename St::T *__restrict__ d,
+                                                  double inv_s, double *__restrict__ xo,
+                                                  typename St::T *__restrict__ rhat, double s_next,
+                                                  double *__restrict__ partials)
+{
+    __shared__ double lds[kBlock / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i1 = blockIdx.y, i2 = blockIdx.z;
+    double rr = 0.0;
+    if (i0 < P.n0) {
+        const int64_t s1 = P.n0, s2 = P.n0 * P.n1;
+        const int64_t p = i0 + s1 * i1 + s2 * i2;
+        auto xn = [&](int64_t q) -> double {
+            if (UPDATE) return x[q] + static_cast<double>(St::load(d[q])) * inv_s;
+            return x[q];
+        };
+        const double xc = xn(p);
+        double s = (P.diag ? P.diag[p] : P.dconst) * xc;
+        if (i0 > 0) s = s - (P.face[0] ? P.face[0][p - 1] : P.c[0]) * xn(p - 1);
+        if (i0 < P.n0 - 1) s = s - (P.face[0] ? P.face[0][p] : P.c[0]) * xn(p + 1);
+        if (ND >= 2) {
+            if (i1 > 0) s = s - (P.face[1] ? P.face[1][p - s1] : P.c[1]) * xn(p - s1);
+            if (i1 < P.n1 - 1) s = s - (P.face[1] ? P.face[1][p] : P.c[1]) * xn(p + s1);
+        }
+        if (ND >= 3) {
+            if (i2 > 0) s = s - (P.face[2] ? P.face[2][p - s2] : P.c[2]) * xn(p - s2);
+            if (i2 < P.n2 - 1) s = s - (P.face[2] ? P.face[2][p] : P.c[2]) * xn(p + s2);
+        }
+        const double r = P.b[p] - s;
+        rr = r * r;
+        if (UPDATE) xo[p] = xc;
+        rhat[p] = St::store(static_cast<float>(s_next * r));
+    }
+    const double t = block_sum256(rr, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+}
+
+template <class T>
+__global__ void k_zero(T *__restrict__ a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = T(0);
+}
+
+__global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ o, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = static_cast<float>(a[i]);
+}
+
+__global__ void k_inv_to_f32(const double *__restrict__ a, float *__restrict__ o, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = static_cast<float>(1.0 / a[i]);
+}
+
+dim3 row_grid(int64_t n0, int64_t n1, int64_t n2)
+{
+    return dim3((unsigned)((n0 + kBlock - 1) / kBlock), (unsigned)n1, (unsigned)n2);
+}
+
+template <class St>
+hipError_t launch_inner(const DevProblem32 &Q, const void *d, void *dout, const void *rhat, float w,
+                        hipStream_t s)
+{
+    using T = typename St::T;
+    const dim3 g = row_grid(Q.n0, Q.n1, Q.n2);
+    const T *dd = static_cast<const T *>(d);
+    T *oo = static_cast<T *>(dout);
+    const T *rr = static_cast<const T *>(rhat);
+    switch (Q.ndim) {
+    case 1: hipLaunchKernelGGL((k_inner_generic<1, St>), g, dim3(kBlock), 0, s, Q, dd, oo, rr, w); break;
+    case 2: hipLaunchKernelGGL((k_inner_generic<2, St>), g, dim3(kBlock), 0, s, Q, dd, oo, rr, w); break;
+    default: hipLaunchKernelGGL((k_inner_generic<3, St>), g, dim3(kBlock), 0, s, Q, dd, oo, rr, w); break;
+    }
+    return hipGetLastError();
+}
+
+template <class St, bool UPDATE>
+hipError_t launch_outer_t(const DevProblem &P, const double *x, const void *d, double inv_s,
+                          double *xo, void *rhat, double s_next, double *partials, hipStream_t s)
+{
+    using T = typename St::T;
+    const dim3 g = row_grid(P.n0, P.n1, P.n2);
+    const T *dd = static_cast<const T *>(d);
+    T *rh = static_cast<T *>(rhat);
+    switch (P.ndim) {
+    case 1: hipLaunchKernelGGL((k_outer<1, St, UPDATE>), g, dim3(kBlock), 0, s, P, x, dd, inv_s, xo, rh, s_next, partials); break;
+    case 2: hipLaunchKernelGGL((k_outer<2, St, UPDATE>), g, dim3(kBlock), 0, s, P, x, dd, inv_s, xo, rh, s_next, partials); break;
+    default: hipLaunchKernelGGL((k_outer<3, St, UPDATE>), g, dim3(kBlock), 0, s, P, x, dd, inv_s, xo, rh, s_next, partials); break;
+    }
+    return hipGetLastError();
+}
+
+template <class St>
+hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const void *d,
+                        double inv_s, double *xo, void *rhat, double s_next, double *partials,
+                        hipStream_t s)
+{
+    if (update) return launch_outer_t<St, true>(P, x, d, inv_s, xo, rhat, s_next, partials, s);
+    return launch_outer_t<St, false>(P, x, d, inv_s, xo, rhat, s_next, partials, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Workspaces
+// ---------------------------------------------------------------------------
+struct Refine {
+    int bytes = 0;                 // storage bytes per element the buffers hold
+    void *da = nullptr, *db = nullptr, *rhat = nullptr;
+    float *face32[3] = {nullptr, nullptr, nullptr};
+    float *d32 = nullptr, *dinv32 = nullptr;
+    bool op_ready = false;
+};
+
+void refine_free(srj_ctx *c)
+{
+    if (!c || !c->refine) return;
+    Refine *R = c->refine;
+    (void)hipFree(R->da);
+    (void)hipFree(R->db);
+    (void)hipFree(R->rhat);
+    for (int d = 0; d < 3; ++d) (void)hipFree(R->face32[d]);
+    (void)hipFree(R->d32);
+    (void)hipFree(R->dinv32);
+    delete R;
+    c->refine = nullptr;
+}
+
+namespace {
+
+int storage_bytes(srj_precision p) { return p == SRJ_PREC_F32_REFINE ? 4 : 2; }
+
+srj_status ensure_workspace(srj_ctx *c, srj_precision prec)
+{
+    if (!c->refine) c->refine = new Refine();
+    Refine *R = c->refine;
+    const int64_t N = c->npoints;
+    const int bytes = storage_bytes(prec);
+    if (R->bytes < bytes) {
+        (void)hipFree(R->da);
+        (void)hipFree(R->db);
+        (void)hipFree(R->rhat);
+        R->da = R->db = R->rhat = nullptr;
+        R->bytes = 0;
+        if (hipMalloc(&R->da, (size_t)N * bytes) != hipSuccess ||
+            hipMalloc(&R->db, (size_t)N * bytes) != hipSuccess ||
+            hipMalloc(&R->rhat, (size_t)N * bytes) != hipSuccess)
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for refinement buffers");
+        R->bytes = bytes;
+    }
+    if (!R->op_ready) {
+        const int64_t blocks = (N + 255) / 256;
+        for (int d = 0; d < c->P.ndim; ++d) {
+            if (!c->P.face[d]) continue;
+            if (hipMalloc(&R->face32[d], sizeof(float) * (size_t)N) != hipSuccess)
+                return fail(SRJ_ERR_NOMEM, "hipMalloc failed for binary32 couplings");
+            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                               c->P.face[d], R->face32[d], N);
+            SRJ_HIP_CHECK(hipGetLastError());
+        }
+        if (c->P.diag) {
+            if (hipMalloc(&R->d32, sizeof(float) * (size_t)N) != hipSuccess ||
+                hipMalloc(&R->dinv32, sizeof(float) * (size_t)N) != hipSuccess)
+                return fail(SRJ_ERR_NOMEM, "hipMalloc failed for binary32 diagonal");
+            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                               c->P.diag, R->d32, N);
+            SRJ_HIP_CHECK(hipGetLastError());
+            hipLaunchKernelGGL(k_inv_to_f32, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                               c->P.diag, R->dinv32, N);
+            SRJ_HIP_CHECK(hipGetLastError());
+        }
+        R->op_ready = true;
+    }
+    return SRJ_OK;
+}
+
+DevProblem32 make_q(const srj_ctx *c)
+{
+    const DevProblem &P = c->P;
+    const Refine *R = c->refine;
+    DevProblem32 Q{};
+    Q.ndim = P.ndim;
+    Q.n0 = P.n0;
+    Q.n1 = P.n1;
+    Q.n2 = P.n2;
+    for (int d = 0; d < 3; ++d) {
+        Q.c[d] = static_cast<float>(P.c[d]);
+        Q.face[d] = R->face32[d];
+    }
+    Q.diag = R->d32;
+    Q.dinv = R->dinv32;
+    Q.dconst = P.diag ? 0.f : static_cast<float>(P.dconst);
+    Q.dinvconst = P.diag ? 0.f : static_cast<float>(1.0 / P.dconst);
+    return Q;
+}
+
+// Largest power of two not above target_rms * sqrt(N) / norm (1 for a zero
+// or non-finite norm).
+double pow2_scale(double norm, int64_t N, double target_rms)
+{
+    if (!(norm > 0.0) || !isfinite(norm)) return 1.0;
+    const double q = target_rms * sqrt(static_cast<double>(N)) / norm;
+    int e = 0;
+    frexp(q, &e);
+    return ldexp(1.0, e - 1);
+}
+
+template <class St>
+srj_status zero_storage(srj_ctx *c, void *a)
+{
+    const int64_t N = c->npoints;
+    hipLaunchKernelGGL(k_zero<typename St::T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       c->stream, static_cast<typename St::T *>(a), N);
+    SRJ_HIP_CHECK(hipGetLastError());
+    return SRJ_OK;
+}
+
+template <class St>
+srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                   int32_t *levels_out, double *norms_out)
+{
+    srj_status st = ensure_workspace(c, o->precision);
+    if (st != SRJ_OK) return st;
+    Refine *R = c->refine;
+    const DevProblem32 Q = make_q(c);
+    const int64_t N = c->npoints;
+    const double tgt = o->scale_target > 0.0 ? o->scale_target
+                       : (o->precision == SRJ_PREC_F16_REFINE ? ldexp(1.0, -8) : 1.0);
+    const int64_t nb = residual_blocks(c->P);
+
+    double *cur = x, *nxt = c->ws;
+    double norm0 = 0.0;
+    st = residual_norm(c, x, &norm0);
+    if (st != SRJ_OK) return st;
+    const double r0 = o->r0 > 0.0 ? o->r0 : norm0;
+    res->r0 = r0;
+    res->r_final = norm0;
+    if (norms_out) norms_out[0] = norm0;
+    const double target = o->tol_mode == SRJ_TOL_RELATIVE ? o->tol * r0 : o->tol;
+    srj_status status = SRJ_ERR_NOT_CONVERGED;
+    int level = o->start_level;
+    double prev = norm0;
+    if (!isfinite(norm0)) {
+        status = fail(SRJ_ERR_NONFINITE, "initial residual norm is not finite");
+    } else if (norm0 == 0.0 || norm0 < target) {
+        res->converged = 1;
+        status = SRJ_OK;
+    } else {
+        double s = pow2_scale(norm0, N, tgt);
+        SRJ_HIP_CHECK(launch_outer<St>(false, c->P, cur, nullptr, 0.0, nullptr, R->rhat, s,
+                                       c->rs.partials, c->stream));
+        void *da = R->da, *db = R->db;
+        for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
+            const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
+            const int M = level_m(lv);
+            if (res->sweeps + M > o->max_sweeps) break;
+            st = zero_storage<St>(c, da);
+            if (st != SRJ_OK) return st;
+            const float *w32 = nullptr;
+            std::vector<float> wl(M);
+            {
+                const std::vector<double> &w = level_factors(lv);
+                for (int k = 0; k < M; ++k) wl[k] = static_cast<float>(w[k]);
+                w32 = wl.data();
+            }
+            if (c->profiling) SRJ_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
+            for (int k = 0; k < M; ++k) {
+                SRJ_HIP_CHECK(launch_inner<St>(Q, da, db, R->rhat, w32[k], c->stream));
+                std::swap(da, db);
+            }
+            if (c->profiling) {
+                SRJ_HIP_CHECK(hipEventRecord(c->ev1, c->stream));
+                c->prof_pending = true;
+                c->prof_pending_launches = M;
+                c->prof_pending_sweeps = M;
+            }
+            res->sweeps += M;
+            const double s_next = pow2_scale(prev, N, tgt);
+            SRJ_HIP_CHECK(launch_outer<St>(true, c->P, cur, da, 1.0 / s, nxt, R->rhat, s_next,
+                                           c->rs.partials, c->stream));
+            std::swap(cur, nxt);
+            SRJ_HIP_CHECK(launch_fold(c->rs, nb, c->stream));
+            SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
+                                         hipMemcpyDeviceToHost, c->stream));
+            SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+            st = collect_profile(c);
+            if (st != SRJ_OK) return st;
+            const double norm = sqrt(*c->rs.host_sum);
+            s = s_next;
+            res->cycles = cycle + 1;
+            res->r_final = norm;
+            res->final_level = lv;
+            if (levels_out) levels_out[cycle] = lv;
+            if (norms_out) norms_out[cycle + 1] = norm;
+            if (!isfinite(norm)) {
+                status = fail(SRJ_ERR_NONFINITE, "residual norm is not finite");
+                break;
+            }
+            if (norm < target) {
+                res->converged = 1;
+                status = SRJ_OK;
+                break;
+            }
+            const double ratio = norm / prev;
+            prev = norm;
+            if (o->rule == SRJ_RULE_HEURISTIC) {
+                const double m = std::min(fabs(ratio - 0.2), fabs(ratio - 0.4));
+                res->min_margin = std::min(res->min_margin, m);
+            }
+            level = next_level(o->rule, level, ratio, o->max_level);
+        }
+        if (status == SRJ_ERR_NOT_CONVERGED) set_error("cycle or sweep cap reached");
+    }
+    if (cur != x)
+        SRJ_HIP_CHECK(hipMemcpyAsync(x, cur, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice,
+                                     c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return status;
+}
+
+}  // namespace
+
+srj_status refine_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                        int32_t *levels_out, double *norms_out)
+{
+    switch (o->precision) {
+    case SRJ_PREC_F32_REFINE: return solve_t<StF32>(c, x, o, res, levels_out, norms_out);
+    case SRJ_PREC_F16_REFINE: return solve_t<StF16>(c, x, o, res, levels_out, norms_out);
+    case SRJ_PREC_BF16_REFINE: return solve_t<StBF16>(c, x, o, res, levels_out, norms_out);
+    default: return fail(SRJ_ERR_INVALID, "not a refinement precision");
+    }
+}
 
 }  // namespace srj

@@ -78,8 +78,8 @@ class Solver:
     def to_device(self, a) -> torch.Tensor:
         return _dev(np.asarray(a).reshape(self.shape), self.device)
 
-    def set_plan(self, kind: int, tile_rows: int = 0, sweeps: int = 1) -> int:
-        return abi.srj_set_plan(self.ctx, kind, tile_rows, sweeps)
+    def set_plan(self, kind: int, tile_rows: int = 0, sweeps: int = 1, occ: int = 1) -> int:
+        return abi.srj_set_plan(self.ctx, kind, tile_rows, sweeps, occ)
 
     def get_plan(self):
         return abi.srj_get_plan(self.ctx)

@@ -107,15 +107,17 @@ def test_fused_plans_bit_identical(torch_cuda, orc):
     s = _solver(prob)
     x0 = np.random.default_rng(5).uniform(-1, 1, prob.shape)
     results = {}
-    plans = [(0, 0, 1)] + [(1, 32, t) for t in (1, 2, 3, 4)] + [(1, 48, t) for t in (5, 6)] + \
-        [(1, 64, t) for t in (7, 8)]
+    from paper_2011_06636_amd import abi
+    plans = [(0, 0, 1, 1)]
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
     for plan in plans:
         assert s.set_plan(*plan) == 0
         x = s.to_device(x0)
         for level in (0, 3, 8, 11):
             s.run_cycle(x, level)
         results[plan] = x.cpu().numpy()
-    base = results[(0, 0, 1)]
+    base = results[(0, 0, 1, 1)]
     for plan, v in results.items():
         assert np.array_equal(v, base), plan
     # and the oracle agrees

@@ -1,0 +1,79 @@
+"""GPU parity of the mixed-precision refinement modes against the oracle.
+
+The oracle runs the same refinement steps on the CPU (binary64 outer
+residual and update, binary32 inner arithmetic, storage rounding after every
+sweep written from the definitions of binary16 and bfloat16), so the level
+chosen at every cycle must be identical and the binary64 iterate must agree
+within a relative 1e-12 (expected: bit identical).  The error of each result
+against the plain binary64 oracle solution is checked against the bound the
+tolerance implies (condition number times tolerance, with a safety factor).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(prob):
+    from paper_2011_06636_amd.solver import Solver
+    return Solver(prob)
+
+
+# (name, problem, tolerance, precisions, max_cycles).  16-bit storage only
+# converges where the problem stays at moderate levels (3D cases); on the 1D
+# case it overflows once the heuristic climbs past level ~13, and the GPU must
+# reproduce that trajectory too.
+CASES = [
+    ("c1_1d_255", lambda: workloads.c1(), 1e-10, ("f32",), 300),
+    ("c1_1d_255_16bit", lambda: workloads.c1(), 1e-10, ("bf16", "f16"), 30),
+    ("c2_recipe_200", lambda: workloads.c2(n=200), 1e-10, ("f32", "bf16"), 300),
+    ("2d_ragged_150x61", lambda: workloads.poisson([150, 61], b=np.random.default_rng(3).uniform(-1, 1, (1, 61, 150))), 1e-10, ("f32",), 300),
+    ("3d_varcoef_20", lambda: workloads.variable_coefficient(20, seed=1, corr_len=4.0), 1e-10, ("f32", "bf16", "f16"), 300),
+    ("3d_aniso_c5_recipe", lambda: workloads.c5_instance(2, lo=16, hi=36), 1e-8, ("f32", "bf16", "f16"), 300),
+]
+PARAMS = [(i, p) for i, c in enumerate(CASES) for p in c[3]]
+
+
+@pytest.mark.parametrize("case,precision", PARAMS)
+def test_refine_matches_oracle(torch_cuda, orc, case, precision):
+    name, make, tol, _, max_cycles = CASES[case]
+    prob = make()
+    ref = orc.solve(prob, tol=tol, precision=precision, max_cycles=max_cycles)
+    s = _solver(prob)
+    out = s.solve(tol=tol, precision=precision, max_cycles=max_cycles)
+    assert out["status"] == ref["status"], (name, out["status"], ref["status"])
+    np.testing.assert_array_equal(out["levels"], ref["levels"])
+    assert out["sweeps"] == ref["sweeps"]
+    fin = np.isfinite(ref["norms"])
+    np.testing.assert_allclose(out["norms"][fin], ref["norms"][fin], rtol=1e-12, atol=0)
+    got = out["x"].cpu().numpy()
+    if np.all(np.isfinite(ref["x"])):
+        scale = np.max(np.abs(ref["x"]))
+        assert np.max(np.abs(got - ref["x"])) <= 1e-12 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_refine_error_vs_f64(torch_cuda, orc, precision):
+    prob = workloads.c2(n=128)
+    f64 = orc.solve(prob, tol=1e-10)
+    s = _solver(prob)
+    out = s.solve(tol=1e-10, precision=precision, max_cycles=300)
+    assert out["status"] == "ok"
+    x = out["x"].cpu().numpy()
+    err = np.linalg.norm(x - f64["x"]) / np.linalg.norm(f64["x"])
+    # kappa(A) for the 128^2 Poisson matrix is about (2 * 129 / pi)^2 ~ 6.7e3
+    assert err < 6.7e3 * 1e-10 * 4, err
+    # the binary64 residual of the returned iterate, recomputed by the oracle
+    assert orc.residual_norm(prob, x) < 1e-10 * out["r0"]
+    s.close()
