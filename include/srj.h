@@ -158,21 +158,22 @@ srj_status srj_residual_norm(srj_ctx *ctx, const double *x, double *norm_out);
 srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_solve_result *res,
                      int32_t *levels_out, double *norms_out);
 
-/* Kernel plan of a context (tuning only; every plan gives bit-identical
- * iterates).  kind 0: one sweep per launch, any problem.  kind 1: 2D
- * constant-coefficient register tiles of 64 columns x tile_rows rows that
- * fuse up to sweeps_per_launch sweeps per launch (b kept in registers);
- * kind 2: the same with b kept in LDS.  waves_per_simd is the register
- * budget the kernel was compiled for.  The available (kind, tile_rows,
- * most sweeps, waves_per_simd) variants are listed by srj_plan_variants.
- * SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
-srj_status srj_set_plan(srj_ctx *ctx, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch,
-                        int32_t waves_per_simd);
-srj_status srj_get_plan(srj_ctx *ctx, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch,
-                        int32_t *waves_per_simd);
-/* Writes up to cap variants as 4 int32 each (kind, tile_rows, max sweeps per
- * launch, waves_per_simd) to out (host) and their number to *count. */
-srj_status srj_plan_variants(int32_t *out, int32_t cap, int32_t *count);
+/* Kernel plans of a context (tuning only: every plan gives bit-identical
+ * iterates).  which = 0 selects the plan of the binary64 sweeps, which = 1
+ * the plan of the inner sweeps of the refinement modes.  kind 0: one sweep
+ * per launch, any problem.  kind 1: 2D constant-coefficient register tiles of
+ * 64 columns x tile_rows rows fusing up to sweeps_per_launch sweeps per launch
+ * (right-hand side in registers); kind 2 (binary64 only): the same with the
+ * right-hand side in LDS.  waves_per_simd is the register budget the kernel
+ * was compiled for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
+srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
+                        int32_t sweeps_per_launch, int32_t waves_per_simd);
+srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,
+                        int32_t *sweeps_per_launch, int32_t *waves_per_simd);
+/* Lists the fused variants for `which` as 4 int32 each (kind, tile_rows, most
+ * sweeps per launch, waves_per_simd): writes up to cap of them to out (host)
+ * and their number to *count. */
+srj_status srj_plan_variants(int32_t which, int32_t *out, int32_t cap, int32_t *count);
 
 /* Profiling aid.  While enabled, the relaxation launches of every cycle
  * are bracketed by HIP events recorded on the context's stream; the elapsed

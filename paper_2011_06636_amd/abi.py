@@ -83,9 +83,9 @@ def load() -> ctypes.CDLL:
         "srj_residual_norm": (i32, [vp, vp, P(f64)]),
         "srj_solve": (i32, [vp, vp, P(SrjSolveOpts), P(SrjSolveResult), P(i32), P(f64)]),
         "srj_destroy": (i32, [vp]),
-        "srj_set_plan": (i32, [vp, i32, i32, i32, i32]),
-        "srj_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32)]),
-        "srj_plan_variants": (i32, [P(i32), i32, P(i32)]),
+        "srj_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
+        "srj_get_plan": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
+        "srj_plan_variants": (i32, [i32, P(i32), i32, P(i32)]),
         "srj_set_profiling": (i32, [vp, i32]),
         "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
@@ -161,22 +161,23 @@ def srj_solve(ctx, x_ptr: int, opts: SrjSolveOpts, levels=None, norms=None):
     return st, res
 
 
-def srj_set_plan(ctx, kind: int, tile_rows: int = 0, sweeps: int = 1, occ: int = 1) -> int:
-    return load().srj_set_plan(ctx, kind, tile_rows, sweeps, occ)
+def srj_set_plan(ctx, kind: int, tile_rows: int = 0, sweeps: int = 1, occ: int = 1,
+                 which: int = 0) -> int:
+    return load().srj_set_plan(ctx, which, kind, tile_rows, sweeps, occ)
 
 
-def srj_get_plan(ctx):
+def srj_get_plan(ctx, which: int = 0):
     k, r, t, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    check(load().srj_get_plan(ctx, ctypes.byref(k), ctypes.byref(r), ctypes.byref(t),
+    check(load().srj_get_plan(ctx, which, ctypes.byref(k), ctypes.byref(r), ctypes.byref(t),
                               ctypes.byref(o)), "srj_get_plan")
     return k.value, r.value, t.value, o.value
 
 
-def srj_plan_variants():
+def srj_plan_variants(which: int = 0):
     """Fused kernel variants as (kind, tile_rows, max sweeps per launch, waves_per_simd)."""
     buf = (ctypes.c_int32 * 512)()
     n = ctypes.c_int32()
-    check(load().srj_plan_variants(buf, 128, ctypes.byref(n)), "srj_plan_variants")
+    check(load().srj_plan_variants(which, buf, 128, ctypes.byref(n)), "srj_plan_variants")
     return [tuple(buf[4 * i:4 * i + 4]) for i in range(min(n.value, 128))]
 
 

@@ -75,6 +75,18 @@ srj_status validate_opts(const srj_solve_opts *o)
     return SRJ_OK;
 }
 
+SweepPlan default_inner_plan(const DevProblem &P)
+{
+    SweepPlan pl;
+    if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
+        pl.kind = 1;
+        pl.by = 24;
+        pl.T = 4;
+        pl.occ = 1;
+    }
+    return pl;
+}
+
 SweepPlan default_plan(const DevProblem &P)
 {
     SweepPlan pl;
@@ -280,45 +292,51 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
         return fail(SRJ_ERR_HIP, std::string("setup: ") + hipGetErrorString(e));
     }
     c->plan = default_plan(P);
+    c->plan_inner = default_inner_plan(P);
     *out = c;
     return SRJ_OK;
 }
 
-srj_status srj_set_plan(srj_ctx *c, int32_t kind, int32_t tile_rows, int32_t sweeps_per_launch,
-                        int32_t waves_per_simd)
+srj_status srj_set_plan(srj_ctx *c, int32_t which, int32_t kind, int32_t tile_rows,
+                        int32_t sweeps_per_launch, int32_t waves_per_simd)
 {
     if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
+    if (which != 0 && which != 1) return fail(SRJ_ERR_INVALID, "which must be 0 or 1");
     SweepPlan pl;
     pl.kind = kind;
     pl.by = tile_rows;
     pl.T = sweeps_per_launch;
     pl.occ = waves_per_simd;
+    SweepPlan &dst = which == 0 ? c->plan : c->plan_inner;
     if (kind == 0) {
-        pl.T = 1;
-        c->plan = pl;
+        dst = SweepPlan{};
         return SRJ_OK;
     }
-    if (!fused_supported(c->P, pl)) return fail(SRJ_ERR_UNSUPPORTED, "plan not supported for this problem");
-    c->plan = pl;
+    const bool ok = which == 0 ? fused_supported(c->P, pl) : inner_fused_supported(c->P, pl);
+    if (!ok) return fail(SRJ_ERR_UNSUPPORTED, "plan not supported for this problem");
+    dst = pl;
     return SRJ_OK;
 }
 
-srj_status srj_get_plan(srj_ctx *c, int32_t *kind, int32_t *tile_rows, int32_t *sweeps_per_launch,
-                        int32_t *waves_per_simd)
+srj_status srj_get_plan(srj_ctx *c, int32_t which, int32_t *kind, int32_t *tile_rows,
+                        int32_t *sweeps_per_launch, int32_t *waves_per_simd)
 {
     if (!c || !kind || !tile_rows || !sweeps_per_launch || !waves_per_simd)
         return fail(SRJ_ERR_INVALID, "NULL argument");
-    *kind = c->plan.kind;
-    *tile_rows = c->plan.by;
-    *sweeps_per_launch = c->plan.T;
-    *waves_per_simd = c->plan.occ;
+    if (which != 0 && which != 1) return fail(SRJ_ERR_INVALID, "which must be 0 or 1");
+    const SweepPlan &pl = which == 0 ? c->plan : c->plan_inner;
+    *kind = pl.kind;
+    *tile_rows = pl.by;
+    *sweeps_per_launch = pl.T;
+    *waves_per_simd = pl.occ;
     return SRJ_OK;
 }
 
-srj_status srj_plan_variants(int32_t *out, int32_t cap, int32_t *count)
+srj_status srj_plan_variants(int32_t which, int32_t *out, int32_t cap, int32_t *count)
 {
     if (!count || (cap > 0 && !out)) return fail(SRJ_ERR_INVALID, "NULL argument");
-    *count = plan_variants(out, cap);
+    if (which != 0 && which != 1) return fail(SRJ_ERR_INVALID, "which must be 0 or 1");
+    *count = which == 0 ? plan_variants(out, cap) : inner_plan_variants(out, cap);
     return SRJ_OK;
 }
 

@@ -119,7 +119,8 @@ struct srj_ctx {
     float *omega32_dev = nullptr;  // the same table rounded to binary32
     std::vector<int32_t> offsets;  // level -> first factor in the tables
     srj::ReduceScratch rs;
-    srj::SweepPlan plan;
+    srj::SweepPlan plan;        // binary64 sweeps
+    srj::SweepPlan plan_inner;  // inner sweeps of the refinement modes
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     // Profiling: HIP events around the sweep launches of each cycle.
     bool profiling = false;
@@ -138,5 +139,7 @@ int next_level(srj_rule rule, int level, double ratio, int max_level);
 srj_status refine_solve(srj_ctx *ctx, double *x, const srj_solve_opts *o, srj_solve_result *res,
                         int32_t *levels_out, double *norms_out);
 void refine_free(srj_ctx *ctx);
+bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan);
+int inner_plan_variants(int32_t *out, int cap);
 }  // namespace srj
 

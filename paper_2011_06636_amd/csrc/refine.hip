@@ -23,44 +23,12 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "storage.h"
+#include "tile2d.h"
 
 #pragma clang fp contract(off)
 
 namespace srj {
-
-// ---------------------------------------------------------------------------
-// Storage formats of the correction
-// ---------------------------------------------------------------------------
-struct StF32 {
-    using T = float;
-    static constexpr int bytes = 4;
-    __device__ static float load(T v) { return v; }
-    __device__ static T store(float v) { return v; }
-};
-
-struct StF16 {
-    using T = _Float16;
-    static constexpr int bytes = 2;
-    __device__ static float load(T v) { return static_cast<float>(v); }
-    // hardware conversion: round to nearest even, subnormals kept, overflow to inf
-    __device__ static T store(float v) { return static_cast<_Float16>(v); }
-};
-
-struct StBF16 {
-    using T = uint16_t;
-    static constexpr int bytes = 2;
-    __device__ static float load(T v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
-    // round to nearest even on the upper 16 bits: add 0x7fff plus the lowest kept
-    // bit, then truncate; a carry into the exponent gives the next binade or inf
-    __device__ static T store(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7f800000u) == 0x7f800000u)  // inf or nan: keep (quiet the nan)
-            return static_cast<T>((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return static_cast<T>(u >> 16);
-    }
-};
 
 namespace {
 
@@ -176,6 +144,28 @@ dim3 row_grid(int64_t n0, int64_t n1, int64_t n2)
     return dim3((unsigned)((n0 + kBlock - 1) / kBlock), (unsigned)n1, (unsigned)n2);
 }
 
+// Fused inner-sweep variants (tile rows, halo); binary32 arithmetic keeps two
+// values per register pair less than binary64, so taller tiles fit.
+#define SRJ_INNER_VARIANTS(X) \
+    X(16, 2) X(24, 4) X(32, 4) X(32, 6) X(48, 6) X(48, 8) X(64, 8)
+
+template <class St>
+hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, const void *d, void *dout,
+                              const void *rhat, const float *w_dev, int T, hipStream_t s)
+{
+    using TT = typename St::T;
+    const Coef2D<float> k2{Q.dconst, Q.dinvconst, Q.c[0], Q.c[1]};
+    const TT *dd = static_cast<const TT *>(d);
+    TT *oo = static_cast<TT *>(dout);
+    const TT *rr = static_cast<const TT *>(rhat);
+#define SRJ_TRY(R, HL)                                                                      \
+    if (plan.by == R && plan.T <= HL)                                                        \
+        return launch_tile2d<St, R, HL, false, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
+    SRJ_INNER_VARIANTS(SRJ_TRY)
+#undef SRJ_TRY
+    return hipErrorInvalidValue;
+}
+
 template <class St>
 hipError_t launch_inner(const DevProblem32 &Q, const void *d, void *dout, const void *rhat, float w,
                         hipStream_t s)
@@ -219,6 +209,33 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 }
 
 }  // namespace
+
+bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
+{
+    if (plan.kind != 1 || plan.occ != 1 || plan.T < 1) return false;
+    if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag)) return false;
+#define SRJ_CHECK(R, HL) \
+    if (plan.by == R && plan.T <= HL) return true;
+    SRJ_INNER_VARIANTS(SRJ_CHECK)
+#undef SRJ_CHECK
+    return false;
+}
+
+int inner_plan_variants(int32_t *out, int cap)
+{
+    int n = 0;
+#define SRJ_LIST(R, HL)                \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 1;            \
+        out[4 * n + 1] = R;            \
+        out[4 * n + 2] = HL;           \
+        out[4 * n + 3] = 1;            \
+    }                                  \
+    ++n;
+    SRJ_INNER_VARIANTS(SRJ_LIST)
+#undef SRJ_LIST
+    return n;
+}
 
 // ---------------------------------------------------------------------------
 // Workspaces
@@ -346,6 +363,7 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
     const double tgt = o->scale_target > 0.0 ? o->scale_target
                        : (o->precision == SRJ_PREC_F16_REFINE ? ldexp(1.0, -8) : 1.0);
     const int64_t nb = residual_blocks(c->P);
+    const bool fused = inner_fused_supported(c->P, c->plan_inner);
 
     double *cur = x, *nxt = c->ws;
     double norm0 = 0.0;
@@ -375,22 +393,31 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
             if (res->sweeps + M > o->max_sweeps) break;
             st = zero_storage<St>(c, da);
             if (st != SRJ_OK) return st;
-            const float *w32 = nullptr;
-            std::vector<float> wl(M);
-            {
-                const std::vector<double> &w = level_factors(lv);
-                for (int k = 0; k < M; ++k) wl[k] = static_cast<float>(w[k]);
-                w32 = wl.data();
-            }
+            const float *w32dev = c->omega32_dev + c->offsets[lv];
+            int64_t launches = 0;
             if (c->profiling) SRJ_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
-            for (int k = 0; k < M; ++k) {
-                SRJ_HIP_CHECK(launch_inner<St>(Q, da, db, R->rhat, w32[k], c->stream));
-                std::swap(da, db);
+            if (fused) {
+                for (int done = 0; done < M;) {
+                    const int T = std::min(c->plan_inner.T, M - done);
+                    SRJ_HIP_CHECK(launch_inner_fused<St>(c->plan_inner, Q, da, db, R->rhat,
+                                                         w32dev + done, T, c->stream));
+                    std::swap(da, db);
+                    done += T;
+                    ++launches;
+                }
+            } else {
+                const std::vector<double> &w = level_factors(lv);
+                for (int k = 0; k < M; ++k) {
+                    SRJ_HIP_CHECK(launch_inner<St>(Q, da, db, R->rhat, static_cast<float>(w[k]),
+                                                   c->stream));
+                    std::swap(da, db);
+                    ++launches;
+                }
             }
             if (c->profiling) {
                 SRJ_HIP_CHECK(hipEventRecord(c->ev1, c->stream));
                 c->prof_pending = true;
-                c->prof_pending_launches = M;
+                c->prof_pending_launches = launches;
                 c->prof_pending_sweeps = M;
             }
             res->sweeps += M;

@@ -8,6 +8,8 @@
 // tile shape or number of fused sweeps is used.  A ghost neighbour holds zero;
 // subtracting c * 0 leaves s unchanged, which equals omitting the term.
 #include "internal.h"
+#include "storage.h"
+#include "tile2d.h"
 
 #pragma clang fp contract(off)
 
@@ -54,135 +56,6 @@ __global__ void k_dinv(const double *__restrict__ d, double *__restrict__ dinv, 
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dinv[i] = 1.0 / d[i];
-}
-
-// ---------------------------------------------------------------------------
-// 2D register-tiled kernel, constant coefficients, T <= HALO sweeps fused.
-//
-// Each wave owns a tile of 64 columns x H rows of the grid (halo included):
-// lane = column, the H rows of its column live in registers.  Vertical
-// neighbours are the lane's own registers; horizontal neighbours come from
-// the adjacent lanes through DPP wave shifts (full-rate VALU moves).  After
-// sweep k the outermost k columns/rows of the tile hold stale values, so the
-// (64 - 2 HALO) x (H - 2 HALO) centre is exact after up to HALO sweeps and is
-// written back.  Points outside the grid (the Dirichlet ghosts) hold zero
-// and are never updated.  Tiles that lie wholly inside the grid take a path
-// without any masking.  b stays in registers (BLDS = false) or in LDS
-// (BLDS = true, fewer registers, more waves per SIMD).  No barriers: waves
-// are independent.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double lane_prev(double v)  // value of lane - 1 (lane 0: 0)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_next(double v)  // value of lane + 1 (lane 63: 0)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-template <int H, bool MASK, bool BLDS>
-__device__ __forceinline__ void tile_sweeps(double (&xr)[H], const double (&br)[H],
-                                            const double *__restrict__ bl, bool col_in,
-                                            uint64_t rowbits, const double *__restrict__ wlist,
-                                            int T, double D, double Dinv, double c0, double c1)
-{
-    for (int k = 0; k < T; ++k) {
-        const double w = wlist[k];
-        double up = 0.0;  // old value of the row above (zero above the tile)
-#pragma unroll
-        for (int r = 0; r < H; ++r) {
-            const double xc = xr[r];
-            const double xl = lane_prev(xc);
-            const double xh = lane_next(xc);
-            const double dn = (r + 1 < H) ? xr[r + 1] : 0.0;
-            double s = D * xc;
-            s = s - c0 * xl;
-            s = s - c0 * xh;
-            s = s - c1 * up;
-            s = s - c1 * dn;
-            const double bv = BLDS ? bl[r * 64] : br[r];
-            const double rr = bv - s;
-            const double t = Dinv * rr;
-            const double nx = xc + w * t;
-            up = xc;
-            if (MASK)
-                xr[r] = (col_in && ((rowbits >> r) & 1)) ? nx : 0.0;
-            else
-                xr[r] = nx;
-        }
-    }
-}
-
-template <int H, int HALO, bool BLDS, int WPB, int OCC>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_sweep2d_reg(DevProblem P, const double *__restrict__ x,
-                                                     double *__restrict__ xo,
-                                                     const double *__restrict__ wlist, int T,
-                                                     int tiles_x, int tiles_y)
-{
-    constexpr int OW = 64 - 2 * HALO;  // output columns per tile
-    constexpr int OH = H - 2 * HALO;   // output rows per tile
-    static_assert(H <= 64, "row validity is a 64-bit mask");
-    __shared__ double bsh[BLDS ? WPB * H * 64 : 1];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tile = blockIdx.x * WPB + wave;
-    if (tile >= tiles_x * tiles_y) return;  // whole wave leaves
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int64_t n0 = P.n0, n1 = P.n1;
-    const int64_t gx0 = (int64_t)tx * OW - HALO;
-    const int64_t gy0 = (int64_t)ty * OH - HALO;
-    const int64_t gx = gx0 + lane;
-    const bool col_in = gx >= 0 && gx < n0;
-    const bool interior = gx0 >= 0 && gx0 + 64 <= n0 && gy0 >= 0 && gy0 + H <= n1;
-    uint64_t rowbits = 0;
-#pragma unroll
-    for (int r = 0; r < H; ++r)
-        if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= (uint64_t)1 << r;
-    const double D = P.dconst, Dinv = P.dinvconst, c0 = P.c[0], c1 = P.c[1];
-
-    double xr[H], br[H];
-    double *bl = bsh + (BLDS ? wave * H * 64 + lane : 0);
-#pragma unroll
-    for (int r = 0; r < H; ++r) {
-        const bool in = col_in && ((rowbits >> r) & 1);
-        const int64_t p = (gy0 + r) * n0 + gx;
-        xr[r] = in ? x[p] : 0.0;
-        const double bv = in ? P.b[p] : 0.0;
-        if (BLDS)
-            bl[r * 64] = bv;
-        else
-            br[r] = bv;
-    }
-    if (interior)
-        tile_sweeps<H, false, BLDS>(xr, br, bl, col_in, rowbits, wlist, T, D, Dinv, c0, c1);
-    else
-        tile_sweeps<H, true, BLDS>(xr, br, bl, col_in, rowbits, wlist, T, D, Dinv, c0, c1);
-    if (lane >= HALO && lane < 64 - HALO && col_in) {
-#pragma unroll
-        for (int r = HALO; r < H - HALO; ++r) {
-            if ((rowbits >> r) & 1) xo[(gy0 + r) * n0 + gx] = xr[r];
-        }
-    }
-}
-
-template <int H, int HALO, bool BLDS, int OCC>
-hipError_t launch_2d_reg(const DevProblem &P, const double *x, double *xo, const double *w_dev,
-                         int T, hipStream_t s)
-{
-    // b in LDS: one wave per block keeps the block's LDS at H * 512 bytes
-    constexpr int WPB = BLDS ? 1 : 4;
-    constexpr int OW = 64 - 2 * HALO, OH = H - 2 * HALO;
-    const int tiles_x = (int)((P.n0 + OW - 1) / OW);
-    const int tiles_y = (int)((P.n1 + OH - 1) / OH);
-    const int64_t tiles = (int64_t)tiles_x * tiles_y;
-    const int blocks = (int)((tiles + WPB - 1) / WPB);
-    hipLaunchKernelGGL((k_sweep2d_reg<H, HALO, BLDS, WPB, OCC>), dim3(blocks), dim3(64 * WPB), 0, s, P,
-                       x, xo, w_dev, T, tiles_x, tiles_y);
-    return hipGetLastError();
 }
 
 // Tile variants: rows H, halo (= most sweeps per launch), b in LDS or not.
@@ -252,11 +125,11 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s)
 {
-    // the first variant (smallest halo) that covers the plan's sweeps per launch
     const bool blds = plan.kind == 2;
+    const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
 #define SRJ_TRY(R, HL, BL, OC)                                                             \
     if (plan.by == R && blds == BL && plan.T <= HL && plan.occ == OC)                      \
-        return launch_2d_reg<R, HL, BL, OC>(P, x, xo, w_dev, T, s);
+        return launch_tile2d<StF64, R, HL, BL, OC>(P.n0, P.n1, x, xo, P.b, w_dev, T, k2, s);
     SRJ_2D_VARIANTS(SRJ_TRY)
 #undef SRJ_TRY
     return hipErrorInvalidValue;

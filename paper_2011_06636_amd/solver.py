@@ -78,11 +78,13 @@ class Solver:
     def to_device(self, a) -> torch.Tensor:
         return _dev(np.asarray(a).reshape(self.shape), self.device)
 
-    def set_plan(self, kind: int, tile_rows: int = 0, sweeps: int = 1, occ: int = 1) -> int:
-        return abi.srj_set_plan(self.ctx, kind, tile_rows, sweeps, occ)
+    def set_plan(self, kind: int, tile_rows: int = 0, sweeps: int = 1, occ: int = 1,
+                 which: int = 0) -> int:
+        """which = 0: binary64 sweeps; which = 1: inner sweeps of the refinement modes."""
+        return abi.srj_set_plan(self.ctx, kind, tile_rows, sweeps, occ, which)
 
-    def get_plan(self):
-        return abi.srj_get_plan(self.ctx)
+    def get_plan(self, which: int = 0):
+        return abi.srj_get_plan(self.ctx, which)
 
     def set_profiling(self, enable: bool = True) -> None:
         abi.srj_set_profiling(self.ctx, enable)

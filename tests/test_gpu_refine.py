@@ -77,3 +77,29 @@ def test_refine_error_vs_f64(torch_cuda, orc, precision):
     # the binary64 residual of the returned iterate, recomputed by the oracle
     assert orc.residual_norm(prob, x) < 1e-10 * out["r0"]
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+def test_inner_plans_bit_identical(torch_cuda, orc, precision):
+    # every fused inner-sweep variant gives the bits of one sweep per launch,
+    # on a grid with ragged tiles in both directions, and the oracle agrees
+    from paper_2011_06636_amd import abi
+    prob = workloads.poisson([301, 137], b=np.random.default_rng(8).uniform(-1, 1, (1, 137, 301)))
+    s = _solver(prob)
+    kw = dict(tol=1e-300, precision=precision, max_cycles=10)
+    plans = [(0, 0, 1, 1)]
+    for kind, rows, halo, occ in abi.srj_plan_variants(which=1):
+        plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan, which=1) == 0, plan
+        out = s.solve(**kw)
+        results[plan] = (out["levels"].copy(), out["x"].cpu().numpy())
+    base_lv, base_x = results[(0, 0, 1, 1)]
+    for plan, (lv, xv) in results.items():
+        assert np.array_equal(lv, base_lv), plan
+        assert np.array_equal(xv, base_x), plan
+    ref = orc.solve(prob, **kw)
+    np.testing.assert_array_equal(ref["levels"], base_lv)
+    assert np.max(np.abs(base_x - ref["x"])) <= 1e-12 * np.max(np.abs(ref["x"]))
+    s.close()
