@@ -78,6 +78,11 @@ srj_status validate_opts(const srj_solve_opts *o)
 SweepPlan default_inner_plan(const DevProblem &P)
 {
     SweepPlan pl;
+    if (P.ndim == 3) {
+        pl.kind = 3;
+        pl.by = 16;
+        return pl;
+    }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
         pl.kind = 1;
         pl.by = 24;
@@ -92,6 +97,11 @@ SweepPlan default_plan(const DevProblem &P)
     SweepPlan pl;
     pl.kind = 0;
     pl.T = 1;
+    if (P.ndim == 3) {
+        pl.kind = 3;
+        pl.by = 16;
+        return pl;
+    }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
         pl.kind = 1;
         pl.by = 24;

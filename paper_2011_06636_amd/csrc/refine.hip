@@ -25,6 +25,7 @@
 #include "internal.h"
 #include "storage.h"
 #include "tile2d.h"
+#include "stream3d.h"
 
 #pragma clang fp contract(off)
 
@@ -158,6 +159,15 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     const TT *dd = static_cast<const TT *>(d);
     TT *oo = static_cast<TT *>(dout);
     const TT *rr = static_cast<const TT *>(rhat);
+    if (plan.kind == 3) {
+        const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
+                                {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
+                                Q.diag, Q.dinv};
+#define SRJ_GO(Z) if (plan.by == Z) return launch_stream3d<St, Z>(S, dd, oo, rr, w_dev, s);
+        SRJ_3D_CHUNKS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
 #define SRJ_TRY(R, HL)                                                                      \
     if (plan.by == R && plan.T <= HL)                                                        \
         return launch_tile2d<St, R, HL, false, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
@@ -212,6 +222,13 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 3) {
+        if (P.ndim != 3 || plan.T != 1 || plan.occ != 1) return false;
+#define SRJ_CHK(Z) if (plan.by == Z) return true;
+        SRJ_3D_CHUNKS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind != 1 || plan.occ != 1 || plan.T < 1) return false;
     if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag)) return false;
 #define SRJ_CHECK(R, HL) \
@@ -224,6 +241,16 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 int inner_plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST3(Z)                   \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 3;            \
+        out[4 * n + 1] = Z;            \
+        out[4 * n + 2] = 1;            \
+        out[4 * n + 3] = 1;            \
+    }                                  \
+    ++n;
+    SRJ_3D_CHUNKS(SRJ_LIST3)
+#undef SRJ_LIST3
 #define SRJ_LIST(R, HL)                \
     if (n < cap) {                     \
         out[4 * n + 0] = 1;            \

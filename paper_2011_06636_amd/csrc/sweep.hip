@@ -10,6 +10,7 @@
 #include "internal.h"
 #include "storage.h"
 #include "tile2d.h"
+#include "stream3d.h"
 
 #pragma clang fp contract(off)
 
@@ -98,6 +99,16 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 int plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST3(Z)                   \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 3;            \
+        out[4 * n + 1] = Z;            \
+        out[4 * n + 2] = 1;            \
+        out[4 * n + 3] = 1;            \
+    }                                  \
+    ++n;
+    SRJ_3D_CHUNKS(SRJ_LIST3)
+#undef SRJ_LIST3
     for (const TileVariant &v : kVariants) {
         if (n < cap) {
             out[4 * n + 0] = v.blds ? 2 : 1;
@@ -112,6 +123,13 @@ int plan_variants(int32_t *out, int cap)
 
 bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 3) {
+        if (P.ndim != 3 || plan.T != 1 || plan.occ != 1) return false;
+#define SRJ_CHK(Z) if (plan.by == Z) return true;
+        SRJ_3D_CHUNKS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 1 || plan.kind == 2) {
         if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && plan.T >= 1)) return false;
         for (const TileVariant &v : kVariants)
@@ -125,6 +143,15 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s)
 {
+    if (plan.kind == 3) {
+        const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
+                                 {P.face[0], P.face[1], P.face[2]}, P.dconst, P.dinvconst,
+                                 P.diag, P.dinv};
+#define SRJ_GO(Z) if (plan.by == Z) return launch_stream3d<StF64, Z>(S, x, xo, P.b, w_dev, s);
+        SRJ_3D_CHUNKS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     const bool blds = plan.kind == 2;
     const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
 #define SRJ_TRY(R, HL, BL, OC)                                                             \

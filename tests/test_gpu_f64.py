@@ -80,6 +80,7 @@ SOLVE_CASES = [
     ("c2_recipe_ragged_333x190", lambda: workloads.poisson([333, 190], b=np.random.default_rng(9).uniform(-1, 1, (1, 190, 333))), dict(tol=1e-10)),
     ("3d_poisson_32_f1", lambda: workloads.poisson([32, 32, 32]), dict(tol=1e-8)),
     ("3d_varcoef_24", lambda: workloads.variable_coefficient(24, seed=0), dict(tol=1e-10)),
+    ("3d_varcoef_c3_recipe_48", lambda: workloads.variable_coefficient(48, seed=0), dict(tol=1e-10)),
     ("3d_aniso_c5_recipe", lambda: workloads.c5_instance(0, lo=16, hi=40), dict(tol=1e-8)),
 ]
 
@@ -110,7 +111,8 @@ def test_fused_plans_bit_identical(torch_cuda, orc):
     from paper_2011_06636_amd import abi
     plans = [(0, 0, 1, 1)]
     for kind, rows, halo, occ in abi.srj_plan_variants():
-        plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+        if kind in (1, 2):
+            plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
     for plan in plans:
         assert s.set_plan(*plan) == 0
         x = s.to_device(x0)
@@ -123,6 +125,38 @@ def test_fused_plans_bit_identical(torch_cuda, orc):
     # and the oracle agrees
     x_ref = x0.copy()
     for level in (0, 3, 8, 11):
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    assert _close(base, x_ref)
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["poisson", "varcoef", "aniso"])
+def test_3d_plans_bit_identical(torch_cuda, orc, case):
+    # the z-streaming 3D kernels (every chunk length) give the bits of the
+    # one-sweep kernel, on a ragged box, and the oracle agrees
+    from paper_2011_06636_amd import abi
+    if case == "poisson":
+        prob = workloads.poisson([70, 9, 37], b=np.random.default_rng(6).uniform(-1, 1, (37, 9, 70)))
+    elif case == "varcoef":
+        prob = workloads.variable_coefficient(27, seed=2, corr_len=3.0)
+    else:
+        prob = workloads.c5_instance(7, lo=20, hi=45)
+    s = _solver(prob)
+    x0 = np.random.default_rng(7).uniform(-1, 1, prob.shape)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] == 3]
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in (0, 4, 9):
+            s.run_cycle(x, level)
+        results[plan] = x.cpu().numpy()
+    base = results[(0, 0, 1, 1)]
+    for plan, v in results.items():
+        assert np.array_equal(v, base), plan
+    x_ref = x0.copy()
+    for level in (0, 4, 9):
         for w in orc.scheme(level):
             x_ref = orc.sweep(prob, x_ref, w)
     assert _close(base, x_ref)
@@ -180,6 +214,23 @@ def test_c2_full_size_first_cycles(torch_cuda, orc):
     x_gpu = s.zeros()
     x_ref = np.zeros(prob.shape)
     for level in range(12):
+        nrm = s.run_cycle(x_gpu, level)
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    got = x_gpu.cpu().numpy()
+    assert _close(got, x_ref), np.max(np.abs(got - x_ref))
+    assert abs(nrm - orc.residual_norm(prob, x_ref)) <= 1e-12 * nrm
+    s.close()
+
+
+def test_c3_full_size_first_cycles(torch_cuda, orc):
+    # the 256^3 variable-coefficient workload: its first 9 cycles (levels 0..8,
+    # 87 sweeps) point by point against the oracle, default plan
+    prob = workloads.c3()
+    s = _solver(prob)
+    x_gpu = s.zeros()
+    x_ref = np.zeros(prob.shape)
+    for level in range(9):
         nrm = s.run_cycle(x_gpu, level)
         for w in orc.scheme(level):
             x_ref = orc.sweep(prob, x_ref, w)

@@ -89,7 +89,30 @@ def test_inner_plans_bit_identical(torch_cuda, orc, precision):
     kw = dict(tol=1e-300, precision=precision, max_cycles=10)
     plans = [(0, 0, 1, 1)]
     for kind, rows, halo, occ in abi.srj_plan_variants(which=1):
-        plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+        if kind == 1:
+            plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan, which=1) == 0, plan
+        out = s.solve(**kw)
+        results[plan] = (out["levels"].copy(), out["x"].cpu().numpy())
+    base_lv, base_x = results[(0, 0, 1, 1)]
+    for plan, (lv, xv) in results.items():
+        assert np.array_equal(lv, base_lv), plan
+        assert np.array_equal(xv, base_x), plan
+    ref = orc.solve(prob, **kw)
+    np.testing.assert_array_equal(ref["levels"], base_lv)
+    assert np.max(np.abs(base_x - ref["x"])) <= 1e-12 * np.max(np.abs(ref["x"]))
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+def test_inner_3d_plans_bit_identical(torch_cuda, orc, precision):
+    from paper_2011_06636_amd import abi
+    prob = workloads.variable_coefficient(23, seed=4, corr_len=3.0)
+    s = _solver(prob)
+    kw = dict(tol=1e-300, precision=precision, max_cycles=9)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] == 3]
     results = {}
     for plan in plans:
         assert s.set_plan(*plan, which=1) == 0, plan
