@@ -186,21 +186,36 @@ srj_status srj_get_profile(srj_ctx *ctx, double *sweep_ms, int64_t *launches, in
 /* Release a context and its workspaces (NULL is accepted). */
 srj_status srj_destroy(srj_ctx *ctx);
 
-/* Batched solves: `count` independent problems (each as in srj_setup), all
- * run by the same launches with per-instance scheme choice (Algorithm 1)
- * and per-instance stopping.  probs[i].b etc. are borrowed device pointers. */
+/* Batched solves: `count` independent problems (each described as for
+ * srj_setup, constant couplings and diagonal only; 1D, 2D and 3D may be
+ * mixed), advanced together with per-instance scheme choice (Algorithm 1),
+ * stopping and caps.  The b arrays are copied into packed device storage at
+ * setup (the caller may free them afterwards).  The batch runs on its own
+ * stream; calls synchronise with hip_stream before reading caller memory.
+ * SRJ_ERR_UNSUPPORTED for per-face couplings or a per-point diagonal. */
 srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_stream,
                            srj_batch **out);
 
-/* xs[i] is instance i's device solution array (in/out).  res[count] and
- * levels_out[count * max_cycles] (may be NULL) are host arrays.  Returns
- * SRJ_OK if every instance converged, else the first non-OK status. */
+/* Kernel plan of a batch: 2D/1D instances use register tiles of 64 columns x
+ * tile_rows rows (16, 24, 32 or 48) fusing up to sweeps_per_launch sweeps per
+ * step (at most 2, 4, 4/6 or 8); 3D instances advance one z-streamed sweep per
+ * step.  steps_per_graph steps are captured in one hipGraph (use_graph = 1)
+ * or enqueued directly (use_graph = 0).  Iterates do not depend on the plan. */
+srj_status srj_batch_set_plan(srj_batch *batch, int32_t tile_rows, int32_t sweeps_per_launch,
+                              int32_t steps_per_graph, int32_t use_graph);
+
+/* Solve every instance from its initial guess xs[i] (device, in/out, the
+ * instance's n0*n1*n2 binary64 values).  opts applies to every instance
+ * (relative tolerances use each instance's own r0).  res[count] (host)
+ * receives each instance's counters; levels_out (host, count * max_cycles,
+ * may be NULL) the level of each of its cycles.  Returns SRJ_OK if every
+ * instance converged, else the first non-OK status among the instances (all
+ * results filled).  Blocks until done. */
 srj_status srj_batch_solve(srj_batch *batch, double *const *xs, const srj_solve_opts *opts,
                            srj_solve_result *res, int32_t *levels_out);
 
 srj_status srj_batch_destroy(srj_batch *batch);
 
-/* Thread-local text for the last non-OK status returned on this thread. */
 const char *srj_last_error(void);
 
 #ifdef __cplusplus

@@ -33,7 +33,7 @@ EXPORTS = [
     "srj_default_opts", "srj_scheme", "srj_setup", "srj_run_cycle", "srj_residual_norm",
     "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_plan_variants",
     "srj_set_profiling",
-    "srj_get_profile", "srj_batch_setup",
+    "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan",
     "srj_batch_solve", "srj_batch_destroy", "srj_last_error",
 ]
 
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
         "srj_set_profiling": (i32, [vp, i32]),
         "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
+        "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
         "srj_last_error": (ctypes.c_char_p, []),
@@ -202,6 +203,12 @@ def srj_batch_setup(probs, stream: int = 0):
     h = ctypes.c_void_p()
     st = load().srj_batch_setup(len(probs), arr, ctypes.c_void_p(stream), ctypes.byref(h))
     return st, h
+
+
+def srj_batch_set_plan(batch, tile_rows: int, sweeps: int, steps_per_graph: int = 16,
+                       use_graph: bool = True) -> int:
+    return load().srj_batch_set_plan(batch, tile_rows, sweeps, steps_per_graph,
+                                     1 if use_graph else 0)
 
 
 def srj_batch_solve(batch, x_ptrs, opts: SrjSolveOpts, levels=None):

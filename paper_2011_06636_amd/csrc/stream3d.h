@@ -31,19 +31,15 @@ struct Stencil3 {
     const A *dinv;
 };
 
+// One thread: column (i0, i1), planes z0 .. z0 + ZC - 1.
 template <class V, int ZC>
-__global__ __launch_bounds__(256) void k_stream3d(Stencil3<typename V::A> S,
-                                                  const typename V::T *__restrict__ x,
-                                                  typename V::T *__restrict__ xo,
-                                                  const typename V::T *__restrict__ b,
-                                                  const typename V::A *__restrict__ wp)
+__device__ __forceinline__ void stream3d_run(const Stencil3<typename V::A> &S,
+                                             const typename V::T *__restrict__ x,
+                                             typename V::T *__restrict__ xo,
+                                             const typename V::T *__restrict__ b,
+                                             typename V::A w, int64_t i0, int64_t i1, int64_t z0)
 {
     using A = typename V::A;
-    const A w = wp[0];
-    const int64_t i0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int64_t i1 = (int64_t)blockIdx.y * 4 + threadIdx.y;
-    const int64_t z0 = (int64_t)blockIdx.z * ZC;
-    if (i0 >= S.n0 || i1 >= S.n1) return;  // no barriers below
     const int64_t zend = z0 + ZC < S.n2 ? z0 + ZC : S.n2;
     const int64_t s1 = S.n0, s2 = S.n0 * S.n1;
     int64_t p = i0 + s1 * i1 + s2 * z0;
@@ -69,6 +65,19 @@ __global__ __launch_bounds__(256) void k_stream3d(Stencil3<typename V::A> S,
         xc = xp;
         f2m = f2c;
     }
+}
+
+template <class V, int ZC>
+__global__ __launch_bounds__(256) void k_stream3d(Stencil3<typename V::A> S,
+                                                  const typename V::T *__restrict__ x,
+                                                  typename V::T *__restrict__ xo,
+                                                  const typename V::T *__restrict__ b,
+                                                  const typename V::A *__restrict__ wp)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t i1 = (int64_t)blockIdx.y * 4 + threadIdx.y;
+    if (i0 >= S.n0 || i1 >= S.n1) return;  // no barriers below
+    stream3d_run<V, ZC>(S, x, xo, b, wp[0], i0, i1, (int64_t)blockIdx.z * ZC);
 }
 
 template <class V, int ZC>

@@ -90,22 +90,20 @@ __device__ __forceinline__ void tile_sweeps(typename V::A (&xr)[H], const typena
     }
 }
 
-template <class V, int H, int HALO, bool BLDS, int WPB, int OCC>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void
-k_tile2d(int64_t n0, int64_t n1, const typename V::T *__restrict__ x, typename V::T *__restrict__ xo,
-         const typename V::T *__restrict__ b, const typename V::A *__restrict__ wlist, int T,
-         Coef2D<typename V::A> k2, int tiles_x, int tiles_y)
+// Body of one wave's tile (tile column tx, tile row ty); bl is this lane's
+// slot in LDS when BLDS, else unused.
+template <class V, int H, int HALO, bool BLDS>
+__device__ __forceinline__ void tile2d_run(int64_t n0, int64_t n1, const typename V::T *__restrict__ x,
+                                           typename V::T *__restrict__ xo,
+                                           const typename V::T *__restrict__ b,
+                                           const typename V::A *__restrict__ wlist, int T,
+                                           Coef2D<typename V::A> k2, int tx, int ty, int lane,
+                                           typename V::A *bl)
 {
     using A = typename V::A;
     constexpr int OW = 64 - 2 * HALO;  // output columns per tile
     constexpr int OH = H - 2 * HALO;   // output rows per tile
     static_assert(H <= 64, "row validity is a 64-bit mask");
-    __shared__ A bsh[BLDS ? WPB * H * 64 : 1];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tile = blockIdx.x * WPB + wave;
-    if (tile >= tiles_x * tiles_y) return;  // whole wave leaves
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int64_t gx0 = (int64_t)tx * OW - HALO;
     const int64_t gy0 = (int64_t)ty * OH - HALO;
     const int64_t gx = gx0 + lane;
@@ -117,7 +115,6 @@ k_tile2d(int64_t n0, int64_t n1, const typename V::T *__restrict__ x, typename V
         if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= (uint64_t)1 << r;
 
     A xr[H], br[H];
-    A *bl = bsh + (BLDS ? wave * H * 64 + lane : 0);
 #pragma unroll
     for (int r = 0; r < H; ++r) {
         const bool in = col_in && ((rowbits >> r) & 1);
@@ -139,6 +136,23 @@ k_tile2d(int64_t n0, int64_t n1, const typename V::T *__restrict__ x, typename V
             if ((rowbits >> r) & 1) xo[(gy0 + r) * n0 + gx] = V::store(xr[r]);
         }
     }
+}
+
+template <class V, int H, int HALO, bool BLDS, int WPB, int OCC>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void
+k_tile2d(int64_t n0, int64_t n1, const typename V::T *__restrict__ x, typename V::T *__restrict__ xo,
+         const typename V::T *__restrict__ b, const typename V::A *__restrict__ wlist, int T,
+         Coef2D<typename V::A> k2, int tiles_x, int tiles_y)
+{
+    using A = typename V::A;
+    __shared__ A bsh[BLDS ? WPB * H * 64 : 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x * WPB + wave;
+    if (tile >= tiles_x * tiles_y) return;  // whole wave leaves
+    A *bl = bsh + (BLDS ? wave * H * 64 + lane : 0);
+    tile2d_run<V, H, HALO, BLDS>(n0, n1, x, xo, b, wlist, T, k2, tile % tiles_x, tile / tiles_x,
+                                 lane, bl);
 }
 
 template <class V, int H, int HALO, bool BLDS, int OCC>

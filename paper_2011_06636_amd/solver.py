@@ -139,3 +139,64 @@ class Solver:
             "levels": np.array(levels[:nc], dtype=np.int32),
             "norms": np.array(norms[:nc + 1], dtype=np.float64),
         }
+
+
+class BatchSolver:
+    """Many problems solved together: wraps srj_batch_setup / srj_batch_solve.
+
+    ``problems`` is a sequence of objects with the attributes of ``Solver``'s
+    problem (constant couplings and diagonal only).
+    """
+
+    def __init__(self, problems, device: str = "cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        abi.load()
+        self.device = torch.device(device)
+        self.shapes = [tuple(p.b.shape) for p in problems]
+        self.count = len(problems)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        bs = [_dev(p.b, self.device) for p in problems]
+        probs = [make_problem(int(p.ndim), p.n, p.c, p.dconst, b) for p, b in zip(problems, bs)]
+        torch.cuda.synchronize(self.device)
+        st, h = abi.srj_batch_setup(probs, self.stream.cuda_stream)
+        if st != abi.SRJ_OK:
+            raise abi.SrjError(st, "srj_batch_setup")
+        self.handle = h
+        del bs  # packed into the batch at setup
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            abi.srj_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_plan(self, tile_rows: int, sweeps: int, steps_per_graph: int = 16,
+                 use_graph: bool = True) -> int:
+        return abi.srj_batch_set_plan(self.handle, tile_rows, sweeps, steps_per_graph, use_graph)
+
+    def zeros(self):
+        return [torch.zeros(sh, dtype=torch.float64, device=self.device) for sh in self.shapes]
+
+    def solve(self, xs=None, **kw) -> Dict:
+        """Solve every instance in place on xs (zeros if None)."""
+        if xs is None:
+            xs = self.zeros()
+        o = Solver.opts(**kw)
+        levels = (ctypes.c_int32 * (self.count * o.max_cycles))()
+        st, res = abi.srj_batch_solve(self.handle, [x.data_ptr() for x in xs], o, levels)
+        if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
+            raise abi.SrjError(st, "srj_batch_solve")
+        lv = np.array(levels, dtype=np.int32).reshape(self.count, o.max_cycles)
+        out = []
+        for i in range(self.count):
+            r = res[i]
+            out.append({"converged": bool(r.converged), "cycles": r.cycles,
+                        "sweeps": int(r.sweeps), "final_level": r.final_level, "r0": r.r0,
+                        "r_final": r.r_final, "min_margin": r.min_margin,
+                        "levels": lv[i, :r.cycles].copy()})
+        return {"status": abi.STATUS_NAMES[st], "xs": xs, "instances": out}
