@@ -176,6 +176,17 @@ srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *til
  * and their number to *count. */
 srj_status srj_plan_variants(int32_t which, int32_t *out, int32_t cap, int32_t *count);
 
+/* Autotuner: times every plan for `which` (0: binary64 sweeps, 1: inner
+ * sweeps of the refinement modes) that fits this problem, `sweeps` sweeps
+ * each on library scratch buffers (x is not touched), with HIP events on the
+ * context's stream; sets the fastest and writes its time per sweep (us) to
+ * *best_us_per_sweep.  With use_cache != 0 and the environment variable
+ * SRJ_TUNE_CACHE naming a file, a plan cached for the same GPU architecture,
+ * CU count and problem shape class is reused without timing, and new choices
+ * are stored there.  Results never depend on the plan. */
+srj_status srj_autotune(srj_ctx *ctx, int32_t which, int32_t sweeps, int32_t use_cache,
+                        double *best_us_per_sweep);
+
 /* Profiling aid.  While enabled, the relaxation launches of every cycle
  * are bracketed by HIP events recorded on the context's stream; the elapsed
  * times (ms), the number of sweep launches and of sweeps are accumulated.
@@ -203,6 +214,8 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
  * or enqueued directly (use_graph = 0).  Iterates do not depend on the plan. */
 srj_status srj_batch_set_plan(srj_batch *batch, int32_t tile_rows, int32_t sweeps_per_launch,
                               int32_t steps_per_graph, int32_t use_graph);
+srj_status srj_batch_get_plan(srj_batch *batch, int32_t *tile_rows, int32_t *sweeps_per_launch,
+                              int32_t *steps_per_graph, int32_t *use_graph);
 
 /* Solve every instance from its initial guess xs[i] (device, in/out, the
  * instance's n0*n1*n2 binary64 values).  opts applies to every instance
@@ -213,6 +226,13 @@ srj_status srj_batch_set_plan(srj_batch *batch, int32_t tile_rows, int32_t sweep
  * results filled).  Blocks until done. */
 srj_status srj_batch_solve(srj_batch *batch, double *const *xs, const srj_solve_opts *opts,
                            srj_solve_result *res, int32_t *levels_out);
+
+/* Batch autotuner: times every tile plan for `precision` on this batch,
+ * `sweeps` sweeps of its 2D instances from x0 = 0 on the batch's own
+ * buffers (no caller memory is touched), sets the fastest plan and writes its
+ * time per sweep (us) to *best_us_per_sweep. */
+srj_status srj_batch_autotune(srj_batch *batch, int32_t precision, int32_t sweeps,
+                              double *best_us_per_sweep);
 
 srj_status srj_batch_destroy(srj_batch *batch);
 

@@ -32,8 +32,10 @@ MAX_M = 2362
 EXPORTS = [
     "srj_default_opts", "srj_scheme", "srj_setup", "srj_run_cycle", "srj_residual_norm",
     "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_plan_variants",
+    "srj_autotune",
     "srj_set_profiling",
-    "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan",
+    "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan", "srj_batch_get_plan",
+    "srj_batch_autotune",
     "srj_batch_solve", "srj_batch_destroy", "srj_last_error",
 ]
 
@@ -86,10 +88,13 @@ def load() -> ctypes.CDLL:
         "srj_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
         "srj_get_plan": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
         "srj_plan_variants": (i32, [i32, P(i32), i32, P(i32)]),
+        "srj_autotune": (i32, [vp, i32, i32, i32, P(f64)]),
         "srj_set_profiling": (i32, [vp, i32]),
         "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
         "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32]),
+        "srj_batch_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32)]),
+        "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
         "srj_last_error": (ctypes.c_char_p, []),
@@ -182,6 +187,13 @@ def srj_plan_variants(which: int = 0):
     return [tuple(buf[4 * i:4 * i + 4]) for i in range(min(n.value, 128))]
 
 
+def srj_autotune(ctx, which: int = 0, sweeps: int = 48, use_cache: bool = True) -> float:
+    us = ctypes.c_double()
+    check(load().srj_autotune(ctx, which, sweeps, 1 if use_cache else 0, ctypes.byref(us)),
+          "srj_autotune")
+    return us.value
+
+
 def srj_set_profiling(ctx, enable: bool) -> None:
     check(load().srj_set_profiling(ctx, 1 if enable else 0), "srj_set_profiling")
 
@@ -209,6 +221,19 @@ def srj_batch_set_plan(batch, tile_rows: int, sweeps: int, steps_per_graph: int 
                        use_graph: bool = True) -> int:
     return load().srj_batch_set_plan(batch, tile_rows, sweeps, steps_per_graph,
                                      1 if use_graph else 0)
+
+
+def srj_batch_get_plan(batch):
+    v = [ctypes.c_int32() for _ in range(4)]
+    check(load().srj_batch_get_plan(batch, *[ctypes.byref(a) for a in v]), "srj_batch_get_plan")
+    return tuple(a.value for a in v)
+
+
+def srj_batch_autotune(batch, precision: str = "f32", sweeps: int = 48) -> float:
+    us = ctypes.c_double()
+    check(load().srj_batch_autotune(batch, PREC[precision], sweeps, ctypes.byref(us)),
+          "srj_batch_autotune")
+    return us.value
 
 
 def srj_batch_solve(batch, x_ptrs, opts: SrjSolveOpts, levels=None):

@@ -356,6 +356,12 @@ __global__ __launch_bounds__(256) void k_bfinal(const BDesc *__restrict__ desc, 
     st[i] = n;
 }
 
+__global__ void k_fill_f64(double *__restrict__ a, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
 __global__ __launch_bounds__(256) void k_count_done(const BState *__restrict__ st, int n,
                                                     int32_t *__restrict__ out)
 {
@@ -488,53 +494,8 @@ srj_status enqueue_step(srj_batch *B, const BParams &prm)
     return SRJ_OK;
 }
 
-template <class St, bool REFINE>
-srj_status batch_solve_t(srj_batch *B, double *const *xs, const srj_solve_opts *o,
-                         srj_solve_result *res, int32_t *levels_out)
+BParams make_params(const srj_batch *B, const srj_solve_opts *o)
 {
-    const int n = B->count;
-    // the caller's x arrays are read on the batch stream: wait for their producers
-    SRJ_HIP_CHECK(hipStreamSynchronize(B->user_stream));
-    // storage for corrections
-    if (REFINE && B->ubytes < St::bytes) {
-        (void)hipFree(B->ua);
-        (void)hipFree(B->ub);
-        (void)hipFree(B->rhat);
-        B->ua = B->ub = B->rhat = nullptr;
-        B->ubytes = 0;
-        if (hipMalloc(&B->ua, (size_t)B->total * St::bytes) != hipSuccess ||
-            hipMalloc(&B->ub, (size_t)B->total * St::bytes) != hipSuccess ||
-            hipMalloc(&B->rhat, (size_t)B->total * St::bytes) != hipSuccess)
-            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for batched corrections");
-        B->ubytes = St::bytes;
-    }
-    const int64_t hist = (int64_t)o->max_cycles + 1;
-    if (B->hist_cap < hist) {
-        (void)hipFree(B->levels_hist);
-        (void)hipFree(B->norms_hist);
-        B->levels_hist = nullptr;
-        B->norms_hist = nullptr;
-        B->hist_cap = 0;
-        if (hipMalloc(&B->levels_hist, sizeof(int32_t) * (size_t)n * o->max_cycles) != hipSuccess ||
-            hipMalloc(&B->norms_hist, sizeof(double) * (size_t)n * hist) != hipSuccess)
-            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for batch histories");
-        B->hist_cap = hist;
-    }
-    // pack the initial iterates (binary64 into xa)
-    for (int i = 0; i < n; ++i)
-        SRJ_HIP_CHECK(hipMemcpyAsync(B->xa + B->hdesc[i].off, xs[i],
-                                     sizeof(double) * (size_t)B->hdesc[i].npts,
-                                     hipMemcpyDeviceToDevice, B->stream));
-    std::vector<BState> hs(n);
-    for (int i = 0; i < n; ++i) {
-        BState &s = hs[i];
-        memset(&s, 0, sizeof(s));
-        s.level = o->rule == SRJ_RULE_FIXED ? o->fixed_level : o->start_level;
-        s.min_margin = INFINITY;
-        s.status = SRJ_ERR_NOT_CONVERGED;
-    }
-    SRJ_HIP_CHECK(hipMemcpyAsync(B->state, hs.data(), sizeof(BState) * n, hipMemcpyHostToDevice,
-                                 B->stream));
     BParams prm{};
     prm.rule = o->rule;
     prm.fixed_level = o->fixed_level;
@@ -551,12 +512,59 @@ srj_status batch_solve_t(srj_batch *B, double *const *xs, const srj_solve_opts *
     prm.offsets = B->offsets;
     prm.omega64 = B->omega64;
     prm.omega32 = B->omega32;
+    return prm;
+}
 
-    const int cus = B->cus;
-    const int og = (int)std::min<int64_t>(B->hoitems.size(), (int64_t)cus * 8);
+template <class St, bool REFINE>
+srj_status ensure_batch_buffers(srj_batch *B, int max_cycles)
+{
+    const int n = B->count;
+    if (REFINE && B->ubytes < St::bytes) {
+        (void)hipFree(B->ua);
+        (void)hipFree(B->ub);
+        (void)hipFree(B->rhat);
+        B->ua = B->ub = B->rhat = nullptr;
+        B->ubytes = 0;
+        if (hipMalloc(&B->ua, (size_t)B->total * St::bytes) != hipSuccess ||
+            hipMalloc(&B->ub, (size_t)B->total * St::bytes) != hipSuccess ||
+            hipMalloc(&B->rhat, (size_t)B->total * St::bytes) != hipSuccess)
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for batched corrections");
+        B->ubytes = St::bytes;
+    }
+    const int64_t hist = (int64_t)max_cycles + 1;
+    if (B->hist_cap < hist) {
+        (void)hipFree(B->levels_hist);
+        (void)hipFree(B->norms_hist);
+        B->levels_hist = nullptr;
+        B->norms_hist = nullptr;
+        B->hist_cap = 0;
+        if (hipMalloc(&B->levels_hist, sizeof(int32_t) * (size_t)n * max_cycles) != hipSuccess ||
+            hipMalloc(&B->norms_hist, sizeof(double) * (size_t)n * hist) != hipSuccess)
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for batch histories");
+        B->hist_cap = hist;
+    }
+    return SRJ_OK;
+}
+
+// Fresh per-instance state and the initial passes (norms; for refinement the
+// scaled cast of r0 and zeroed corrections).  x0 must already be in xa.
+template <class St, bool REFINE>
+srj_status batch_init(srj_batch *B, const srj_solve_opts *o, const BParams &prm)
+{
+    const int n = B->count;
+    std::vector<BState> hs(n);
+    for (int i = 0; i < n; ++i) {
+        BState &s = hs[i];
+        memset(&s, 0, sizeof(s));
+        s.level = o->rule == SRJ_RULE_FIXED ? o->fixed_level : o->start_level;
+        s.min_margin = INFINITY;
+        s.status = SRJ_ERR_NOT_CONVERGED;
+    }
+    SRJ_HIP_CHECK(hipMemcpyAsync(B->state, hs.data(), sizeof(BState) * n, hipMemcpyHostToDevice,
+                                 B->stream));
+    const int og = (int)std::min<int64_t>(B->hoitems.size(), (int64_t)B->cus * 8);
     void *ua = REFINE ? B->ua : (void *)B->xa;
     void *ub = REFINE ? B->ub : (void *)B->xb;
-    // initial norms (and for refinement the scaled cast of r0 and zero corrections)
     hipLaunchKernelGGL((k_bouter<St, REFINE>), dim3(og), dim3(256), 0, B->stream, B->desc, B->state,
                        B->oitems, (int)B->hoitems.size(), B->b, B->xa, B->xb, ua, ub,
                        (typename St::T *)B->rhat, B->partials, prm, (int)OUT_NORM);
@@ -570,6 +578,55 @@ srj_status batch_solve_t(srj_batch *B, double *const *xs, const srj_solve_opts *
                            (typename St::T *)B->rhat, B->partials, prm, (int)OUT_CAST);
         SRJ_HIP_CHECK(hipGetLastError());
     }
+    return SRJ_OK;
+}
+
+// Times `steps` steps from a fresh state with x0 = 0 (tuning).
+template <class St, bool REFINE>
+srj_status batch_time_steps(srj_batch *B, const srj_solve_opts *o, int steps, float *ms)
+{
+    srj_status st = ensure_batch_buffers<St, REFINE>(B, o->max_cycles);
+    if (st != SRJ_OK) return st;
+    const BParams prm = make_params(B, o);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((B->total + 255) / 256)), dim3(256), 0,
+                       B->stream, B->xa, B->total, 0.0);
+    SRJ_HIP_CHECK(hipGetLastError());
+    st = batch_init<St, REFINE>(B, o, prm);
+    if (st != SRJ_OK) return st;
+    hipEvent_t e0, e1;
+    SRJ_HIP_CHECK(hipEventCreate(&e0));
+    SRJ_HIP_CHECK(hipEventCreate(&e1));
+    st = enqueue_step<St, REFINE>(B, prm);  // warm-up
+    hipError_t e = hipEventRecord(e0, B->stream);
+    for (int k = 0; k < steps && st == SRJ_OK && e == hipSuccess; ++k) st = enqueue_step<St, REFINE>(B, prm);
+    if (e == hipSuccess) e = hipEventRecord(e1, B->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SRJ_OK) return st;
+    SRJ_HIP_CHECK(e);
+    return SRJ_OK;
+}
+
+template <class St, bool REFINE>
+srj_status batch_solve_t(srj_batch *B, double *const *xs, const srj_solve_opts *o,
+                         srj_solve_result *res, int32_t *levels_out)
+{
+    const int n = B->count;
+    // the caller's x arrays are read on the batch stream: wait for their producers
+    SRJ_HIP_CHECK(hipStreamSynchronize(B->user_stream));
+    srj_status bst = ensure_batch_buffers<St, REFINE>(B, o->max_cycles);
+    if (bst != SRJ_OK) return bst;
+    // pack the initial iterates (binary64 into xa)
+    for (int i = 0; i < n; ++i)
+        SRJ_HIP_CHECK(hipMemcpyAsync(B->xa + B->hdesc[i].off, xs[i],
+                                     sizeof(double) * (size_t)B->hdesc[i].npts,
+                                     hipMemcpyDeviceToDevice, B->stream));
+    const BParams prm = make_params(B, o);
+    bst = batch_init<St, REFINE>(B, o, prm);
+    if (bst != SRJ_OK) return bst;
+    std::vector<BState> hs(n);
 
     // steps, replayed from a graph until every instance is done
     hipGraph_t graph = nullptr;
@@ -891,6 +948,69 @@ srj_status srj_batch_solve(srj_batch *B, double *const *xs, const srj_solve_opts
     case SRJ_PREC_BF16_REFINE: return batch_solve_t<StBF16, true>(B, xs, o, res, levels_out);
     default: return fail(SRJ_ERR_INVALID, "unknown precision");
     }
+}
+
+srj_status srj_batch_get_plan(srj_batch *B, int32_t *tile_rows, int32_t *sweeps_per_launch,
+                              int32_t *steps_per_graph, int32_t *use_graph)
+{
+    if (!B || !tile_rows || !sweeps_per_launch || !steps_per_graph || !use_graph)
+        return fail(SRJ_ERR_INVALID, "NULL argument");
+    *tile_rows = B->tile_rows;
+    *sweeps_per_launch = B->T2;
+    *steps_per_graph = B->steps_per_graph;
+    *use_graph = B->use_graph ? 1 : 0;
+    return SRJ_OK;
+}
+
+srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
+                              double *best_us_per_sweep)
+{
+    if (!B || !best_us_per_sweep) return fail(SRJ_ERR_INVALID, "NULL argument");
+    if (sweeps < 1 || sweeps > 100000) return fail(SRJ_ERR_INVALID, "sweeps must be 1..100000");
+    if (precision < SRJ_PREC_F64 || precision > SRJ_PREC_BF16_REFINE)
+        return fail(SRJ_ERR_INVALID, "unknown precision");
+    SRJ_HIP_CHECK(hipStreamSynchronize(B->user_stream));
+    srj_solve_opts o;
+    srj_default_opts(&o);
+    o.precision = (srj_precision)precision;
+    o.tol = 1e-300;  // nothing converges while timing
+    o.max_cycles = 1000000;
+    o.max_sweeps = (int64_t)1 << 60;
+    const int steps_per_graph = B->steps_per_graph;
+    const bool use_graph = B->use_graph;
+    int best_rows = B->tile_rows, best_T = B->T2;
+    double best = INFINITY;
+    struct Cand {
+        int rows, T;
+    };
+    std::vector<Cand> cands;
+#define SRJ_C(R, HL)                                        \
+    cands.push_back({R, HL});                               \
+    if ((HL + 1) / 2 != HL) cands.push_back({R, (HL + 1) / 2});
+    SRJ_BATCH_2D(SRJ_C)
+#undef SRJ_C
+    for (const Cand &cd : cands) {
+        srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, steps_per_graph, use_graph);
+        if (st != SRJ_OK) return st;
+        // every step moves 2D instances by T sweeps and 3D instances by one
+        const int steps = std::max(1, (sweeps + cd.T - 1) / cd.T);
+        float ms = 0.f;
+        switch (o.precision) {
+        case SRJ_PREC_F64: st = batch_time_steps<StF32, false>(B, &o, steps, &ms); break;
+        case SRJ_PREC_F32_REFINE: st = batch_time_steps<StF32, true>(B, &o, steps, &ms); break;
+        case SRJ_PREC_F16_REFINE: st = batch_time_steps<StF16, true>(B, &o, steps, &ms); break;
+        default: st = batch_time_steps<StBF16, true>(B, &o, steps, &ms); break;
+        }
+        if (st != SRJ_OK) return st;
+        const double us = 1e3 * ms / (steps * cd.T);
+        if (us < best) {
+            best = us;
+            best_rows = cd.rows;
+            best_T = cd.T;
+        }
+    }
+    *best_us_per_sweep = best;
+    return srj_batch_set_plan(B, best_rows, best_T, steps_per_graph, use_graph ? 1 : 0);
 }
 
 srj_status srj_batch_destroy(srj_batch *B)

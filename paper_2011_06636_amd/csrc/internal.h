@@ -140,6 +140,13 @@ srj_status refine_solve(srj_ctx *ctx, double *x, const srj_solve_opts *o, srj_so
                         int32_t *levels_out, double *norms_out);
 void refine_free(srj_ctx *ctx);
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan);
+srj_status time_inner_plan(srj_ctx *c, const SweepPlan &plan, int sweeps, const float *w_dev,
+                           float *ms);
+// Autotuner cache (tune.hip): key -> plan and time per sweep.
+std::string tune_key(const char *what, int which, int ndim, const int64_t n[3], bool faces,
+                     bool diag);
+bool tune_cache_get(const std::string &key, SweepPlan &plan, double &us);
+void tune_cache_put(const std::string &key, const SweepPlan &plan, double us);
 int inner_plan_variants(int32_t *out, int cap);
 }  // namespace srj
 

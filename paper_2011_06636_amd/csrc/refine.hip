@@ -493,6 +493,45 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
 
 }  // namespace
 
+// Runs `sweeps` binary32 inner sweeps with `plan` on the refinement
+// workspaces (contents are scratch) and returns the elapsed milliseconds
+// between HIP events on the context's stream.
+srj_status time_inner_plan(srj_ctx *c, const SweepPlan &plan, int sweeps, const float *w_dev,
+                           float *ms)
+{
+    srj_status st = ensure_workspace(c, SRJ_PREC_F32_REFINE);
+    if (st != SRJ_OK) return st;
+    Refine *R = c->refine;
+    const DevProblem32 Q = make_q(c);
+    const bool fused = plan.kind != 0;
+    void *da = R->da, *db = R->db;
+    st = zero_storage<StF32>(c, da);
+    if (st != SRJ_OK) return st;
+    st = zero_storage<StF32>(c, R->rhat);
+    if (st != SRJ_OK) return st;
+    auto run = [&](int n) -> srj_status {
+        for (int done = 0; done < n;) {
+            const int T = fused ? std::min(plan.T, n - done) : 1;
+            if (fused)
+                SRJ_HIP_CHECK(launch_inner_fused<StF32>(plan, Q, da, db, R->rhat, w_dev, T, c->stream));
+            else
+                SRJ_HIP_CHECK(launch_inner<StF32>(Q, da, db, R->rhat, 0.6666667f, c->stream));
+            std::swap(da, db);
+            done += T;
+        }
+        return SRJ_OK;
+    };
+    st = run(fused ? plan.T : 1);  // warm-up
+    if (st != SRJ_OK) return st;
+    SRJ_HIP_CHECK(hipEventRecord(c->ev0, c->stream));
+    st = run(sweeps);
+    if (st != SRJ_OK) return st;
+    SRJ_HIP_CHECK(hipEventRecord(c->ev1, c->stream));
+    SRJ_HIP_CHECK(hipEventSynchronize(c->ev1));
+    SRJ_HIP_CHECK(hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return SRJ_OK;
+}
+
 srj_status refine_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
                         int32_t *levels_out, double *norms_out)
 {

@@ -86,6 +86,10 @@ class Solver:
     def get_plan(self, which: int = 0):
         return abi.srj_get_plan(self.ctx, which)
 
+    def autotune(self, which: int = 0, sweeps: int = 48, use_cache: bool = True) -> float:
+        """Pick the fastest plan for `which` by timing; returns its us per sweep."""
+        return abi.srj_autotune(self.ctx, which, sweeps, use_cache)
+
     def set_profiling(self, enable: bool = True) -> None:
         abi.srj_set_profiling(self.ctx, enable)
 
@@ -178,6 +182,14 @@ class BatchSolver:
     def set_plan(self, tile_rows: int, sweeps: int, steps_per_graph: int = 16,
                  use_graph: bool = True) -> int:
         return abi.srj_batch_set_plan(self.handle, tile_rows, sweeps, steps_per_graph, use_graph)
+
+    def autotune(self, precision: str = "f32", sweeps: int = 48) -> float:
+        """Pick the fastest batch plan by timing; returns its us per sweep."""
+        return abi.srj_batch_autotune(self.handle, precision, sweeps)
+
+    def get_plan(self):
+        """(tile_rows, sweeps per step, steps per graph, use_graph)."""
+        return abi.srj_batch_get_plan(self.handle)
 
     def zeros(self):
         return [torch.zeros(sh, dtype=torch.float64, device=self.device) for sh in self.shapes]

@@ -94,3 +94,20 @@ def test_batch_caps_and_errors(torch_cuda, orc):
     vc = workloads.variable_coefficient(6, seed=1)
     with pytest.raises(abi.SrjError):
         BatchSolver([vc])
+
+
+def test_batch_autotune_keeps_results(torch_cuda, orc):
+    from paper_2011_06636_amd.solver import BatchSolver
+    probs = mixed_batch()
+    bs = BatchSolver(probs)
+    kw = dict(tol=1e-10, precision="f32", max_cycles=200)
+    ref = bs.solve(**kw)
+    ref_x = [x.cpu().numpy() for x in ref["xs"]]
+    us = bs.autotune("f32", sweeps=24)
+    assert us > 0
+    rows, T, _, _ = bs.get_plan()
+    assert rows in (16, 24, 32, 48) and T >= 1
+    out = bs.solve(**kw)
+    for a, b in zip(out["xs"], ref_x):
+        assert np.array_equal(a.cpu().numpy(), b)
+    bs.close()
