@@ -14,6 +14,11 @@ same line reports the binary32-refined solve of the same problem (binary64
 residual and update, binary32 inner cycles) with its time to the target, the
 roofline of the dominant kernel measured with HIP events on the solver's
 stream, and the CPU oracle timed on a bounded sample of the binary64 solve.
+Unless --no-extras is given, the line also carries the other workloads'
+comparisons: the 256^3 variable-coefficient problem (binary64 vs
+binary32-refined time to 1e-10) and the two batches (512 2D problems,
+binary32-refined; 128 3D anisotropic boxes, bfloat16-stored correction),
+each batched solve against a loop of single-problem binary64 solves.
 --copy-probe-mib runs one plain device copy of known size first (a reference
 dispatch for hardware byte counters).
 """
@@ -45,6 +50,8 @@ def parse():
     ap.add_argument("--max-cycles", type=int, default=50)
     ap.add_argument("--plan", type=str, default="", help="kind:rows:T:occ kernel plan override")
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 3D and batched comparison legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target length of the CPU oracle sample (0 = skip)")
     return ap.parse_args()
@@ -75,6 +82,92 @@ def cpu_baseline(prob, target_s):
                   f"{out['sweeps']} sweeps, residual after each cycle) of the same solve, "
                   f"{dt:.1f} s",
     }
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def extra_c3():
+    """3D variable-coefficient 256^3: plain binary64 vs binary32-refined, to 1e-10."""
+    import workloads
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.c3()
+    s = Solver(prob)
+    s.autotune(0)
+    s.autotune(1)
+    rec = {"workload": "3D -div(k grad u) = 1, 7-point, 256^3, k log-normal (sigma 1, "
+                       "correlation 8 cells, seed 0), relative residual 1e-10",
+           "plans": {"f64": list(s.get_plan(0)), "inner": list(s.get_plan(1))}}
+    for prec in ("f64", "f32"):
+        x = s.zeros()
+        s.solve(x, tol=1e-10, precision=prec, max_cycles=200)
+        x.zero_()
+        out, dt = _timed(lambda: s.solve(x, tol=1e-10, precision=prec, max_cycles=200))
+        rec[prec] = {"converged": out["converged"], "cycles": out["cycles"],
+                     "sweeps": out["sweeps"], "time_ms": round(dt * 1e3, 3),
+                     "GLUPS": round(out["sweeps"] * prob.npoints / dt / 1e9, 3),
+                     "final_rel_residual_f64": s.residual_norm(x) / out["r0"]}
+        print(f"# c3 {prec}: {dt * 1e3:.1f} ms {out['status']}", file=sys.stderr, flush=True)
+    if rec["f64"]["converged"] and rec["f32"]["converged"]:
+        rec["f32_refined_speedup_time_to_tol"] = round(rec["f64"]["time_ms"] / rec["f32"]["time_ms"], 3)
+    s.close()
+    return rec
+
+
+def extra_batch(which):
+    """Batched solve vs a sequential loop of single-problem binary64 solves."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2011_06636_amd.solver import BatchSolver, Solver
+    if which == "c4":
+        probs, prec, tol = workloads.c4(), "f32", 1e-10
+        desc = ("512 2D Poisson squares, sides log-uniform in [64, 1024] (seed 1000+i), "
+                "b ~ U(-1,1), relative residual 1e-10; batch: binary32-refined")
+    else:
+        probs, prec, tol = workloads.c5(), "bf16", 1e-8
+        desc = ("128 3D anisotropic boxes, sides uniform in [32, 128], couplings (1, a, b), "
+                "a, b log-uniform in [0.01, 1] (seed 2000+i), b ~ U(-1,1), relative residual "
+                "1e-8; batch: bfloat16-stored correction, binary32 arithmetic")
+    npts = sum(p.npoints for p in probs)
+    bs = BatchSolver(probs)
+    tune_us = bs.autotune(prec, sweeps=48)
+    bs.solve(tol=tol, precision=prec, max_cycles=300)
+    out, dt_b = _timed(lambda: bs.solve(tol=tol, precision=prec, max_cycles=300))
+    xb = out["xs"]
+    conv_b = sum(i["converged"] for i in out["instances"])
+    sweeps_b = sum(i["sweeps"] * p.npoints for i, p in zip(out["instances"], probs))
+    plan = list(bs.get_plan())
+    bs.close()
+    print(f"# {which} batch {prec}: {dt_b * 1e3:.1f} ms, {conv_b}/{len(probs)}", file=sys.stderr,
+          flush=True)
+    t_seq, conv_s, errs = 0.0, 0, []
+    for k, p in enumerate(probs):
+        s = Solver(p)
+        x = s.zeros()
+        if k == 0:
+            s.solve(x, tol=tol, max_cycles=300)
+            x.zero_()
+        o, dt = _timed(lambda: s.solve(x, tol=tol, max_cycles=300))
+        t_seq += dt
+        conv_s += o["converged"]
+        errs.append(float(torch.linalg.norm(xb[k] - x) / torch.linalg.norm(x)))
+        s.close()
+    print(f"# {which} sequential f64: {t_seq * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": desc, "instances": len(probs), "points": npts,
+            "batched": {"precision": prec, "time_ms": round(dt_b * 1e3, 3), "converged": conv_b,
+                        "GLUPS": round(sweeps_b / dt_b / 1e9, 3), "plan": plan,
+                        "autotune_us_per_sweep": round(tune_us, 3)},
+            "sequential_f64": {"time_ms": round(t_seq * 1e3, 3), "converged": conv_s},
+            "batched_speedup_time_to_tol": round(t_seq / dt_b, 3),
+            "rel_error_vs_f64": {"max": max(errs), "median": float(np.median(errs))}}
 
 
 def run_leg(s, x, kw, steps, warmup, label):
@@ -193,9 +286,13 @@ def main():
                      "bytes_per_launch": alg_bytes,
                      "effective_GBps_per_sweep": round(24.0 * glups, 1)},
     }
+    s.close()
+    del x
+    if not args.no_extras:
+        rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
+                         "c5_batch_3d": extra_batch("c5")}
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
-    s.close()
     print(json.dumps(rec), flush=True)
 
 
