@@ -171,6 +171,14 @@ srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_
                         int32_t sweeps_per_launch, int32_t waves_per_simd);
 srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,
                         int32_t *sweeps_per_launch, int32_t *waves_per_simd);
+/* Small grids (at most 4000 points): with resident mode on (the default
+ * when the grid fits), a binary64 srj_solve runs entirely inside one
+ * workgroup of one kernel launch: sweeps in LDS, the residual norm, Algorithm
+ * 1 and the stop test on the device, no host round trip per cycle.  Iterates
+ * are bit-identical to the multi-kernel path; norms may differ in the last
+ * bits (summation order).  SRJ_ERR_UNSUPPORTED to enable it on a larger grid. */
+srj_status srj_set_resident(srj_ctx *ctx, int32_t enable);
+
 /* Lists the fused variants for `which` as 4 int32 each (kind, tile_rows, most
  * sweeps per launch, waves_per_simd): writes up to cap of them to out (host)
  * and their number to *count. */

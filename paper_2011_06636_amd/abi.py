@@ -32,7 +32,7 @@ MAX_M = 2362
 EXPORTS = [
     "srj_default_opts", "srj_scheme", "srj_setup", "srj_run_cycle", "srj_residual_norm",
     "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_plan_variants",
-    "srj_autotune",
+    "srj_autotune", "srj_set_resident",
     "srj_set_profiling",
     "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan", "srj_batch_get_plan",
     "srj_batch_autotune",
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
         "srj_get_plan": (i32, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
         "srj_plan_variants": (i32, [i32, P(i32), i32, P(i32)]),
         "srj_autotune": (i32, [vp, i32, i32, i32, P(f64)]),
+        "srj_set_resident": (i32, [vp, i32]),
         "srj_set_profiling": (i32, [vp, i32]),
         "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
@@ -192,6 +193,10 @@ def srj_autotune(ctx, which: int = 0, sweeps: int = 48, use_cache: bool = True) 
     check(load().srj_autotune(ctx, which, sweeps, 1 if use_cache else 0, ctypes.byref(us)),
           "srj_autotune")
     return us.value
+
+
+def srj_set_resident(ctx, enable: bool) -> int:
+    return load().srj_set_resident(ctx, 1 if enable else 0)
 
 
 def srj_set_profiling(ctx, enable: bool) -> None:

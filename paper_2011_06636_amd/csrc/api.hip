@@ -303,6 +303,7 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     }
     c->plan = default_plan(P);
     c->plan_inner = default_inner_plan(P);
+    c->resident = resident_fits(P);
     *out = c;
     return SRJ_OK;
 }
@@ -339,6 +340,15 @@ srj_status srj_get_plan(srj_ctx *c, int32_t which, int32_t *kind, int32_t *tile_
     *tile_rows = pl.by;
     *sweeps_per_launch = pl.T;
     *waves_per_simd = pl.occ;
+    return SRJ_OK;
+}
+
+srj_status srj_set_resident(srj_ctx *c, int32_t enable)
+{
+    if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
+    if (enable && !resident_fits(c->P))
+        return fail(SRJ_ERR_UNSUPPORTED, "grid too large for a one-workgroup solve");
+    c->resident = enable != 0;
     return SRJ_OK;
 }
 
@@ -401,6 +411,7 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     memset(res, 0, sizeof(*res));
     res->min_margin = INFINITY;
     if (o->precision != SRJ_PREC_F64) return refine_solve(c, x, o, res, levels_out, norms_out);
+    if (c->resident && resident_fits(c->P)) return resident_solve(c, x, o, res, levels_out, norms_out);
 
     double *cur = x, *nxt = c->ws;
     double norm0 = 0.0;

@@ -120,6 +120,7 @@ struct srj_ctx {
     std::vector<int32_t> offsets;  // level -> first factor in the tables
     srj::ReduceScratch rs;
     srj::SweepPlan plan;        // binary64 sweeps
+    bool resident = false;      // binary64 solves of small grids run in one workgroup
     srj::SweepPlan plan_inner;  // inner sweeps of the refinement modes
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     // Profiling: HIP events around the sweep launches of each cycle.
@@ -142,6 +143,11 @@ void refine_free(srj_ctx *ctx);
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan);
 srj_status time_inner_plan(srj_ctx *c, const SweepPlan &plan, int sweeps, const float *w_dev,
                            float *ms);
+// Whole binary64 solve of a small grid in one workgroup (resident.hip).
+constexpr int64_t kResidentMax = 4000;
+bool resident_fits(const DevProblem &P);
+srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                          int32_t *levels_out, double *norms_out);
 // Autotuner cache (tune.hip): key -> plan and time per sweep.
 std::string tune_key(const char *what, int which, int ndim, const int64_t n[3], bool faces,
                      bool diag);

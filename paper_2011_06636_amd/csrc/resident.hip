@@ -1,0 +1,283 @@
+// Whole solve of a small problem inside one workgroup (one launch).
+//
+// For grids of at most kResidentMax points the iterate lives in LDS (two
+// ping-pong copies) and one workgroup (one thread per point up to 1024
+// threads, then up to four points per thread) runs every cycle of the
+// solve: the sweeps of the cycle's scheme (Islam & Wang, arXiv 2011.06636,
+// section 2, Eq. 3 and Eq. 7, Eq. (17) factors in the library's execution
+// order), the L2 residual norm after the cycle (a fixed-order block
+// reduction), the next level from Algorithm 1 (section 3) and the stopping
+// test — with no host round trip per cycle.  Every thread takes the same
+// decisions from the same broadcast norm.  The per-point arithmetic is the
+// binary64 expression of the other kernels, so iterates are bit-identical;
+// the norms differ from the multi-kernel path only in summation order.
+#include <math.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace srj {
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kPPT = 4;  // points per thread
+
+struct ResidentOut {
+    int32_t status, converged, cycles, final_level;
+    int64_t sweeps;
+    double r0, r_final, min_margin;
+};
+
+struct ResidentArgs {
+    int32_t rule, fixed_level, max_level, max_cycles, start_level, tol_mode;
+    int64_t max_sweeps;
+    double tol, r0_given;
+};
+
+__device__ __forceinline__ double row_s(const DevProblem &P, const double *u, int64_t p,
+                                        int64_t i0, int64_t i1, int64_t i2)
+{
+    const int64_t s1 = P.n0, s2 = P.n0 * P.n1;
+    double s = (P.diag ? P.diag[p] : P.dconst) * u[p];
+    if (i0 > 0) s = s - (P.face[0] ? P.face[0][p - 1] : P.c[0]) * u[p - 1];
+    if (i0 < P.n0 - 1) s = s - (P.face[0] ? P.face[0][p] : P.c[0]) * u[p + 1];
+    if (P.ndim >= 2) {
+        if (i1 > 0) s = s - (P.face[1] ? P.face[1][p - s1] : P.c[1]) * u[p - s1];
+        if (i1 < P.n1 - 1) s = s - (P.face[1] ? P.face[1][p] : P.c[1]) * u[p + s1];
+    }
+    if (P.ndim >= 3) {
+        if (i2 > 0) s = s - (P.face[2] ? P.face[2][p - s2] : P.c[2]) * u[p - s2];
+        if (i2 < P.n2 - 1) s = s - (P.face[2] ? P.face[2][p] : P.c[2]) * u[p + s2];
+    }
+    return s;
+}
+
+// Fixed-order sum over the workgroup, broadcast to every thread.
+__device__ double group_sum(double v, double *red)
+{
+    v = wave_sum64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const int nw = blockDim.x / 64;
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int i = 1; i < nw; ++i) t += red[i];
+        red[kThreads / 64] = t;
+    }
+    __syncthreads();
+    return red[kThreads / 64];
+}
+
+__global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__restrict__ x,
+                                                       const double *__restrict__ omega,
+                                                       const int32_t *__restrict__ offsets,
+                                                       const int32_t *__restrict__ levelM,
+                                                       ResidentArgs a, int32_t *__restrict__ levels_hist,
+                                                       double *__restrict__ norms_hist,
+                                                       ResidentOut *__restrict__ out)
+{
+    extern __shared__ double lds[];
+    const int64_t N = P.n0 * P.n1 * P.n2;
+    double *cur = lds, *nxt = lds + N, *red = lds + 2 * N;
+    // this thread's points: p = threadIdx.x + k * blockDim.x
+    int64_t pi[kPPT], c0[kPPT], c1[kPPT], c2[kPPT];
+    double bv[kPPT], dinv[kPPT];
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k) {
+        const int64_t p = threadIdx.x + (int64_t)k * blockDim.x;
+        pi[k] = p < N ? p : -1;
+        c0[k] = p % P.n0;
+        c1[k] = (p / P.n0) % P.n1;
+        c2[k] = p / (P.n0 * P.n1);
+        bv[k] = p < N ? P.b[p] : 0.0;
+        dinv[k] = p < N ? (P.diag ? P.dinv[p] : P.dinvconst) : 0.0;
+        if (p < N) cur[p] = x[p];
+    }
+    __syncthreads();
+    auto norm_of = [&](const double *u) -> double {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            if (pi[k] < 0) continue;
+            const double r = bv[k] - row_s(P, u, pi[k], c0[k], c1[k], c2[k]);
+            acc += r * r;
+        }
+        return sqrt(group_sum(acc, red));
+    };
+    const int hist = a.max_cycles + 1;
+    const double norm0 = norm_of(cur);
+    const double r0 = a.r0_given > 0.0 ? a.r0_given : norm0;
+    const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
+    if (threadIdx.x == 0) norms_hist[0] = norm0;
+    int status = SRJ_ERR_NOT_CONVERGED, cycles = 0, level = a.start_level, last_level = a.start_level;
+    int64_t sweeps = 0;
+    double prev = norm0, last = norm0, margin = INFINITY;
+    if (!isfinite(norm0)) {
+        status = SRJ_ERR_NONFINITE;
+    } else if (norm0 == 0.0 || norm0 < target) {
+        status = SRJ_OK;
+    } else {
+        for (int cycle = 0; cycle < a.max_cycles; ++cycle) {
+            const int lv = a.rule == SRJ_RULE_FIXED ? a.fixed_level : level;
+            const int M = levelM[lv];
+            if (sweeps + M > a.max_sweeps) break;
+            const double *w = omega + offsets[lv];
+            double wnext = w[0];
+            for (int j = 0; j < M; ++j) {
+                const double wj = wnext;
+                if (j + 1 < M) wnext = w[j + 1];  // in flight during this sweep
+#pragma unroll
+                for (int k = 0; k < kPPT; ++k) {
+                    if (pi[k] < 0) continue;
+                    const double s = row_s(P, cur, pi[k], c0[k], c1[k], c2[k]);
+                    const double r = bv[k] - s;
+                    const double t = dinv[k] * r;
+                    nxt[pi[k]] = cur[pi[k]] + wj * t;
+                }
+                __syncthreads();
+                double *tmp = cur;
+                cur = nxt;
+                nxt = tmp;
+            }
+            sweeps += M;
+            const double norm = norm_of(cur);
+            cycles = cycle + 1;
+            last = norm;
+            last_level = lv;
+            if (threadIdx.x == 0) {
+                levels_hist[cycle] = lv;
+                norms_hist[cycle + 1] = norm;
+            }
+            if (!isfinite(norm)) {
+                status = SRJ_ERR_NONFINITE;
+                break;
+            }
+            if (norm < target) {
+                status = SRJ_OK;
+                break;
+            }
+            const double ratio = norm / prev;
+            prev = norm;
+            int nl = level;
+            if (a.rule == SRJ_RULE_HEURISTIC) {
+                margin = fmin(margin, fmin(fabs(ratio - 0.2), fabs(ratio - 0.4)));
+                if (ratio > 0.4)
+                    nl = level + 1;
+                else if (ratio < 0.4 && ratio > 0.2)
+                    nl = level - 1;
+            } else if (a.rule == SRJ_RULE_INCREASING) {
+                nl = level + 1;
+            }
+            level = nl < 0 ? 0 : (nl > a.max_level ? a.max_level : nl);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k)
+        if (pi[k] >= 0) x[pi[k]] = cur[pi[k]];
+    if (threadIdx.x == 0) {
+        out->status = status;
+        out->converged = status == SRJ_OK;
+        out->cycles = cycles;
+        out->final_level = cycles > 0 ? last_level : a.start_level;
+        out->sweeps = sweeps;
+        out->r0 = r0;
+        out->r_final = last;
+        out->min_margin = margin;
+    }
+}
+
+}  // namespace
+
+bool resident_fits(const DevProblem &P) { return P.n0 * P.n1 * P.n2 <= kResidentMax; }
+
+srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                          int32_t *levels_out, double *norms_out)
+{
+    ResidentArgs a{};
+    a.rule = o->rule;
+    a.fixed_level = o->fixed_level;
+    a.max_level = o->max_level;
+    a.max_cycles = o->max_cycles;
+    a.start_level = o->start_level;
+    a.tol_mode = o->tol_mode;
+    a.max_sweeps = o->max_sweeps;
+    a.tol = o->tol;
+    a.r0_given = o->r0;
+    const int64_t N = c->npoints;
+    int32_t *lh = nullptr;
+    double *nh = nullptr;
+    ResidentOut *dout = nullptr;
+    int32_t *lm = nullptr;
+    std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = level_m(l);
+    srj_status st = SRJ_OK;
+    if (hipMalloc(&lh, sizeof(int32_t) * (size_t)o->max_cycles) != hipSuccess ||
+        hipMalloc(&nh, sizeof(double) * ((size_t)o->max_cycles + 1)) != hipSuccess ||
+        hipMalloc(&dout, sizeof(ResidentOut)) != hipSuccess ||
+        hipMalloc(&lm, sizeof(int32_t) * SRJ_NUM_LEVELS) != hipSuccess)
+        st = fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
+    int32_t *offs = nullptr;
+    if (st == SRJ_OK && hipMalloc(&offs, sizeof(int32_t) * c->offsets.size()) != hipSuccess)
+        st = fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
+    ResidentOut h{};
+    if (st == SRJ_OK) {
+        hipError_t e = hipMemcpyAsync(lm, lmh.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(offs, c->offsets.data(), sizeof(int32_t) * c->offsets.size(),
+                               hipMemcpyHostToDevice, c->stream);
+        const size_t shmem = sizeof(double) * (size_t)(2 * N + kThreads / 64 + 1);
+        if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
+        if (e == hipSuccess) {
+            // one point per thread up to 1024 points (latency hiding across
+            // waves), then up to kPPT points per thread
+            const int threads = (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
+            hipLaunchKernelGGL(k_resident, dim3(1), dim3(threads), shmem, c->stream, c->P, x,
+                               c->omega_dev, offs, lm, a, lh, nh, dout);
+            e = hipGetLastError();
+        }
+        if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && levels_out && o->max_cycles > 0)
+            e = hipMemcpy(levels_out, lh, sizeof(int32_t) * (size_t)o->max_cycles,
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess && norms_out)
+            e = hipMemcpy(norms_out, nh, sizeof(double) * ((size_t)h.cycles + 1),
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess && c->profiling) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+            c->prof_ms += ms;
+            c->prof_launches += 1;
+            c->prof_sweeps += h.sweeps;
+        }
+        if (e != hipSuccess) st = fail(SRJ_ERR_HIP, std::string("resident solve: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(lh);
+    (void)hipFree(nh);
+    (void)hipFree(dout);
+    (void)hipFree(lm);
+    (void)hipFree(offs);
+    if (st != SRJ_OK) return st;
+    res->converged = h.converged;
+    res->cycles = h.cycles;
+    res->final_level = h.final_level;
+    res->sweeps = h.sweeps;
+    res->r0 = h.r0;
+    res->r_final = h.r_final;
+    res->min_margin = h.min_margin;
+    if (h.status == SRJ_ERR_NONFINITE) return fail(SRJ_ERR_NONFINITE, "residual norm is not finite");
+    if (h.status == SRJ_ERR_NOT_CONVERGED) return fail(SRJ_ERR_NOT_CONVERGED, "cycle or sweep cap reached");
+    return SRJ_OK;
+}
+
+}  // namespace srj

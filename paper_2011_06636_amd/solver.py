@@ -86,6 +86,10 @@ class Solver:
     def get_plan(self, which: int = 0):
         return abi.srj_get_plan(self.ctx, which)
 
+    def set_resident(self, enable: bool) -> int:
+        """Whole binary64 solve of a small grid in one workgroup (default when it fits)."""
+        return abi.srj_set_resident(self.ctx, enable)
+
     def autotune(self, which: int = 0, sweeps: int = 48, use_cache: bool = True) -> float:
         """Pick the fastest plan for `which` by timing; returns its us per sweep."""
         return abi.srj_autotune(self.ctx, which, sweeps, use_cache)

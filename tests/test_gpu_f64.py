@@ -238,3 +238,42 @@ def test_c3_full_size_first_cycles(torch_cuda, orc):
     assert _close(got, x_ref), np.max(np.abs(got - x_ref))
     assert abs(nrm - orc.residual_norm(prob, x_ref)) <= 1e-12 * nrm
     s.close()
+
+
+RESIDENT_CASES = [
+    ("c1", lambda: workloads.c1(), dict(tol=1e-10)),
+    ("n100_abs", lambda: workloads.poisson_1d(100), dict(tol=1e-7, tol_mode="absolute")),
+    ("n100_increasing", lambda: workloads.poisson_1d(100), dict(tol=1e-7, tol_mode="absolute", rule="increasing")),
+    ("2d_40x37", lambda: workloads.poisson([40, 37], b=np.random.default_rng(11).uniform(-1, 1, (1, 37, 40))), dict(tol=1e-10)),
+    ("3d_15x16x15", lambda: workloads.c5_instance(9, lo=15, hi=16), dict(tol=1e-8)),
+    ("3d_varcoef_15", lambda: workloads.variable_coefficient(15, seed=8, corr_len=3.0), dict(tol=1e-10)),
+    ("cap", lambda: workloads.c1(), dict(tol=1e-10, max_cycles=3)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RESIDENT_CASES)))
+def test_resident_solve(torch_cuda, orc, case):
+    # one-workgroup solve: same levels and bits as the multi-kernel path and the oracle
+    name, make, kw = RESIDENT_CASES[case]
+    prob = make()
+    s = _solver(prob)
+    assert s.set_resident(True) == 0
+    a = s.solve(**kw)
+    assert s.set_resident(False) == 0
+    b = s.solve(**kw)
+    ref = orc.solve(prob, **kw)
+    assert a["status"] == b["status"] == ref["status"], name
+    np.testing.assert_array_equal(a["levels"], ref["levels"])
+    np.testing.assert_array_equal(b["levels"], ref["levels"])
+    assert a["sweeps"] == ref["sweeps"] and a["cycles"] == ref["cycles"]
+    assert np.array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+    np.testing.assert_allclose(a["norms"], ref["norms"], rtol=1e-12, atol=0)
+    assert _close(a["x"].cpu().numpy(), ref["x"])
+    s.close()
+
+
+def test_resident_rejects_large(torch_cuda):
+    from paper_2011_06636_amd import abi
+    s = _solver(workloads.poisson([80, 80]))
+    assert s.set_resident(True) == abi.SRJ_ERR_UNSUPPORTED
+    s.close()
