@@ -165,7 +165,9 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * 64 columns x tile_rows rows fusing up to sweeps_per_launch sweeps per launch
  * (right-hand side in registers); kind 2 (binary64 only): the same with the
  * right-hand side in LDS; kind 3: 3D, one sweep per launch, each thread
- * streaming tile_rows planes along axis 2 (any coefficients).  waves_per_simd is the register budget the kernel
+ * streaming tile_rows planes along axis 2 (any coefficients); kind 5: 2D
+ * constant-coefficient wavefront strips of 64 columns x tile_rows output rows
+ * that push every loaded row through up to sweeps_per_launch sweeps.  waves_per_simd is the register budget the kernel
  * was compiled for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);

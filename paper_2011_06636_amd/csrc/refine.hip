@@ -26,6 +26,7 @@
 #include "storage.h"
 #include "tile2d.h"
 #include "stream3d.h"
+#include "wave2d.h"
 
 #pragma clang fp contract(off)
 
@@ -159,6 +160,13 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     const TT *dd = static_cast<const TT *>(d);
     TT *oo = static_cast<TT *>(dout);
     const TT *rr = static_cast<const TT *>(rhat);
+    if (plan.kind == 5) {
+#define SRJ_GO(OH, TM) \
+    if (plan.by == OH && plan.T <= TM) return launch_wave2d<St, OH, TM>(T, Q.n0, Q.n1, dd, oo, rr, w_dev, k2, s);
+        SRJ_WAVE_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 3) {
         const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
                                 {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
@@ -222,6 +230,14 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 5) {
+        if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.occ != 1 || plan.T < 1)
+            return false;
+#define SRJ_CHK(OH, TM) if (plan.by == OH && plan.T <= TM) return true;
+        SRJ_WAVE_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 3) {
         if (P.ndim != 3 || plan.T != 1 || plan.occ != 1) return false;
 #define SRJ_CHK(Z) if (plan.by == Z) return true;
@@ -241,6 +257,16 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 int inner_plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST5(OH, TM)              \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 5;            \
+        out[4 * n + 1] = OH;           \
+        out[4 * n + 2] = TM;           \
+        out[4 * n + 3] = 1;            \
+    }                                  \
+    ++n;
+    SRJ_WAVE_VARIANTS(SRJ_LIST5)
+#undef SRJ_LIST5
 #define SRJ_LIST3(Z)                   \
     if (n < cap) {                     \
         out[4 * n + 0] = 3;            \

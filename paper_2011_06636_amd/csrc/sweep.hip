@@ -11,6 +11,7 @@
 #include "storage.h"
 #include "tile2d.h"
 #include "stream3d.h"
+#include "wave2d.h"
 
 #pragma clang fp contract(off)
 
@@ -99,6 +100,16 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 int plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST5(OH, TM)              \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 5;            \
+        out[4 * n + 1] = OH;           \
+        out[4 * n + 2] = TM;           \
+        out[4 * n + 3] = 1;            \
+    }                                  \
+    ++n;
+    SRJ_WAVE_VARIANTS(SRJ_LIST5)
+#undef SRJ_LIST5
 #define SRJ_LIST3(Z)                   \
     if (n < cap) {                     \
         out[4 * n + 0] = 3;            \
@@ -123,6 +134,14 @@ int plan_variants(int32_t *out, int cap)
 
 bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 5) {
+        if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.occ != 1 || plan.T < 1)
+            return false;
+#define SRJ_CHK(OH, TM) if (plan.by == OH && plan.T <= TM) return true;
+        SRJ_WAVE_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 3) {
         if (P.ndim != 3 || plan.T != 1 || plan.occ != 1) return false;
 #define SRJ_CHK(Z) if (plan.by == Z) return true;
@@ -143,6 +162,14 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s)
 {
+    if (plan.kind == 5) {
+        const Coef2D<double> kw{P.dconst, P.dinvconst, P.c[0], P.c[1]};
+#define SRJ_GO(OH, TM) \
+    if (plan.by == OH && plan.T <= TM) return launch_wave2d<StF64, OH, TM>(T, P.n0, P.n1, x, xo, P.b, w_dev, kw, s);
+        SRJ_WAVE_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 3) {
         const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
                                  {P.face[0], P.face[1], P.face[2]}, P.dconst, P.dinvconst,
