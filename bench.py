@@ -128,26 +128,32 @@ def extra_batch(which):
     import workloads
     from paper_2011_06636_amd.solver import BatchSolver, Solver
     if which == "c4":
-        probs, prec, tol = workloads.c4(), "f32", 1e-10
+        probs, precs, tol = workloads.c4(), ("f32",), 1e-10
         desc = ("512 2D Poisson squares, sides log-uniform in [64, 1024] (seed 1000+i), "
-                "b ~ U(-1,1), relative residual 1e-10; batch: binary32-refined")
+                "b ~ U(-1,1), relative residual 1e-10")
     else:
-        probs, prec, tol = workloads.c5(), "bf16", 1e-8
+        probs, precs, tol = workloads.c5(), ("f64", "bf16"), 1e-8
         desc = ("128 3D anisotropic boxes, sides uniform in [32, 128], couplings (1, a, b), "
                 "a, b log-uniform in [0.01, 1] (seed 2000+i), b ~ U(-1,1), relative residual "
-                "1e-8; batch: bfloat16-stored correction, binary32 arithmetic")
+                "1e-8")
     npts = sum(p.npoints for p in probs)
     bs = BatchSolver(probs)
-    tune_us = bs.autotune(prec, sweeps=48)
-    bs.solve(tol=tol, precision=prec, max_cycles=300)
-    out, dt_b = _timed(lambda: bs.solve(tol=tol, precision=prec, max_cycles=300))
-    xb = out["xs"]
-    conv_b = sum(i["converged"] for i in out["instances"])
-    sweeps_b = sum(i["sweeps"] * p.npoints for i, p in zip(out["instances"], probs))
-    plan = list(bs.get_plan())
+    batched, best, xb = [], None, None
+    for prec in precs:
+        tune_us = bs.autotune(prec, sweeps=48)
+        bs.solve(tol=tol, precision=prec, max_cycles=300)
+        out, dt_b = _timed(lambda: bs.solve(tol=tol, precision=prec, max_cycles=300))
+        conv_b = sum(i["converged"] for i in out["instances"])
+        sweeps_b = sum(i["sweeps"] * p.npoints for i, p in zip(out["instances"], probs))
+        rec = {"precision": prec, "time_ms": round(dt_b * 1e3, 3), "converged": conv_b,
+               "GLUPS": round(sweeps_b / dt_b / 1e9, 3), "plan": list(bs.get_plan()),
+               "autotune_us_per_sweep": round(tune_us, 3)}
+        batched.append(rec)
+        if best is None or dt_b < best[0]:
+            best, xb = (dt_b, prec), [x.clone() for x in out["xs"]]
+        print(f"# {which} batch {prec}: {dt_b * 1e3:.1f} ms, {conv_b}/{len(probs)}",
+              file=sys.stderr, flush=True)
     bs.close()
-    print(f"# {which} batch {prec}: {dt_b * 1e3:.1f} ms, {conv_b}/{len(probs)}", file=sys.stderr,
-          flush=True)
     t_seq, conv_s, errs = 0.0, 0, []
     for k, p in enumerate(probs):
         s = Solver(p)
@@ -161,13 +167,12 @@ def extra_batch(which):
         errs.append(float(torch.linalg.norm(xb[k] - x) / torch.linalg.norm(x)))
         s.close()
     print(f"# {which} sequential f64: {t_seq * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    return {"workload": desc, "instances": len(probs), "points": npts,
-            "batched": {"precision": prec, "time_ms": round(dt_b * 1e3, 3), "converged": conv_b,
-                        "GLUPS": round(sweeps_b / dt_b / 1e9, 3), "plan": plan,
-                        "autotune_us_per_sweep": round(tune_us, 3)},
+    return {"workload": desc, "instances": len(probs), "points": npts, "batched": batched,
             "sequential_f64": {"time_ms": round(t_seq * 1e3, 3), "converged": conv_s},
-            "batched_speedup_time_to_tol": round(t_seq / dt_b, 3),
-            "rel_error_vs_f64": {"max": max(errs), "median": float(np.median(errs))}}
+            "fastest_batched": best[1],
+            "batched_speedup_time_to_tol": round(t_seq / best[0], 3),
+            "fastest_batched_rel_error_vs_sequential_f64": {"max": max(errs),
+                                                            "median": float(np.median(errs))}}
 
 
 def run_leg(s, x, kw, steps, warmup, label):

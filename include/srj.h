@@ -167,7 +167,11 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * right-hand side in LDS; kind 3: 3D, one sweep per launch, each thread
  * streaming tile_rows planes along axis 2 (any coefficients); kind 5: 2D
  * constant-coefficient wavefront strips of 64 columns x tile_rows output rows
- * that push every loaded row through up to sweeps_per_launch sweeps.  waves_per_simd is the register budget the kernel
+ * that push every loaded row through up to sweeps_per_launch sweeps; kind 6:
+ * 3D, one sweep per launch, register plane tiles of 64 columns x tile_rows
+ * rows streamed over waves_per_simd planes along axis 2 (for kind 6 that
+ * field is the plane-chunk length; all faces and a diagonal array, or all
+ * constant).  Otherwise waves_per_simd is the register budget the kernel
  * was compiled for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);

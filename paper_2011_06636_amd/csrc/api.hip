@@ -14,6 +14,7 @@
 #include <string>
 
 #include "internal.h"
+#include "plane3d.h"
 
 namespace srj {
 
@@ -79,8 +80,14 @@ SweepPlan default_inner_plan(const DevProblem &P)
 {
     SweepPlan pl;
     if (P.ndim == 3) {
-        pl.kind = 3;
-        pl.by = 16;
+        if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
+            pl.kind = 6;  // plane tiles: 4 rows, 8 planes per chunk
+            pl.by = 4;
+            pl.occ = 8;
+        } else {
+            pl.kind = 3;
+            pl.by = 16;
+        }
         return pl;
     }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
@@ -98,8 +105,14 @@ SweepPlan default_plan(const DevProblem &P)
     pl.kind = 0;
     pl.T = 1;
     if (P.ndim == 3) {
-        pl.kind = 3;
-        pl.by = 16;
+        if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
+            pl.kind = 6;
+            pl.by = 4;
+            pl.occ = 8;
+        } else {
+            pl.kind = 3;
+            pl.by = 16;
+        }
         return pl;
     }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {

@@ -8,7 +8,8 @@
 // scale.  One step is
 //   1. sweeps: every active instance advances its cycle by T sweeps (2D and
 //      1D instances: register tiles, T <= tile halo; 3D instances: one
-//      z-streamed sweep); waves loop over (instance, tile) work items;
+//      sweep of register plane tiles streamed along axis 2); waves loop over
+//      (instance, tile) work items;
 //   2. outer pass over the points of the instances whose cycle just ended:
 //      binary64 residual (refinement: after x += d / s, with the scaled cast
 //      of the residual for the next cycle and the next correction zeroed),
@@ -29,6 +30,7 @@
 #include "storage.h"
 #include "stream3d.h"
 #include "tile2d.h"
+#include "plane3d.h"
 
 #pragma clang fp contract(off)
 
@@ -37,7 +39,8 @@ namespace srj {
 namespace {
 
 constexpr int kOuterPts = 2048;  // points per outer-pass work item (256 threads x 8)
-constexpr int kZC = 16;          // planes per 3D sweep work item
+constexpr int kPH = 4;           // rows per 3D plane tile
+constexpr int kZC = 8;           // planes per 3D sweep work item
 
 struct BDesc {
     int32_t ndim;
@@ -45,7 +48,7 @@ struct BDesc {
     int64_t n0, n1, n2, npts, off;
     double c[3], D, Dinv, sqrtN;
     float c32[3], D32, Dinv32, pad1;
-    int32_t tiles_x, gx3, gy3, pad2;     // 2D tile columns; 3D block grid (x, y)
+    int32_t tiles_x, gx3, gy3, pad2;     // 2D tile columns; 3D plane-tile grid (x, y)
     int32_t oitem_first, oitem_count;    // outer-pass work items
 };
 
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void k_bsweep2d(const BDesc *__restrict__ desc
     }
 }
 
-// 1'. sweeps, 3D instances: one 64 x 4 block per (instance, block) item
+// 1'. sweeps, 3D instances: one wave per (instance, plane tile) item
 template <class V>
 __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc,
                                                   const BState *__restrict__ st,
@@ -141,19 +144,18 @@ __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc
                                                   const typename V::T *__restrict__ rhs, BParams prm)
 {
     using A = typename V::A;
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int nwaves = gridDim.x * 4;
+    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < nitems; item += nwaves) {
         const int2 it = items[item];
         const BState s = st[it.x];
         if (s.done) continue;
         const BDesc &d = desc[it.x];
-        const int bx = it.y % d.gx3, by = (it.y / d.gx3) % d.gy3, bz = it.y / (d.gx3 * d.gy3);
-        const int64_t i0 = (int64_t)bx * 64 + threadIdx.x, i1 = (int64_t)by * 4 + threadIdx.y;
-        if (i0 >= d.n0 || i1 >= d.n1) continue;
+        const int tx = it.y % d.gx3, ty = (it.y / d.gx3) % d.gy3, tz = it.y / (d.gx3 * d.gy3);
         const A w = Sel<A>::omega(prm)[prm.offsets[s.level] + s.pos];
         const typename V::T *uin = (s.pu ? ub : ua) + d.off;
         typename V::T *uout = (s.pu ? ua : ub) + d.off;
-        stream3d_run<V, kZC>(Sel<A>::sten(d), uin, uout, rhs + d.off, w, i0, i1,
-                             (int64_t)bz * kZC);
+        plane3d_run<V, kPH, kZC, false, false>(Sel<A>::sten(d), uin, uout, rhs + d.off, w, tx, ty,
+                                               tz, threadIdx.x & 63);
     }
 }
 
@@ -477,8 +479,8 @@ srj_status enqueue_step(srj_batch *B, const BParams &prm)
         SRJ_HIP_CHECK(launch_bsweep2d<V>(B, ua, ub, rhs, prm, grid));
     }
     if (!B->hitems3.empty()) {
-        const int grid = (int)std::min<int64_t>(B->hitems3.size(), (int64_t)cus * 8);
-        hipLaunchKernelGGL((k_bsweep3d<V>), dim3(grid), dim3(64, 4), 0, B->stream, B->desc,
+        const int grid = (int)std::min<int64_t>((B->hitems3.size() + 3) / 4, (int64_t)cus * 8);
+        hipLaunchKernelGGL((k_bsweep3d<V>), dim3(grid), dim3(256), 0, B->stream, B->desc,
                            B->state, B->items3, (int)B->hitems3.size(), (typename V::T *)ua,
                            (typename V::T *)ub, (const typename V::T *)rhs, prm);
         SRJ_HIP_CHECK(hipGetLastError());
@@ -890,8 +892,8 @@ srj_status srj_batch_set_plan(srj_batch *B, int32_t tile_rows, int32_t sweeps_pe
     for (int i = 0; i < B->count; ++i) {
         BDesc &d = B->hdesc[i];
         if (d.ndim == 3) {
-            d.gx3 = (int)((d.n0 + 63) / 64);
-            d.gy3 = (int)((d.n1 + 3) / 4);
+            d.gx3 = (int)((d.n0 + 61) / 62);
+            d.gy3 = (int)((d.n1 + kPH - 1) / kPH);
             const int gz = (int)((d.n2 + kZC - 1) / kZC);
             for (int k = 0; k < d.gx3 * d.gy3 * gz; ++k) B->hitems3.push_back({i, k});
         } else {

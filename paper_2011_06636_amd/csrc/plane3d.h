@@ -1,0 +1,155 @@
+// 3D relaxed Jacobi sweep: register plane tiles streamed along axis 2.
+//
+// One sweep (Islam & Wang, arXiv 2011.06636, section 2, Eq. 3 in residual
+// form) of a 7-point stencil with constant or per-face couplings and a
+// constant or per-point diagonal, in the fixed order
+//   s = D u - c0lo u_{-e0} - c0hi u_{+e0} - c1lo u_{-e1} - c1hi u_{+e1}
+//           - c2lo u_{-e2} - c2hi u_{+e2},   u' = u + w (Dinv (f - s)),
+// without fused multiply-add (bit-identical to the other kernels).  A ghost
+// neighbour is loaded as zero with a zero coupling, which leaves s unchanged.
+//
+// A wave owns 64 columns along axis 0 (lane = column; the outer lane on each
+// side is a halo, 62 columns are written) and H rows along axis 1 (in
+// registers), and walks ZC planes along axis 2.  It keeps the previous,
+// current and next plane of u in registers, plus the rows just above and
+// below its H rows; neighbours along axis 0 come from DPP wave shifts.  Each
+// value of u, f, D, 1/D and each coupling is loaded once per plane (rows and
+// lanes of the halo aside).  Value policy V as in tile2d.h; FACE selects
+// per-face couplings (all three axes) and DIAG a per-point diagonal.
+#pragma once
+
+#include "internal.h"
+#include "stream3d.h"
+#include "tile2d.h"
+
+#pragma clang fp contract(off)
+
+namespace srj {
+
+template <class V, int H, int ZC, bool FACE, bool DIAG>
+__device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
+                                            const typename V::T *__restrict__ x,
+                                            typename V::T *__restrict__ xo,
+                                            const typename V::T *__restrict__ b,
+                                            typename V::A w, int tx, int ty, int tz, int lane)
+{
+    using A = typename V::A;
+    const int64_t n0 = S.n0, n1 = S.n1, n2 = S.n2;
+    const int64_t s1 = n0, s2 = n0 * n1;
+    const int64_t gx = (int64_t)tx * 62 - 1 + lane;
+    const int64_t gy0 = (int64_t)ty * H;
+    const int64_t z0 = (int64_t)tz * ZC;
+    const int64_t z1 = z0 + ZC < n2 ? z0 + ZC : n2;
+    const bool col_in = gx >= 0 && gx < n0;
+    const int64_t colp = gx;  // column part of the flat index
+    auto row_ok = [&](int64_t gy) { return col_in && gy >= 0 && gy < n1; };
+    auto ldu = [&](int64_t z, int64_t gy) -> A {
+        return (z >= 0 && z < n2 && row_ok(gy)) ? V::load(x[colp + gy * s1 + z * s2]) : A(0);
+    };
+    auto ldc = [&](const A *arr, A cst, int64_t z, int64_t gy) -> A {  // coupling / D / 1/D
+        if (!(z >= 0 && z < n2 && row_ok(gy))) return A(0);
+        return arr ? arr[colp + gy * s1 + z * s2] : cst;
+    };
+    A um[H], uc[H], up[H];
+    A f2m[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        um[r] = ldu(z0 - 1, gy0 + r);
+        uc[r] = ldu(z0, gy0 + r);
+        f2m[r] = FACE ? ldc(S.face[2], S.c[2], z0 - 1, gy0 + r) : S.c[2];
+    }
+    for (int64_t z = z0; z < z1; ++z) {
+        A bz[H], f0[H], f1[H], f2c[H], dd[H], di[H];
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            const int64_t gy = gy0 + r;
+            up[r] = ldu(z + 1, gy);
+            bz[r] = row_ok(gy) ? V::load(b[colp + gy * s1 + z * s2]) : A(0);
+            f0[r] = FACE ? ldc(S.face[0], S.c[0], z, gy) : S.c[0];
+            f1[r] = FACE ? ldc(S.face[1], S.c[1], z, gy) : S.c[1];
+            f2c[r] = FACE ? ldc(S.face[2], S.c[2], z, gy) : S.c[2];
+            dd[r] = DIAG ? ldc(S.diag, S.dconst, z, gy) : S.dconst;
+            di[r] = DIAG ? ldc(S.dinv, S.dinvconst, z, gy) : S.dinvconst;
+        }
+        const A u_above = ldu(z, gy0 - 1);   // row gy0 - 1 of this plane
+        const A u_below = ldu(z, gy0 + H);   // row gy0 + H of this plane
+        const A f1_above = FACE ? ldc(S.face[1], S.c[1], z, gy0 - 1) : S.c[1];
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            const A xc = uc[r];
+            const A xl = dpp_prev(xc);
+            const A xh = dpp_next(xc);
+            const A cl0 = FACE ? dpp_prev(f0[r]) : S.c[0];
+            const A yu = r > 0 ? uc[r - 1] : u_above;
+            const A yd = r + 1 < H ? uc[r + 1] : u_below;
+            const A cl1 = r > 0 ? f1[r - 1] : f1_above;
+            A s = dd[r] * xc;
+            s = s - cl0 * xl;
+            s = s - f0[r] * xh;
+            s = s - cl1 * yu;
+            s = s - f1[r] * yd;
+            s = s - f2m[r] * um[r];
+            s = s - f2c[r] * up[r];
+            const A rr = bz[r] - s;
+            const A t = di[r] * rr;
+            const int64_t gy = gy0 + r;
+            if (lane >= 1 && lane < 63 && row_ok(gy))
+                xo[colp + gy * s1 + z * s2] = V::store(xc + w * t);
+        }
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+            um[r] = uc[r];
+            uc[r] = up[r];
+            f2m[r] = f2c[r];
+        }
+    }
+}
+
+template <class V, int H, int ZC, bool FACE, bool DIAG>
+__global__ __launch_bounds__(256) void k_plane3d(Stencil3<typename V::A> S,
+                                                 const typename V::T *__restrict__ x,
+                                                 typename V::T *__restrict__ xo,
+                                                 const typename V::T *__restrict__ b,
+                                                 const typename V::A *__restrict__ wp, int tiles_x,
+                                                 int tiles_y, int tiles_z)
+{
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
+    const int tx = item % tiles_x, ty = (item / tiles_x) % tiles_y, tz = item / (tiles_x * tiles_y);
+    plane3d_run<V, H, ZC, FACE, DIAG>(S, x, xo, b, wp[0], tx, ty, tz, threadIdx.x & 63);
+}
+
+template <class V, int H, int ZC>
+hipError_t launch_plane3d(const Stencil3<typename V::A> &S, const typename V::T *x,
+                          typename V::T *xo, const typename V::T *b, const typename V::A *w_dev,
+                          hipStream_t s)
+{
+    const int tx = (int)((S.n0 + 61) / 62), ty = (int)((S.n1 + H - 1) / H),
+              tz = (int)((S.n2 + ZC - 1) / ZC);
+    const int64_t items = (int64_t)tx * ty * tz;
+    const dim3 grid((unsigned)((items + 3) / 4));
+    const bool face = S.face[0] && S.face[1] && S.face[2];
+    const bool diag = S.diag != nullptr;
+    if (face && diag)
+        hipLaunchKernelGGL((k_plane3d<V, H, ZC, true, true>), grid, dim3(256), 0, s, S, x, xo, b, w_dev, tx, ty, tz);
+    else if (!face && !S.face[0] && !S.face[1] && !S.face[2] && !diag)
+        hipLaunchKernelGGL((k_plane3d<V, H, ZC, false, false>), grid, dim3(256), 0, s, S, x, xo, b, w_dev, tx, ty, tz);
+    else
+        return hipErrorInvalidValue;  // mixed coefficient kinds: use another plan
+    return hipGetLastError();
+}
+
+// Coefficient layouts the plane kernel takes: all faces and a per-point
+// diagonal, or constant couplings and diagonal.
+inline bool plane3d_fits(int ndim, const void *f0, const void *f1, const void *f2, const void *diag)
+{
+    if (ndim != 3) return false;
+    const bool all = f0 && f1 && f2 && diag;
+    const bool none = !f0 && !f1 && !f2 && !diag;
+    return all || none;
+}
+
+// (rows per tile, planes per chunk) of the plane plans (kind 6)
+#define SRJ_PLANE_VARIANTS(X) X(2, 16) X(4, 8) X(4, 16) X(4, 32) X(8, 16)
+
+}  // namespace srj

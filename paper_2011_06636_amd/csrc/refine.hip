@@ -27,6 +27,7 @@
 #include "tile2d.h"
 #include "stream3d.h"
 #include "wave2d.h"
+#include "plane3d.h"
 
 #pragma clang fp contract(off)
 
@@ -160,6 +161,16 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     const TT *dd = static_cast<const TT *>(d);
     TT *oo = static_cast<TT *>(dout);
     const TT *rr = static_cast<const TT *>(rhat);
+    if (plan.kind == 6) {
+        const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
+                                {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
+                                Q.diag, Q.dinv};
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d<St, HH, ZZ>(S, dd, oo, rr, w_dev, s);
+        SRJ_PLANE_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 5) {
 #define SRJ_GO(OH, TM) \
     if (plan.by == OH && plan.T <= TM) return launch_wave2d<St, OH, TM>(T, Q.n0, Q.n1, dd, oo, rr, w_dev, k2, s);
@@ -230,6 +241,14 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 6) {
+        if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_PLANE_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 5) {
         if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.occ != 1 || plan.T < 1)
             return false;
@@ -257,6 +276,16 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 int inner_plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST6(HH, ZZ)              \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 6;            \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 1;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_PLANE_VARIANTS(SRJ_LIST6)
+#undef SRJ_LIST6
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \

@@ -12,6 +12,7 @@
 #include "tile2d.h"
 #include "stream3d.h"
 #include "wave2d.h"
+#include "plane3d.h"
 
 #pragma clang fp contract(off)
 
@@ -100,6 +101,16 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 int plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST6(HH, ZZ)              \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 6;            \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 1;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_PLANE_VARIANTS(SRJ_LIST6)
+#undef SRJ_LIST6
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \
@@ -134,6 +145,15 @@ int plan_variants(int32_t *out, int cap)
 
 bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 6) {
+        if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1 ||
+            plan.occ < 1)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_PLANE_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 5) {
         if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.occ != 1 || plan.T < 1)
             return false;
@@ -162,6 +182,16 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s)
 {
+    if (plan.kind == 6) {
+        const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
+                                 {P.face[0], P.face[1], P.face[2]}, P.dconst, P.dinvconst,
+                                 P.diag, P.dinv};
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d<StF64, HH, ZZ>(S, x, xo, P.b, w_dev, s);
+        SRJ_PLANE_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 5) {
         const Coef2D<double> kw{P.dconst, P.dinvconst, P.c[0], P.c[1]};
 #define SRJ_GO(OH, TM) \

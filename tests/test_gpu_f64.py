@@ -144,7 +144,7 @@ def test_3d_plans_bit_identical(torch_cuda, orc, case):
         prob = workloads.c5_instance(7, lo=20, hi=45)
     s = _solver(prob)
     x0 = np.random.default_rng(7).uniform(-1, 1, prob.shape)
-    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] == 3]
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] in (3, 6)]
     results = {}
     for plan in plans:
         assert s.set_plan(*plan) == 0, plan

@@ -112,7 +112,7 @@ def test_inner_3d_plans_bit_identical(torch_cuda, orc, precision):
     prob = workloads.variable_coefficient(23, seed=4, corr_len=3.0)
     s = _solver(prob)
     kw = dict(tol=1e-300, precision=precision, max_cycles=9)
-    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] == 3]
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] in (3, 6)]
     results = {}
     for plan in plans:
         assert s.set_plan(*plan, which=1) == 0, plan
