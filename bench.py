@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB device copy
 # (fetch x2.000, write x1.000).  Valid only for the kernel plan and source they
 # were taken with; any other plan reports null.
-MEASURED_TRAFFIC = {(1, 24, 4, 1): 144.8e6}
+MEASURED_TRAFFIC = {}
 
 
 def parse():

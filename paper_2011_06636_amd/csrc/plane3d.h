@@ -50,13 +50,23 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
         if (!(z >= 0 && z < n2 && row_ok(gy))) return A(0);
         return arr ? arr[colp + gy * s1 + z * s2] : cst;
     };
+    // Products are formed once and moved or kept, not recomputed: c0lo u_{-e0}
+    // is lane p-1's (c0 u) shifted one lane; with constant couplings, c1 u of
+    // a row serves the rows on both sides, and c2 u of a plane serves the
+    // planes before and after it.  A product does not depend on where it is
+    // formed, so the terms are bit-identical to forming each one in place.
     A um[H], uc[H], up[H];
     A f2m[H];
+    A pm[H], pc[H];  // constant couplings: c2 * plane z - 1 and c2 * plane z
 #pragma unroll
     for (int r = 0; r < H; ++r) {
         um[r] = ldu(z0 - 1, gy0 + r);
         uc[r] = ldu(z0, gy0 + r);
         f2m[r] = FACE ? ldc(S.face[2], S.c[2], z0 - 1, gy0 + r) : S.c[2];
+        if (!FACE) {
+            pm[r] = S.c[2] * um[r];
+            pc[r] = S.c[2] * uc[r];
+        }
     }
     for (int64_t z = z0; z < z1; ++z) {
         A bz[H], f0[H], f1[H], f2c[H], dd[H], di[H];
@@ -74,22 +84,40 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
         const A u_above = ldu(z, gy0 - 1);   // row gy0 - 1 of this plane
         const A u_below = ldu(z, gy0 + H);   // row gy0 + H of this plane
         const A f1_above = FACE ? ldc(S.face[1], S.c[1], z, gy0 - 1) : S.c[1];
+        // constant couplings: c1 * row, for the H rows and the two outside
+        A py[H + 2];
+        A pp[H];
+        if (!FACE) {
+            py[0] = S.c[1] * u_above;
+#pragma unroll
+            for (int r = 0; r < H; ++r) py[r + 1] = S.c[1] * uc[r];
+            py[H + 1] = S.c[1] * u_below;
+#pragma unroll
+            for (int r = 0; r < H; ++r) pp[r] = S.c[2] * up[r];
+        }
 #pragma unroll
         for (int r = 0; r < H; ++r) {
             const A xc = uc[r];
-            const A xl = dpp_prev(xc);
-            const A xh = dpp_next(xc);
-            const A cl0 = FACE ? dpp_prev(f0[r]) : S.c[0];
-            const A yu = r > 0 ? uc[r - 1] : u_above;
-            const A yd = r + 1 < H ? uc[r + 1] : u_below;
-            const A cl1 = r > 0 ? f1[r - 1] : f1_above;
             A s = dd[r] * xc;
-            s = s - cl0 * xl;
-            s = s - f0[r] * xh;
-            s = s - cl1 * yu;
-            s = s - f1[r] * yd;
-            s = s - f2m[r] * um[r];
-            s = s - f2c[r] * up[r];
+            if (FACE) {
+                const A yu = r > 0 ? uc[r - 1] : u_above;
+                const A yd = r + 1 < H ? uc[r + 1] : u_below;
+                const A cl1 = r > 0 ? f1[r - 1] : f1_above;
+                s = s - dpp_prev(f0[r] * xc);
+                s = s - f0[r] * dpp_next(xc);
+                s = s - cl1 * yu;
+                s = s - f1[r] * yd;
+                s = s - f2m[r] * um[r];
+                s = s - f2c[r] * up[r];
+            } else {
+                const A p0 = S.c[0] * xc;
+                s = s - dpp_prev(p0);
+                s = s - dpp_next(p0);
+                s = s - py[r];
+                s = s - py[r + 2];
+                s = s - pm[r];
+                s = s - pp[r];
+            }
             const A rr = bz[r] - s;
             const A t = di[r] * rr;
             const int64_t gy = gy0 + r;
@@ -101,6 +129,10 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
             um[r] = uc[r];
             uc[r] = up[r];
             f2m[r] = f2c[r];
+            if (!FACE) {
+                pm[r] = pc[r];
+                pc[r] = pp[r];
+            }
         }
     }
 }

@@ -77,11 +77,11 @@ __device__ __forceinline__ void wave2d_run(int64_t n0, int64_t n1, const typenam
             const A xc = W[k - 1][1];
             const A up = W[k - 1][0];
             const A dn = W[k - 1][2];
-            const A xl = dpp_prev(xc);
-            const A xh = dpp_next(xc);
+            // c0 u_{p -+ e0} is the neighbour lane's c0 u, shifted one lane
+            const A p0 = k2.c0 * xc;
             A s = k2.D * xc;
-            s = s - k2.c0 * xl;
-            s = s - k2.c0 * xh;
+            s = s - dpp_prev(p0);
+            s = s - dpp_next(p0);
             s = s - k2.c1 * up;
             s = s - k2.c1 * dn;
             const A rr = Bw[2 * k] - s;
