@@ -37,7 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB device copy
 # (fetch x2.000, write x1.000).  Valid only for the kernel plan and source they
 # were taken with; any other plan reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {(7, 8, 8, 8): 104.8e6}
+# the same for the one-sweep reference kernel (plan kind 0)
+MEASURED_TRAFFIC_UNFUSED = 104.4e6
 
 
 def parse():
@@ -82,6 +84,52 @@ def cpu_baseline(prob, target_s):
                   f"{out['sweeps']} sweeps, residual after each cycle) of the same solve, "
                   f"{dt:.1f} s",
     }
+
+
+KERNEL_NAMES = {
+    0: "k_sweep_generic<2> (one sweep per launch)",
+    1: "k_tile2d<StF64> (register tiles, fused sweeps)",
+    2: "k_tile2d<StF64> (register tiles, right-hand side in LDS)",
+    5: "k_wave2d<StF64> (wavefront strips)",
+    7: "k_block2d<StF64, C=1> (cooperative wave blocks, fused sweeps)",
+    8: "k_block2d<StF64, C=2> (cooperative wave blocks, two columns per lane)",
+}
+
+
+def unfused_reference(s, x, prob, level=12):
+    """One sweep per launch (kind 0) on the same grid: GLUPS and algorithmic GB/s."""
+    plan = s.get_plan(0)
+    assert s.set_plan(0, 0, 1, 1) == 0
+    s.run_cycle(x, level)
+    s.set_profiling(True)
+    s.run_cycle(x, level)
+    ms, launches, sweeps = s.profile()
+    s.set_profiling(False)
+    assert s.set_plan(*plan) == 0
+    t = ms / 1e3 / max(launches, 1)
+    return {"kernel": KERNEL_NAMES[0], "avg_launch_us": round(t * 1e6, 3),
+            "GLUPS": round(prob.npoints / t / 1e9, 3),
+            "achieved_GBps": round(24.0 * prob.npoints / t / 1e9, 1),
+            "frac": round(24.0 * prob.npoints / t / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_TRAFFIC_UNFUSED if prob.n[0] == 2048 and prob.n[1] == 2048 else None}
+
+
+def copy_ceiling(mib=1024, reps=3):
+    """Device-to-device copy of mib MiB (read + write bytes / time), best of reps."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = max(best, 2.0 * src.numel() * 8 / (a.elapsed_time(b) / 1e3) / 1e9)
+    del src, dst
+    return best
 
 
 def _timed(fn):
@@ -255,6 +303,8 @@ def main():
     avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
     alg_bytes = 24.0 * prob.npoints
     achieved = alg_bytes / avg_launch_s / 1e9
+    unfused = unfused_reference(s, x, prob)
+    ceiling = copy_ceiling()
     f64_time = total / args.steps
     f32_time = sum(t32) / args.steps
     rec = {
@@ -285,11 +335,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": MEASURED_TRAFFIC.get(tuple(plan)) if args.n == 2048 else None,
-                     "kernel": "k_tile2d<StF64> (binary64 relaxation, fused sweeps)",
+                     "kernel": KERNEL_NAMES.get(plan[0], f"plan kind {plan[0]}"),
                      "sweeps_per_launch": round(prof_sweeps / max(launches, 1), 3),
                      "avg_launch_us": round(avg_launch_s * 1e6, 3),
                      "bytes_per_launch": alg_bytes,
-                     "effective_GBps_per_sweep": round(24.0 * glups, 1)},
+                     "effective_GBps_per_sweep": round(24.0 * glups, 1),
+                     "copy_ceiling_GBps": round(ceiling, 1),
+                     "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+                     "unfused_one_sweep": unfused},
     }
     s.close()
     del x

@@ -171,8 +171,12 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * 3D, one sweep per launch, register plane tiles of 64 columns x tile_rows
  * rows streamed over waves_per_simd planes along axis 2 (for kind 6 that
  * field is the plane-chunk length; all faces and a diagonal array, or all
- * constant).  Otherwise waves_per_simd is the register budget the kernel
- * was compiled for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
+ * constant); kind 7: 2D constant-coefficient blocks of waves_per_simd
+ * cooperating waves (for kind 7 that field is the number of waves per
+ * block), each wave holding tile_rows rows of 64 columns, fusing up to
+ * sweeps_per_launch sweeps per launch with the halo paid once per block.
+ * Otherwise waves_per_simd is the register budget the kernel was compiled
+ * for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);
 srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,

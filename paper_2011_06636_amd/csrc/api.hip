@@ -91,10 +91,10 @@ SweepPlan default_inner_plan(const DevProblem &P)
         return pl;
     }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
-        pl.kind = 1;  // 64 x 32 register tiles, 6 sweeps per launch
-        pl.by = 32;
-        pl.T = 6;
-        pl.occ = 1;
+        pl.kind = 7;  // blocks of 8 waves x 8 rows, 8 sweeps per launch
+        pl.by = 8;
+        pl.T = 8;
+        pl.occ = 8;
     }
     return pl;
 }
@@ -116,10 +116,10 @@ SweepPlan default_plan(const DevProblem &P)
         return pl;
     }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
-        pl.kind = 1;  // 64 x 24 register tiles, 4 sweeps per launch, 3 waves per SIMD
-        pl.by = 24;
-        pl.T = 4;
-        pl.occ = 3;
+        pl.kind = 7;  // blocks of 8 waves x 8 rows, 8 sweeps per launch
+        pl.by = 8;
+        pl.T = 8;
+        pl.occ = 8;
     }
     return pl;
 }

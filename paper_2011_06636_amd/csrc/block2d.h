@@ -1,0 +1,262 @@
+// 2D relaxed Jacobi sweeps fused over blocks of cooperating waves.
+//
+// Same per-point expression as every other kernel (Islam & Wang, arXiv
+// 2011.06636, section 2, Eq. 3 in residual form, no fused multiply-add), so
+// results are bit-identical.
+//
+// A workgroup of NW waves owns a block of 64 C columns x NW HW rows, halo
+// included: lane l holds the C adjacent columns l C .. l C + C - 1, and wave w
+// holds rows w HW .. w HW + HW - 1 of the block, all in registers.  Horizontal
+// neighbours inside a lane are its own registers and across lanes come from
+// DPP wave shifts (one shift per direction for C columns); vertical
+// neighbours are registers too, except the rows just above and below a
+// wave's rows, which belong to the neighbouring waves: every wave publishes
+// its first and last rows in LDS before each sweep (double-buffered, one
+// barrier per sweep).  The halo is paid once per block instead of once per
+// wave: after T sweeps the outer T rows and columns of the block are stale,
+// and the (64 C - 2 HALO) x (NW HW - 2 HALO) centre is exact for T <= HALO.
+// Ghost points (outside the grid) hold zero and are never updated.  Blocks
+// are mapped so that consecutive blocks of a block row land on the same XCD.
+#pragma once
+
+#include "internal.h"
+#include "tile2d.h"
+
+#pragma clang fp contract(off)
+
+namespace srj {
+
+template <class T, int C>
+struct alignas(C * sizeof(T)) BlockVec {
+    T v[C];
+};
+
+// T sweeps of one wave's rows.  edge: [2 buffers][2: first row, last row][NW][C][64].
+template <class V, int HW, int NW, int C, bool MASK>
+__device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
+                                             const typename V::A (&br)[HW][C],
+                                             const bool (&col_in)[C], uint32_t rowbits,
+                                             const typename V::A *__restrict__ wlist, int T,
+                                             Coef2D<typename V::A> k2, typename V::A *edge,
+                                             int wave, int lane)
+{
+    using A = typename V::A;
+    for (int k = 0; k < T; ++k) {
+        A *e = edge + (k & 1) * (2 * NW * C * 64);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            e[(wave * C + c) * 64 + lane] = xr[0][c];
+            e[((NW + wave) * C + c) * 64 + lane] = xr[HW - 1][c];
+        }
+        __syncthreads();
+        // rows outside the block read zero (they only feed halo rows)
+        A upv[C], dnv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            upv[c] = wave > 0 ? e[((NW + wave - 1) * C + c) * 64 + lane] : A(0);
+            dnv[c] = wave + 1 < NW ? e[((wave + 1) * C + c) * 64 + lane] : A(0);
+        }
+        const A w = wlist[k];
+        // products are formed once and moved: c0 u of a column serves the
+        // columns on both sides (in the lane, or one lane over by a shift),
+        // and c1 u of a row serves the rows on both sides
+        A c1up[C], c1cur[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            c1up[c] = k2.c1 * upv[c];
+            c1cur[c] = k2.c1 * xr[0][c];
+        }
+#pragma unroll
+        for (int r = 0; r < HW; ++r) {
+            A p[C], c1dn[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                p[c] = k2.c0 * xr[r][c];
+                c1dn[c] = k2.c1 * ((r + 1 < HW) ? xr[r + 1][c] : dnv[c]);
+            }
+            const A pl = dpp_prev(p[C - 1]);  // c0 u of the column left of this lane
+            const A ph = dpp_next(p[0]);      // c0 u of the column right of this lane
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const A xc = xr[r][c];
+                A s = k2.D * xc;
+                s = s - (c > 0 ? p[c > 0 ? c - 1 : 0] : pl);
+                s = s - (c + 1 < C ? p[c + 1 < C ? c + 1 : 0] : ph);
+                s = s - c1up[c];
+                s = s - c1dn[c];
+                const A rr = br[r][c] - s;
+                const A t = k2.Dinv * rr;
+                const A nx = V::round(xc + w * t);
+                c1up[c] = c1cur[c];
+                c1cur[c] = c1dn[c];
+                if (MASK)
+                    xr[r][c] = (col_in[c] && ((rowbits >> r) & 1)) ? nx : A(0);
+                else
+                    xr[r][c] = nx;
+            }
+        }
+    }
+}
+
+template <class V, int HW, int HALO, int NW, int C>
+__device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1, const typename V::T *__restrict__ x,
+                                            typename V::T *__restrict__ xo,
+                                            const typename V::T *__restrict__ b,
+                                            const typename V::A *__restrict__ wlist, int T,
+                                            Coef2D<typename V::A> k2, int bx, int by, bool vec,
+                                            int wave, int lane, typename V::A *edge)
+{
+    using A = typename V::A;
+    using ST = typename V::T;
+    constexpr int BW = 64 * C;         // columns per block, halo included
+    constexpr int OW = BW - 2 * HALO;  // output columns per block
+    constexpr int BH = NW * HW;        // rows per block, halo included
+    constexpr int OH = BH - 2 * HALO;  // output rows per block
+    static_assert(HW <= 32, "row validity is a 32-bit mask");
+    static_assert(OH > 0 && OW > 0, "halo larger than the block");
+    static_assert(HALO % C == 0, "lane columns must stay aligned");
+    const int64_t bx0 = (int64_t)bx * OW - HALO;
+    const int64_t by0 = (int64_t)by * OH - HALO;
+    const int64_t gx = bx0 + (int64_t)lane * C;    // first column of this lane
+    const int64_t gy0 = by0 + (int64_t)wave * HW;  // first row of this wave
+    // uniform over the block: both paths run the same barriers
+    const bool interior = bx0 >= 0 && bx0 + BW <= n0 && by0 >= 0 && by0 + BH <= n1;
+    // rows of this wave that are written back: block rows HALO .. BH - HALO - 1
+    const int rlo = HALO - wave * HW, rhi = BH - HALO - wave * HW;
+    A xr[HW][C], br[HW][C];
+    const int64_t p0 = gy0 * n0 + gx;
+    if (interior) {
+        if (C > 1 && vec) {
+            using VT = BlockVec<ST, C>;
+#pragma unroll
+            for (int r = 0; r < HW; ++r) {
+                const VT qx = *reinterpret_cast<const VT *>(x + p0 + r * n0);
+                const VT qb = *reinterpret_cast<const VT *>(b + p0 + r * n0);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    xr[r][c] = V::load(qx.v[c]);
+                    br[r][c] = V::load(qb.v[c]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < HW; ++r)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    xr[r][c] = V::load(x[p0 + r * n0 + c]);
+                    br[r][c] = V::load(b[p0 + r * n0 + c]);
+                }
+        }
+        bool col_in[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) col_in[c] = true;
+        block_sweeps<V, HW, NW, C, false>(xr, br, col_in, ~0u, wlist, T, k2, edge, wave, lane);
+        // lanes whose columns are all output (HALO is a multiple of C)
+        if (lane * C >= HALO && lane * C < BW - HALO) {
+            if (C > 1 && vec) {
+                using VT = BlockVec<ST, C>;
+#pragma unroll
+                for (int r = 0; r < HW; ++r)
+                    if (r >= rlo && r < rhi) {
+                        VT q;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) q.v[c] = V::store(xr[r][c]);
+                        *reinterpret_cast<VT *>(xo + p0 + r * n0) = q;
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < HW; ++r)
+                    if (r >= rlo && r < rhi)
+#pragma unroll
+                        for (int c = 0; c < C; ++c) xo[p0 + r * n0 + c] = V::store(xr[r][c]);
+            }
+        }
+        return;
+    }
+    bool col_in[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) col_in[c] = gx + c >= 0 && gx + c < n0;
+    uint32_t rowbits = 0;
+#pragma unroll
+    for (int r = 0; r < HW; ++r)
+        if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= 1u << r;
+#pragma unroll
+    for (int r = 0; r < HW; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const bool in = col_in[c] && ((rowbits >> r) & 1);
+            const int64_t p = (gy0 + r) * n0 + gx + c;
+            xr[r][c] = in ? V::load(x[p]) : A(0);
+            br[r][c] = in ? V::load(b[p]) : A(0);
+        }
+    block_sweeps<V, HW, NW, C, true>(xr, br, col_in, rowbits, wlist, T, k2, edge, wave, lane);
+    if (lane * C >= HALO && lane * C < BW - HALO) {
+#pragma unroll
+        for (int r = 0; r < HW; ++r)
+            if (r >= rlo && r < rhi && ((rowbits >> r) & 1))
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (col_in[c]) xo[(gy0 + r) * n0 + gx + c] = V::store(xr[r][c]);
+    }
+}
+
+template <class V, int HW, int HALO, int NW, int C>
+__global__ __launch_bounds__(64 * NW) void k_block2d(int64_t n0, int64_t n1,
+                                                     const typename V::T *__restrict__ x,
+                                                     typename V::T *__restrict__ xo,
+                                                     const typename V::T *__restrict__ b,
+                                                     const typename V::A *__restrict__ wlist, int T,
+                                                     Coef2D<typename V::A> k2, int blocks_x,
+                                                     int nblocks, int vec)
+{
+    using A = typename V::A;
+    __shared__ A edge[2 * 2 * NW * C * 64];
+    // XCD-aware order: hardware places block i on XCD i % 8; each XCD takes a
+    // contiguous range of logical blocks so neighbouring blocks share its L2.
+    const int per_xcd = (nblocks + 7) / 8;
+    const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (logical >= nblocks) return;  // whole block leaves
+    block2d_run<V, HW, HALO, NW, C>(n0, n1, x, xo, b, wlist, T, k2, logical % blocks_x,
+                                    logical / blocks_x, vec != 0, threadIdx.x >> 6,
+                                    threadIdx.x & 63, edge);
+}
+
+template <class V, int HW, int HALO, int NW, int C>
+hipError_t launch_block2d(int64_t n0, int64_t n1, const typename V::T *x, typename V::T *xo,
+                          const typename V::T *b, const typename V::A *w_dev, int T,
+                          Coef2D<typename V::A> k2, hipStream_t s)
+{
+    constexpr int OW = 64 * C - 2 * HALO, OH = NW * HW - 2 * HALO;
+    if (T < 1 || T > HALO) return hipErrorInvalidValue;
+    const int64_t bxn = (n0 + OW - 1) / OW, byn = (n1 + OH - 1) / OH;
+    const int64_t nblocks = bxn * byn;
+    if (nblocks > (int64_t)1 << 28) return hipErrorInvalidValue;
+    // C-wide vector accesses need every row start and every pointer aligned
+    // to C values (the block origins are, since OW and HALO are multiples of C)
+    const uintptr_t al = (uintptr_t)C * sizeof(typename V::T);
+    const int vec = C > 1 && n0 % C == 0 && (uintptr_t)x % al == 0 && (uintptr_t)xo % al == 0 &&
+                    (uintptr_t)b % al == 0;
+    // a multiple of 8 blocks, so the XCD mapping covers every logical block
+    const int grid = (int)((nblocks + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_block2d<V, HW, HALO, NW, C>), dim3(grid), dim3(64 * NW), 0, s, n0, n1,
+                       x, xo, b, w_dev, T, k2, (int)bxn, (int)nblocks, vec);
+    return hipGetLastError();
+}
+
+// (rows per wave, halo = most sweeps per launch, waves per block) of the
+// binary64 block plans: one column per lane (kind 7) and two (kind 8)
+#define SRJ_BLOCK_VARIANTS(X)                                                               \
+    X(8, 4, 8) X(8, 6, 8) X(8, 8, 8) X(8, 8, 16) X(12, 6, 8) X(12, 8, 6) X(12, 8, 8)          \
+    X(16, 6, 4) X(16, 8, 4) X(16, 8, 6) X(16, 8, 8) X(20, 8, 4) X(24, 8, 4)
+#define SRJ_BLOCK2_VARIANTS(X) \
+    X(4, 8, 8) X(4, 8, 16) X(6, 8, 8) X(8, 6, 8) X(8, 8, 4) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4) X(12, 8, 8)
+
+// the same for sweeps in binary32 arithmetic (two values per register pair
+// fewer, so taller waves fit)
+#define SRJ_INNER_BLOCK_VARIANTS(X)                                                         \
+    X(8, 6, 8) X(8, 8, 8) X(8, 8, 16) X(12, 6, 8) X(12, 8, 6) X(12, 8, 8) X(16, 6, 8)       \
+    X(16, 8, 4) X(16, 8, 8) X(24, 8, 4) X(24, 8, 8) X(32, 8, 4)
+#define SRJ_INNER_BLOCK2_VARIANTS(X) \
+    X(4, 8, 8) X(6, 8, 8) X(8, 8, 4) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4) X(12, 8, 8) X(16, 8, 4)
+
+}  // namespace srj

@@ -28,6 +28,7 @@
 #include "stream3d.h"
 #include "wave2d.h"
 #include "plane3d.h"
+#include "block2d.h"
 
 #pragma clang fp contract(off)
 
@@ -161,6 +162,19 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     const TT *dd = static_cast<const TT *>(d);
     TT *oo = static_cast<TT *>(dout);
     const TT *rr = static_cast<const TT *>(rhat);
+    if (plan.kind == 7 || plan.kind == 8) {
+#define SRJ_GO1(HW, HL, NW)                                \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+        return launch_block2d<St, HW, HL, NW, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
+#define SRJ_GO2(HW, HL, NW)                                \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+        return launch_block2d<St, HW, HL, NW, 2>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
+        if (plan.kind == 7) { SRJ_INNER_BLOCK_VARIANTS(SRJ_GO1) }
+        else { SRJ_INNER_BLOCK2_VARIANTS(SRJ_GO2) }
+#undef SRJ_GO1
+#undef SRJ_GO2
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 6) {
         const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
                                 {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
@@ -241,6 +255,14 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 7 || plan.kind == 8) {
+        if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.T < 1) return false;
+#define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
+        if (plan.kind == 7) { SRJ_INNER_BLOCK_VARIANTS(SRJ_CHK) }
+        else { SRJ_INNER_BLOCK2_VARIANTS(SRJ_CHK) }
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 6) {
         if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1)
             return false;
@@ -276,6 +298,21 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 int inner_plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST7(HW, HL, NW)          \
+    if (n < cap) {                     \
+        out[4 * n + 0] = KIND;         \
+        out[4 * n + 1] = HW;           \
+        out[4 * n + 2] = HL;           \
+        out[4 * n + 3] = NW;           \
+    }                                  \
+    ++n;
+#define KIND 7
+    SRJ_INNER_BLOCK_VARIANTS(SRJ_LIST7)
+#undef KIND
+#define KIND 8
+    SRJ_INNER_BLOCK2_VARIANTS(SRJ_LIST7)
+#undef KIND
+#undef SRJ_LIST7
 #define SRJ_LIST6(HH, ZZ)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 6;            \

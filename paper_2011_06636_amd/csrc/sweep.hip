@@ -13,6 +13,7 @@
 #include "stream3d.h"
 #include "wave2d.h"
 #include "plane3d.h"
+#include "block2d.h"
 
 #pragma clang fp contract(off)
 
@@ -101,6 +102,21 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 int plan_variants(int32_t *out, int cap)
 {
     int n = 0;
+#define SRJ_LIST7(HW, HL, NW)          \
+    if (n < cap) {                     \
+        out[4 * n + 0] = KIND;         \
+        out[4 * n + 1] = HW;           \
+        out[4 * n + 2] = HL;           \
+        out[4 * n + 3] = NW;           \
+    }                                  \
+    ++n;
+#define KIND 7
+    SRJ_BLOCK_VARIANTS(SRJ_LIST7)
+#undef KIND
+#define KIND 8
+    SRJ_BLOCK2_VARIANTS(SRJ_LIST7)
+#undef KIND
+#undef SRJ_LIST7
 #define SRJ_LIST6(HH, ZZ)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 6;            \
@@ -145,6 +161,14 @@ int plan_variants(int32_t *out, int cap)
 
 bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (plan.kind == 7 || plan.kind == 8) {
+        if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.T < 1) return false;
+#define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
+        if (plan.kind == 7) { SRJ_BLOCK_VARIANTS(SRJ_CHK) }
+        else { SRJ_BLOCK2_VARIANTS(SRJ_CHK) }
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 6) {
         if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1 ||
             plan.occ < 1)
@@ -182,6 +206,20 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s)
 {
+    if (plan.kind == 7 || plan.kind == 8) {
+        const Coef2D<double> kb{P.dconst, P.dinvconst, P.c[0], P.c[1]};
+#define SRJ_GO1(HW, HL, NW)                                \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+        return launch_block2d<StF64, HW, HL, NW, 1>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s);
+#define SRJ_GO2(HW, HL, NW)                                \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+        return launch_block2d<StF64, HW, HL, NW, 2>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s);
+        if (plan.kind == 7) { SRJ_BLOCK_VARIANTS(SRJ_GO1) }
+        else { SRJ_BLOCK2_VARIANTS(SRJ_GO2) }
+#undef SRJ_GO1
+#undef SRJ_GO2
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 6) {
         const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
                                  {P.face[0], P.face[1], P.face[2]}, P.dconst, P.dinvconst,

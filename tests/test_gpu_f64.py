@@ -111,7 +111,7 @@ def test_fused_plans_bit_identical(torch_cuda, orc):
     from paper_2011_06636_amd import abi
     plans = [(0, 0, 1, 1)]
     for kind, rows, halo, occ in abi.srj_plan_variants():
-        if kind in (1, 2, 5):
+        if kind in (1, 2, 5, 7, 8):
             plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
     for plan in plans:
         assert s.set_plan(*plan) == 0

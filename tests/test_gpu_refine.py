@@ -89,7 +89,7 @@ def test_inner_plans_bit_identical(torch_cuda, orc, precision):
     kw = dict(tol=1e-300, precision=precision, max_cycles=10)
     plans = [(0, 0, 1, 1)]
     for kind, rows, halo, occ in abi.srj_plan_variants(which=1):
-        if kind in (1, 5):
+        if kind in (1, 5, 7, 8):
             plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
     results = {}
     for plan in plans:
