@@ -59,7 +59,11 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(prob, target_s):
+def cpu_baseline(prob, target_s, levels):
+    """The oracle on the first cycles of the same solve, about target_s seconds.
+
+    levels: the level of every cycle of the GPU solve (the oracle takes the
+    same ones), used only to size the sample."""
     import oracle
     rate_probe = prob.zeros()
     rate_probe = oracle.sweep(prob, rate_probe, 0.6)
@@ -67,11 +71,12 @@ def cpu_baseline(prob, target_s):
     for w in (0.6, 1.1, 0.9):
         rate_probe = oracle.sweep(prob, rate_probe, w)
     per_sweep = (time.perf_counter() - t) / 3.0
-    # cycles of the heuristic climb 0, 1, 2, ... until the sample fills target_s
     budget = max(1, int(target_s / max(per_sweep, 1e-9)))
     cycles, sweeps = 0, 0
-    while cycles < 25 and sweeps + oracle.level_M(cycles) <= budget:
-        sweeps += oracle.level_M(cycles)
+    for lv in levels:
+        if sweeps + oracle.level_M(int(lv)) > budget:
+            break
+        sweeps += oracle.level_M(int(lv))
         cycles += 1
     cycles = max(cycles, 1)
     t = time.perf_counter()
@@ -350,7 +355,7 @@ def main():
         rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
                          "c5_batch_3d": extra_batch("c5")}
     if args.cpu_seconds > 0:
-        rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"])
     print(json.dumps(rec), flush=True)
 
 

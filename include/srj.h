@@ -172,9 +172,10 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * rows streamed over waves_per_simd planes along axis 2 (for kind 6 that
  * field is the plane-chunk length; all faces and a diagonal array, or all
  * constant); kind 7: 2D constant-coefficient blocks of waves_per_simd
- * cooperating waves (for kind 7 that field is the number of waves per
- * block), each wave holding tile_rows rows of 64 columns, fusing up to
- * sweeps_per_launch sweeps per launch with the halo paid once per block.
+ * cooperating waves (for kinds 7 and 8 that field is the number of waves
+ * per block), each wave holding tile_rows rows of 64 columns, fusing up to
+ * sweeps_per_launch sweeps per launch with the halo paid once per block;
+ * kind 8: the same with two adjacent columns per lane (128-column blocks).
  * Otherwise waves_per_simd is the register budget the kernel was compiled
  * for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
@@ -225,15 +226,20 @@ srj_status srj_destroy(srj_ctx *ctx);
 srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_stream,
                            srj_batch **out);
 
-/* Kernel plan of a batch: 2D/1D instances use register tiles of 64 columns x
- * tile_rows rows (16, 24, 32 or 48) fusing up to sweeps_per_launch sweeps per
- * step (at most 2, 4, 4/6 or 8); 3D instances advance one z-streamed sweep per
- * step.  steps_per_graph steps are captured in one hipGraph (use_graph = 1)
- * or enqueued directly (use_graph = 0).  Iterates do not depend on the plan. */
+/* Kernel plan of a batch.  With waves_per_block = 1, 2D/1D instances use
+ * single-wave register tiles of 64 columns x tile_rows rows (16, 24, 32 or
+ * 48) fusing up to sweeps_per_launch sweeps per step (at most 2, 4, 4/6 or
+ * 8); with waves_per_block > 1 they use blocks of that many cooperating waves
+ * of tile_rows rows each (the shapes of plan kind 7: (8, 8 waves, up to 4 or
+ * 8 sweeps), (12, 8 waves, 8), (16, 4 waves, 8)).  3D instances advance one
+ * plane-tile sweep per step.  steps_per_graph steps are captured in one
+ * hipGraph (use_graph = 1) or enqueued directly (use_graph = 0).  Iterates do
+ * not depend on the plan. */
 srj_status srj_batch_set_plan(srj_batch *batch, int32_t tile_rows, int32_t sweeps_per_launch,
-                              int32_t steps_per_graph, int32_t use_graph);
+                              int32_t waves_per_block, int32_t steps_per_graph, int32_t use_graph);
 srj_status srj_batch_get_plan(srj_batch *batch, int32_t *tile_rows, int32_t *sweeps_per_launch,
-                              int32_t *steps_per_graph, int32_t *use_graph);
+                              int32_t *waves_per_block, int32_t *steps_per_graph,
+                              int32_t *use_graph);
 
 /* Solve every instance from its initial guess xs[i] (device, in/out, the
  * instance's n0*n1*n2 binary64 values).  opts applies to every instance

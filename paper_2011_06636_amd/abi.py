@@ -93,8 +93,8 @@ def load() -> ctypes.CDLL:
         "srj_set_profiling": (i32, [vp, i32]),
         "srj_get_profile": (i32, [vp, P(f64), P(i64), P(i64)]),
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
-        "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32]),
-        "srj_batch_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32)]),
+        "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
+        "srj_batch_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
         "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
@@ -222,14 +222,14 @@ def srj_batch_setup(probs, stream: int = 0):
     return st, h
 
 
-def srj_batch_set_plan(batch, tile_rows: int, sweeps: int, steps_per_graph: int = 16,
-                       use_graph: bool = True) -> int:
-    return load().srj_batch_set_plan(batch, tile_rows, sweeps, steps_per_graph,
+def srj_batch_set_plan(batch, tile_rows: int, sweeps: int, waves_per_block: int = 1,
+                       steps_per_graph: int = 16, use_graph: bool = True) -> int:
+    return load().srj_batch_set_plan(batch, tile_rows, sweeps, waves_per_block, steps_per_graph,
                                      1 if use_graph else 0)
 
 
 def srj_batch_get_plan(batch):
-    v = [ctypes.c_int32() for _ in range(4)]
+    v = [ctypes.c_int32() for _ in range(5)]
     check(load().srj_batch_get_plan(batch, *[ctypes.byref(a) for a in v]), "srj_batch_get_plan")
     return tuple(a.value for a in v)
 

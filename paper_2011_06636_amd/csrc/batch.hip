@@ -31,6 +31,7 @@
 #include "stream3d.h"
 #include "tile2d.h"
 #include "plane3d.h"
+#include "block2d.h"
 
 #pragma clang fp contract(off)
 
@@ -132,6 +133,40 @@ __global__ __launch_bounds__(256) void k_bsweep2d(const BDesc *__restrict__ desc
         typename V::T *uout = (s.pu ? ua : ub) + d.off;
         tile2d_run<V, H, HALO, false>(d.n0, d.n1, uin, uout, rhs + d.off, w, T, Sel<A>::coef2(d),
                                       it.y % d.tiles_x, it.y / d.tiles_x, lane, nullptr);
+    }
+}
+
+// 1 (blocks). sweeps, 2D/1D instances: one workgroup of NW cooperating waves
+// per (instance, block) item.  The workgroups of one XCD take the items of
+// one contiguous range in turn (hardware places workgroup i on XCD i % 8), so
+// neighbouring blocks of an instance share that XCD's L2.
+template <class V, int HW, int HALO, int NW>
+__global__ __launch_bounds__(64 * NW) void k_bsweep2d_blk(const BDesc *__restrict__ desc,
+                                                          const BState *__restrict__ st,
+                                                          const int2 *__restrict__ items, int nitems,
+                                                          typename V::T *ua, typename V::T *ub,
+                                                          const typename V::T *__restrict__ rhs,
+                                                          BParams prm)
+{
+    using A = typename V::A;
+    __shared__ A edge[2 * 2 * NW * 64];
+    const int per_xcd = (nitems + 7) / 8;
+    const int xcd = blockIdx.x % 8, stride = gridDim.x / 8;
+    const int end = min((xcd + 1) * per_xcd, nitems);
+    int kbase = 0;
+    for (int item = xcd * per_xcd + blockIdx.x / 8; item < end; item += stride) {
+        const int2 it = items[item];
+        const BState s = st[it.x];
+        if (s.done) continue;  // uniform over the workgroup
+        const BDesc &d = desc[it.x];
+        const int T = sweeps_this_step(d, s, prm);
+        const A *w = Sel<A>::omega(prm) + prm.offsets[s.level] + s.pos;
+        const typename V::T *uin = (s.pu ? ub : ua) + d.off;
+        typename V::T *uout = (s.pu ? ua : ub) + d.off;
+        block2d_item<V, HW, HALO, NW, 1>(d.n0, d.n1, uin, uout, rhs + d.off, w, T,
+                                         Sel<A>::coef2(d), it.y % d.tiles_x, it.y / d.tiles_x,
+                                         false, threadIdx.x >> 6, threadIdx.x & 63, edge, kbase);
+        kbase += T;
     }
 }
 
@@ -407,7 +442,7 @@ struct srj_batch {
     int64_t hist_cap = 0;
     int32_t *done_dev = nullptr, *done_host = nullptr;
     // plan
-    int tile_rows = 24, halo = 4, T2 = 4, steps_per_graph = 16;
+    int tile_rows = 24, halo = 4, T2 = 4, waves = 1, steps_per_graph = 16;
     bool use_graph = true;
 };
 
@@ -432,12 +467,23 @@ void batch_free(srj_batch *B)
 // tile shapes (rows, halo) of the batched 2D sweep kernel
 #define SRJ_BATCH_2D(X) X(16, 2) X(24, 4) X(32, 4) X(32, 6) X(48, 8)
 
-bool batch_tile_ok(int rows, int T)
+// cooperative block shapes (rows per wave, halo, waves per block)
+#define SRJ_BATCH_BLOCK(X) X(8, 4, 8) X(8, 8, 8) X(12, 8, 8) X(16, 8, 4)
+
+// the halo of a plan, 0 if there is no such plan
+int batch_plan_halo(int rows, int T, int waves)
 {
-#define SRJ_OK_(R, HL) if (rows == R && T >= 1 && T <= HL) return true;
-    SRJ_BATCH_2D(SRJ_OK_)
+    if (T < 1) return 0;
+    if (waves == 1) {
+#define SRJ_OK_(R, HL) if (rows == R && T <= HL) return HL;
+        SRJ_BATCH_2D(SRJ_OK_)
 #undef SRJ_OK_
-    return false;
+        return 0;
+    }
+#define SRJ_OK_(HW, HL, NW) if (rows == HW && waves == NW && T <= HL) return HL;
+    SRJ_BATCH_BLOCK(SRJ_OK_)
+#undef SRJ_OK_
+    return 0;
 }
 
 template <class V>
@@ -445,6 +491,22 @@ hipError_t launch_bsweep2d(srj_batch *B, void *ua, void *ub, const void *rhs, co
                            int grid)
 {
     using T = typename V::T;
+    if (B->waves > 1) {
+        // a few resident workgroups per CU, a multiple of 8 (one set per XCD)
+        const int64_t items = (int64_t)B->hitems2.size();
+        const int g = (int)std::max<int64_t>(8, std::min<int64_t>((items + 7) / 8 * 8,
+                                                                  (int64_t)B->cus * 3 / 8 * 8));
+#define SRJ_GOB(HW, HL, NW)                                                                    \
+        if (B->tile_rows == HW && B->halo == HL && B->waves == NW) {                           \
+            hipLaunchKernelGGL((k_bsweep2d_blk<V, HW, HL, NW>), dim3(g), dim3(64 * NW), 0,     \
+                               B->stream, B->desc, B->state, B->items2, (int)items, (T *)ua,   \
+                               (T *)ub, (const T *)rhs, prm);                                  \
+            return hipGetLastError();                                                          \
+        }
+        SRJ_BATCH_BLOCK(SRJ_GOB)
+#undef SRJ_GOB
+        return hipErrorInvalidValue;
+    }
 #define SRJ_GO(R, HL)                                                                         \
     if (B->tile_rows == R && B->halo == HL) {                                                 \
         hipLaunchKernelGGL((k_bsweep2d<V, R, HL>), dim3(grid), dim3(256), 0, B->stream, B->desc, \
@@ -858,7 +920,7 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
         batch_free(B);
         return fail(SRJ_ERR_HIP, std::string("batch setup: ") + hipGetErrorString(e));
     }
-    srj_status st = srj_batch_set_plan(B, B->tile_rows, B->T2, B->steps_per_graph, 1);
+    srj_status st = srj_batch_set_plan(B, B->tile_rows, B->T2, B->waves, B->steps_per_graph, 1);
     if (st != SRJ_OK) {
         batch_free(B);
         return st;
@@ -868,23 +930,22 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
 }
 
 srj_status srj_batch_set_plan(srj_batch *B, int32_t tile_rows, int32_t sweeps_per_launch,
-                              int32_t steps_per_graph, int32_t use_graph)
+                              int32_t waves_per_block, int32_t steps_per_graph, int32_t use_graph)
 {
     if (!B) return fail(SRJ_ERR_INVALID, "batch is NULL");
-    if (!batch_tile_ok(tile_rows, sweeps_per_launch))
-        return fail(SRJ_ERR_UNSUPPORTED, "tile rows / sweeps per launch not available");
+    const int halo = batch_plan_halo(tile_rows, sweeps_per_launch, waves_per_block);
+    if (halo == 0)
+        return fail(SRJ_ERR_UNSUPPORTED, "tile rows / sweeps per launch / waves not available");
     if (steps_per_graph < 1 || steps_per_graph > 1024)
         return fail(SRJ_ERR_INVALID, "steps_per_graph must be 1..1024");
     B->tile_rows = tile_rows;
     B->T2 = sweeps_per_launch;
+    B->waves = waves_per_block;
     B->steps_per_graph = steps_per_graph;
     B->use_graph = use_graph != 0;
-    int halo = 0;
-#define SRJ_H(R, HL) if (tile_rows == R && halo == 0 && sweeps_per_launch <= HL) halo = HL;
-    SRJ_BATCH_2D(SRJ_H)
-#undef SRJ_H
     B->halo = halo;
-    const int OW = 64 - 2 * halo, OH = tile_rows - 2 * halo;
+    // output columns and rows per work item (a single-wave tile or a block)
+    const int OW = 64 - 2 * halo, OH = tile_rows * waves_per_block - 2 * halo;
     // work items
     B->hitems2.clear();
     B->hitems3.clear();
@@ -953,12 +1014,14 @@ srj_status srj_batch_solve(srj_batch *B, double *const *xs, const srj_solve_opts
 }
 
 srj_status srj_batch_get_plan(srj_batch *B, int32_t *tile_rows, int32_t *sweeps_per_launch,
-                              int32_t *steps_per_graph, int32_t *use_graph)
+                              int32_t *waves_per_block, int32_t *steps_per_graph,
+                              int32_t *use_graph)
 {
-    if (!B || !tile_rows || !sweeps_per_launch || !steps_per_graph || !use_graph)
+    if (!B || !tile_rows || !sweeps_per_launch || !waves_per_block || !steps_per_graph || !use_graph)
         return fail(SRJ_ERR_INVALID, "NULL argument");
     *tile_rows = B->tile_rows;
     *sweeps_per_launch = B->T2;
+    *waves_per_block = B->waves;
     *steps_per_graph = B->steps_per_graph;
     *use_graph = B->use_graph ? 1 : 0;
     return SRJ_OK;
@@ -980,19 +1043,22 @@ srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
     o.max_sweeps = (int64_t)1 << 60;
     const int steps_per_graph = B->steps_per_graph;
     const bool use_graph = B->use_graph;
-    int best_rows = B->tile_rows, best_T = B->T2;
+    int best_rows = B->tile_rows, best_T = B->T2, best_waves = B->waves;
     double best = INFINITY;
     struct Cand {
-        int rows, T;
+        int rows, T, waves;
     };
     std::vector<Cand> cands;
 #define SRJ_C(R, HL)                                        \
-    cands.push_back({R, HL});                               \
-    if ((HL + 1) / 2 != HL) cands.push_back({R, (HL + 1) / 2});
+    cands.push_back({R, HL, 1});                            \
+    if ((HL + 1) / 2 != HL) cands.push_back({R, (HL + 1) / 2, 1});
     SRJ_BATCH_2D(SRJ_C)
 #undef SRJ_C
+#define SRJ_CB(HW, HL, NW) cands.push_back({HW, HL, NW});
+    SRJ_BATCH_BLOCK(SRJ_CB)
+#undef SRJ_CB
     for (const Cand &cd : cands) {
-        srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, steps_per_graph, use_graph);
+        srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, cd.waves, steps_per_graph, use_graph);
         if (st != SRJ_OK) return st;
         // every step moves 2D instances by T sweeps and 3D instances by one
         const int steps = std::max(1, (sweeps + cd.T - 1) / cd.T);
@@ -1009,10 +1075,11 @@ srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
             best = us;
             best_rows = cd.rows;
             best_T = cd.T;
+            best_waves = cd.waves;
         }
     }
     *best_us_per_sweep = best;
-    return srj_batch_set_plan(B, best_rows, best_T, steps_per_graph, use_graph ? 1 : 0);
+    return srj_batch_set_plan(B, best_rows, best_T, best_waves, steps_per_graph, use_graph ? 1 : 0);
 }
 
 srj_status srj_batch_destroy(srj_batch *B)

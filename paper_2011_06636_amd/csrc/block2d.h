@@ -31,18 +31,20 @@ struct alignas(C * sizeof(T)) BlockVec {
     T v[C];
 };
 
-// T sweeps of one wave's rows.  edge: [2 buffers][2: first row, last row][NW][C][64].
+// T sweeps of one wave's rows.  edge: [2 buffers][2: first row, last row][NW][C][64];
+// sweep k uses buffer (kbase + k) & 1, so consecutive sweeps alternate
+// buffers also across the blocks of a persistent workgroup.
 template <class V, int HW, int NW, int C, bool MASK>
 __device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
                                              const typename V::A (&br)[HW][C],
                                              const bool (&col_in)[C], uint32_t rowbits,
                                              const typename V::A *__restrict__ wlist, int T,
                                              Coef2D<typename V::A> k2, typename V::A *edge,
-                                             int wave, int lane)
+                                             int wave, int lane, int kbase)
 {
     using A = typename V::A;
     for (int k = 0; k < T; ++k) {
-        A *e = edge + (k & 1) * (2 * NW * C * 64);
+        A *e = edge + ((kbase + k) & 1) * (2 * NW * C * 64);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             e[(wave * C + c) * 64 + lane] = xr[0][c];
@@ -98,40 +100,58 @@ __device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
     }
 }
 
-template <class V, int HW, int HALO, int NW, int C>
-__device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1, const typename V::T *__restrict__ x,
-                                            typename V::T *__restrict__ xo,
-                                            const typename V::T *__restrict__ b,
-                                            const typename V::A *__restrict__ wlist, int T,
-                                            Coef2D<typename V::A> k2, int bx, int by, bool vec,
-                                            int wave, int lane, typename V::A *edge)
-{
-    using A = typename V::A;
-    using ST = typename V::T;
-    constexpr int BW = 64 * C;         // columns per block, halo included
-    constexpr int OW = BW - 2 * HALO;  // output columns per block
-    constexpr int BH = NW * HW;        // rows per block, halo included
-    constexpr int OH = BH - 2 * HALO;  // output rows per block
+// Where one wave's part of block (bx, by) lies.
+template <int HW, int HALO, int NW, int C>
+struct BlockPos {
+    static constexpr int BW = 64 * C;         // columns per block, halo included
+    static constexpr int OW = BW - 2 * HALO;  // output columns per block
+    static constexpr int BH = NW * HW;        // rows per block, halo included
+    static constexpr int OH = BH - 2 * HALO;  // output rows per block
     static_assert(HW <= 32, "row validity is a 32-bit mask");
     static_assert(OH > 0 && OW > 0, "halo larger than the block");
     static_assert(HALO % C == 0, "lane columns must stay aligned");
-    const int64_t bx0 = (int64_t)bx * OW - HALO;
-    const int64_t by0 = (int64_t)by * OH - HALO;
-    const int64_t gx = bx0 + (int64_t)lane * C;    // first column of this lane
-    const int64_t gy0 = by0 + (int64_t)wave * HW;  // first row of this wave
-    // uniform over the block: both paths run the same barriers
-    const bool interior = bx0 >= 0 && bx0 + BW <= n0 && by0 >= 0 && by0 + BH <= n1;
-    // rows of this wave that are written back: block rows HALO .. BH - HALO - 1
-    const int rlo = HALO - wave * HW, rhi = BH - HALO - wave * HW;
-    A xr[HW][C], br[HW][C];
-    const int64_t p0 = gy0 * n0 + gx;
-    if (interior) {
+    int64_t gx, gy0, p0;  // first column of the lane, first row of the wave, flat index
+    bool interior;        // uniform over the block: both paths run the same barriers
+    bool col_in[C];
+    uint32_t rowbits;
+    int rlo, rhi;         // rows of this wave written back: block rows HALO .. BH - HALO - 1
+    bool lane_out;        // all C columns of the lane are output columns
+
+    __device__ __forceinline__ BlockPos(int64_t n0, int64_t n1, int bx, int by, int wave, int lane)
+    {
+        const int64_t bx0 = (int64_t)bx * OW - HALO;
+        const int64_t by0 = (int64_t)by * OH - HALO;
+        gx = bx0 + (int64_t)lane * C;
+        gy0 = by0 + (int64_t)wave * HW;
+        p0 = gy0 * n0 + gx;
+        interior = bx0 >= 0 && bx0 + BW <= n0 && by0 >= 0 && by0 + BH <= n1;
+#pragma unroll
+        for (int c = 0; c < C; ++c) col_in[c] = gx + c >= 0 && gx + c < n0;
+        rowbits = 0;
+#pragma unroll
+        for (int r = 0; r < HW; ++r)
+            if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= 1u << r;
+        rlo = HALO - wave * HW;
+        rhi = BH - HALO - wave * HW;
+        lane_out = lane * C >= HALO && lane * C < BW - HALO;
+    }
+};
+
+template <class V, int HW, int HALO, int NW, int C>
+__device__ __forceinline__ void block_load(const BlockPos<HW, HALO, NW, C> &q, int64_t n0,
+                                           const typename V::T *__restrict__ x,
+                                           const typename V::T *__restrict__ b, bool vec,
+                                           typename V::A (&xr)[HW][C], typename V::A (&br)[HW][C])
+{
+    using A = typename V::A;
+    using ST = typename V::T;
+    if (q.interior) {
         if (C > 1 && vec) {
             using VT = BlockVec<ST, C>;
 #pragma unroll
             for (int r = 0; r < HW; ++r) {
-                const VT qx = *reinterpret_cast<const VT *>(x + p0 + r * n0);
-                const VT qb = *reinterpret_cast<const VT *>(b + p0 + r * n0);
+                const VT qx = *reinterpret_cast<const VT *>(x + q.p0 + r * n0);
+                const VT qb = *reinterpret_cast<const VT *>(b + q.p0 + r * n0);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     xr[r][c] = V::load(qx.v[c]);
@@ -143,25 +163,94 @@ __device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1, const typena
             for (int r = 0; r < HW; ++r)
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    xr[r][c] = V::load(x[p0 + r * n0 + c]);
-                    br[r][c] = V::load(b[p0 + r * n0 + c]);
+                    xr[r][c] = V::load(x[q.p0 + r * n0 + c]);
+                    br[r][c] = V::load(b[q.p0 + r * n0 + c]);
                 }
         }
-        bool col_in[C];
+        return;
+    }
 #pragma unroll
-        for (int c = 0; c < C; ++c) col_in[c] = true;
-        block_sweeps<V, HW, NW, C, false>(xr, br, col_in, ~0u, wlist, T, k2, edge, wave, lane);
-        // lanes whose columns are all output (HALO is a multiple of C)
-        if (lane * C >= HALO && lane * C < BW - HALO) {
+    for (int r = 0; r < HW; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const bool in = q.col_in[c] && ((q.rowbits >> r) & 1);
+            const int64_t p = (q.gy0 + r) * n0 + q.gx + c;
+            xr[r][c] = in ? V::load(x[p]) : A(0);
+            br[r][c] = in ? V::load(b[p]) : A(0);
+        }
+}
+
+template <class V, int HW, int HALO, int NW, int C>
+__device__ __forceinline__ void block_store(const BlockPos<HW, HALO, NW, C> &q, int64_t n0,
+                                            typename V::T *__restrict__ xo, bool vec,
+                                            const typename V::A (&xr)[HW][C])
+{
+    using ST = typename V::T;
+    if (!q.lane_out) return;
+    if (q.interior) {
+        if (C > 1 && vec) {
+            using VT = BlockVec<ST, C>;
+#pragma unroll
+            for (int r = 0; r < HW; ++r)
+                if (r >= q.rlo && r < q.rhi) {
+                    VT v;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) v.v[c] = V::store(xr[r][c]);
+                    *reinterpret_cast<VT *>(xo + q.p0 + r * n0) = v;
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < HW; ++r)
+                if (r >= q.rlo && r < q.rhi)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) xo[q.p0 + r * n0 + c] = V::store(xr[r][c]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < HW; ++r)
+        if (r >= q.rlo && r < q.rhi && ((q.rowbits >> r) & 1))
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q.col_in[c]) xo[(q.gy0 + r) * n0 + q.gx + c] = V::store(xr[r][c]);
+}
+
+// One block: load, T sweeps, store.  kbase continues the LDS buffer parity
+// of the workgroup's previous sweeps (0 for a fresh workgroup).
+template <class V, int HW, int HALO, int NW, int C>
+__device__ __forceinline__ void block2d_item(int64_t n0, int64_t n1,
+                                             const typename V::T *__restrict__ x,
+                                             typename V::T *__restrict__ xo,
+                                             const typename V::T *__restrict__ b,
+                                             const typename V::A *__restrict__ wlist, int T,
+                                             Coef2D<typename V::A> k2, int bx, int by, bool vec,
+                                             int wave, int lane, typename V::A *edge, int kbase)
+{
+    using A = typename V::A;
+    A xr[HW][C], br[HW][C];
+    {
+        // interior blocks: straight-line loads and stores, no masks
+        const BlockPos<HW, HALO, NW, C> q(n0, n1, bx, by, wave, lane);
+        if (q.interior) {
+            const int64_t p0 = q.p0;
+            const int rlo = q.rlo, rhi = q.rhi;
+            const bool lane_out = q.lane_out;
+            block_load<V, HW, HALO, NW, C>(q, n0, x, b, vec, xr, br);
+            bool all[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) all[c] = true;
+            block_sweeps<V, HW, NW, C, false>(xr, br, all, ~0u, wlist, T, k2, edge, wave, lane,
+                                              kbase);
+            if (!lane_out) return;
             if (C > 1 && vec) {
-                using VT = BlockVec<ST, C>;
+                using VT = BlockVec<typename V::T, C>;
 #pragma unroll
                 for (int r = 0; r < HW; ++r)
                     if (r >= rlo && r < rhi) {
-                        VT q;
+                        VT v;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) q.v[c] = V::store(xr[r][c]);
-                        *reinterpret_cast<VT *>(xo + p0 + r * n0) = q;
+                        for (int c = 0; c < C; ++c) v.v[c] = V::store(xr[r][c]);
+                        *reinterpret_cast<VT *>(xo + p0 + r * n0) = v;
                     }
             } else {
 #pragma unroll
@@ -170,36 +259,17 @@ __device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1, const typena
 #pragma unroll
                         for (int c = 0; c < C; ++c) xo[p0 + r * n0 + c] = V::store(xr[r][c]);
             }
+            return;
         }
-        return;
     }
-    bool col_in[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) col_in[c] = gx + c >= 0 && gx + c < n0;
-    uint32_t rowbits = 0;
-#pragma unroll
-    for (int r = 0; r < HW; ++r)
-        if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= 1u << r;
-#pragma unroll
-    for (int r = 0; r < HW; ++r)
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const bool in = col_in[c] && ((rowbits >> r) & 1);
-            const int64_t p = (gy0 + r) * n0 + gx + c;
-            xr[r][c] = in ? V::load(x[p]) : A(0);
-            br[r][c] = in ? V::load(b[p]) : A(0);
-        }
-    block_sweeps<V, HW, NW, C, true>(xr, br, col_in, rowbits, wlist, T, k2, edge, wave, lane);
-    if (lane * C >= HALO && lane * C < BW - HALO) {
-#pragma unroll
-        for (int r = 0; r < HW; ++r)
-            if (r >= rlo && r < rhi && ((rowbits >> r) & 1))
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    if (col_in[c]) xo[(gy0 + r) * n0 + gx + c] = V::store(xr[r][c]);
-    }
+    const BlockPos<HW, HALO, NW, C> q(n0, n1, bx, by, wave, lane);
+    block_load<V, HW, HALO, NW, C>(q, n0, x, b, vec, xr, br);
+    block_sweeps<V, HW, NW, C, true>(xr, br, q.col_in, q.rowbits, wlist, T, k2, edge, wave, lane,
+                                     kbase);
+    block_store<V, HW, HALO, NW, C>(q, n0, xo, vec, xr);
 }
 
+// One block per workgroup.
 template <class V, int HW, int HALO, int NW, int C>
 __global__ __launch_bounds__(64 * NW) void k_block2d(int64_t n0, int64_t n1,
                                                      const typename V::T *__restrict__ x,
@@ -216,9 +286,9 @@ __global__ __launch_bounds__(64 * NW) void k_block2d(int64_t n0, int64_t n1,
     const int per_xcd = (nblocks + 7) / 8;
     const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (logical >= nblocks) return;  // whole block leaves
-    block2d_run<V, HW, HALO, NW, C>(n0, n1, x, xo, b, wlist, T, k2, logical % blocks_x,
-                                    logical / blocks_x, vec != 0, threadIdx.x >> 6,
-                                    threadIdx.x & 63, edge);
+    block2d_item<V, HW, HALO, NW, C>(n0, n1, x, xo, b, wlist, T, k2, logical % blocks_x,
+                                     logical / blocks_x, vec != 0, threadIdx.x >> 6,
+                                     threadIdx.x & 63, edge, 0);
 }
 
 template <class V, int HW, int HALO, int NW, int C>
@@ -245,18 +315,13 @@ hipError_t launch_block2d(int64_t n0, int64_t n1, const typename V::T *x, typena
 
 // (rows per wave, halo = most sweeps per launch, waves per block) of the
 // binary64 block plans: one column per lane (kind 7) and two (kind 8)
-#define SRJ_BLOCK_VARIANTS(X)                                                               \
-    X(8, 4, 8) X(8, 6, 8) X(8, 8, 8) X(8, 8, 16) X(12, 6, 8) X(12, 8, 6) X(12, 8, 8)          \
-    X(16, 6, 4) X(16, 8, 4) X(16, 8, 6) X(16, 8, 8) X(20, 8, 4) X(24, 8, 4)
-#define SRJ_BLOCK2_VARIANTS(X) \
-    X(4, 8, 8) X(4, 8, 16) X(6, 8, 8) X(8, 6, 8) X(8, 8, 4) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4) X(12, 8, 8)
+#define SRJ_BLOCK_VARIANTS(X) X(8, 4, 8) X(8, 6, 8) X(8, 8, 8) X(12, 8, 8) X(16, 6, 4) X(16, 8, 4)
+#define SRJ_BLOCK2_VARIANTS(X) X(4, 8, 8) X(8, 6, 8) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4)
 
 // the same for sweeps in binary32 arithmetic (two values per register pair
 // fewer, so taller waves fit)
-#define SRJ_INNER_BLOCK_VARIANTS(X)                                                         \
-    X(8, 6, 8) X(8, 8, 8) X(8, 8, 16) X(12, 6, 8) X(12, 8, 6) X(12, 8, 8) X(16, 6, 8)       \
-    X(16, 8, 4) X(16, 8, 8) X(24, 8, 4) X(24, 8, 8) X(32, 8, 4)
-#define SRJ_INNER_BLOCK2_VARIANTS(X) \
-    X(4, 8, 8) X(6, 8, 8) X(8, 8, 4) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4) X(12, 8, 8) X(16, 8, 4)
+#define SRJ_INNER_BLOCK_VARIANTS(X) \
+    X(8, 6, 8) X(8, 8, 8) X(12, 6, 8) X(12, 8, 8) X(16, 8, 4) X(24, 8, 4)
+#define SRJ_INNER_BLOCK2_VARIANTS(X) X(6, 8, 8) X(8, 8, 8) X(8, 10, 8) X(12, 8, 4)
 
 }  // namespace srj

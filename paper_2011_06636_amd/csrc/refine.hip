@@ -163,11 +163,11 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     TT *oo = static_cast<TT *>(dout);
     const TT *rr = static_cast<const TT *>(rhat);
     if (plan.kind == 7 || plan.kind == 8) {
-#define SRJ_GO1(HW, HL, NW)                                \
-    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+#define SRJ_GO1(HW, HL, NW)                                                         \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
         return launch_block2d<St, HW, HL, NW, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
-#define SRJ_GO2(HW, HL, NW)                                \
-    if (plan.by == HW && plan.occ == NW && plan.T <= HL) \
+#define SRJ_GO2(HW, HL, NW)                                                         \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
         return launch_block2d<St, HW, HL, NW, 2>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
         if (plan.kind == 7) { SRJ_INNER_BLOCK_VARIANTS(SRJ_GO1) }
         else { SRJ_INNER_BLOCK2_VARIANTS(SRJ_GO2) }

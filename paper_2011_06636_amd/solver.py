@@ -184,15 +184,17 @@ class BatchSolver:
             pass
 
     def set_plan(self, tile_rows: int, sweeps: int, steps_per_graph: int = 16,
-                 use_graph: bool = True) -> int:
-        return abi.srj_batch_set_plan(self.handle, tile_rows, sweeps, steps_per_graph, use_graph)
+                 use_graph: bool = True, waves_per_block: int = 1) -> int:
+        """waves_per_block 1: single-wave tiles; > 1: cooperative blocks."""
+        return abi.srj_batch_set_plan(self.handle, tile_rows, sweeps, waves_per_block,
+                                      steps_per_graph, use_graph)
 
     def autotune(self, precision: str = "f32", sweeps: int = 48) -> float:
         """Pick the fastest batch plan by timing; returns its us per sweep."""
         return abi.srj_batch_autotune(self.handle, precision, sweeps)
 
     def get_plan(self):
-        """(tile_rows, sweeps per step, steps per graph, use_graph)."""
+        """(tile_rows, sweeps per step, waves per block, steps per graph, use_graph)."""
         return abi.srj_batch_get_plan(self.handle)
 
     def zeros(self):

@@ -65,7 +65,8 @@ def test_batch_plans_identical(torch_cuda, orc):
     kw = dict(tol=1e-10, precision="f32", max_cycles=200)
     base = None
     for plan in [(24, 4, 16, True), (16, 2, 3, True), (32, 6, 7, True), (48, 8, 16, True),
-                 (24, 1, 5, False), (32, 4, 1, False)]:
+                 (24, 1, 5, False), (32, 4, 1, False), (8, 8, 16, True, 8), (8, 3, 5, True, 8),
+                 (12, 8, 4, False, 8), (16, 5, 16, True, 4)]:
         assert bs.set_plan(*plan) == 0, plan
         out = bs.solve(**kw)
         got = [x.cpu().numpy() for x in out["xs"]]
@@ -105,8 +106,8 @@ def test_batch_autotune_keeps_results(torch_cuda, orc):
     ref_x = [x.cpu().numpy() for x in ref["xs"]]
     us = bs.autotune("f32", sweeps=24)
     assert us > 0
-    rows, T, _, _ = bs.get_plan()
-    assert rows in (16, 24, 32, 48) and T >= 1
+    rows, T, waves, _, _ = bs.get_plan()
+    assert (rows, waves) in ((16, 1), (24, 1), (32, 1), (48, 1), (8, 8), (12, 8), (16, 4)) and T >= 1
     out = bs.solve(**kw)
     for a, b in zip(out["xs"], ref_x):
         assert np.array_equal(a.cpu().numpy(), b)
