@@ -18,7 +18,9 @@ Unless --no-extras is given, the line also carries the other workloads'
 comparisons: the 256^3 variable-coefficient problem (binary64 vs
 binary32-refined time to 1e-10) and the two batches (512 2D problems,
 binary32-refined; 128 3D anisotropic boxes, bfloat16-stored correction),
-each batched solve against a loop of single-problem binary64 solves.
+each batched solve against a loop of single-problem binary64 solves, and the
+selector's training data of section 3 collected on the GPU at the paper's
+scale with the rule fitted to it.
 --copy-probe-mib runs one plain device copy of known size first (a reference
 dispatch for hardware byte counters).
 """
@@ -228,6 +230,79 @@ def extra_batch(which):
                                                             "median": float(np.median(errs))}}
 
 
+def extra_training(per_size=1_000_000, n_set=10000, z=1.96):
+    """Section 3 on the GPU: selector training data at the paper's scale, the
+    clusters, the rule fitted to them, and the CPU reference on a sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import Solver
+    sizes, flats, t_total, lups = [], [], 0.0, 0
+    for N in workloads.TRAINING_SIZES:
+        s = Solver(workloads.training_problem(N))
+        # a pilot sizes the run: trials for about per_size tuples, step cap 2x the longest
+        pilot = s.collect(torch.from_numpy(workloads.training_draws(256, 4000, seed=N)).cuda(),
+                          compact=True)
+        mean_steps = float(pilot["steps"].mean())
+        max_steps = int(min(4000, 2 * int(pilot["steps"].max()) + 16))
+        trials = int(np.ceil(per_size / (2.9 * mean_steps)))
+        u = torch.from_numpy(workloads.training_draws(trials, max_steps, seed=1000 + N)).cuda()
+        out, dt = _timed(lambda: s.collect(u, compact=True))
+        s.close()
+        flat = out["samples"][out["samples"]["M"] > 0]
+        t_total += dt
+        lups += (int(flat["M"].astype(np.int64).sum()) + trials) * N
+        flats.append(flat)
+        sizes.append({"N": N, "trials": trials, "tuples": int(len(flat)), "time_ms": round(dt * 1e3, 2),
+                      "capped_trials": int((out["steps"] == max_steps).sum())})
+        print(f"# training N={N}: {len(flat)} tuples, {dt * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    flat = np.concatenate(flats)
+    clusters, t_cl = _timed(lambda: abi.srj_cluster_samples(flat, n_set=n_set, z=z))
+    t_low, t_high, agree, decided = abi.srj_fit_rule(clusters)
+    dec = clusters[clusters["best"] != abi.SRJ_ACTION_NONE]
+
+    def agreement(lo, hi, cs=None):
+        ok = 0
+        for c in (dec if cs is None else cs):
+            r = float(c["mean_ratio"])
+            act = 1 if r > hi else (-1 if lo < r < hi else 0)
+            ok += int(act == int(c["best"]))
+        return ok
+    # does the best action depend on the level?  one rule, scored level by level
+    per_level = []
+    for lv in range(25):
+        cs = dec[dec["level"] == lv]
+        if len(cs):
+            per_level.append({"level": lv, "decided": int(len(cs)),
+                              "agree_fitted": agreement(t_low, t_high, cs),
+                              "agree_paper": agreement(0.2, 0.4, cs)})
+    # CPU reference on a bounded sample: N = 100, 64 trials
+    u = workloads.training_draws(64, 2000, seed=7)
+    ref, t_ref = _timed(lambda: oracle.collect(workloads.training_problem(100), u))
+    n_ref = int((ref["samples"]["M"] > 0).sum())
+    gpu100 = next(r for r in sizes if r["N"] == 100)
+    return {"workload": "section 3 data collection: 1D Poisson N in {2, 5, 10, 20, ..., 100, 200, "
+                        "300, 400}, b = 1, x0 = 0, random branch per step (seeded draws), trials "
+                        f"to about {per_size} tuples per size, stop at residual norm 1e-8; "
+                        f"clusters of {n_set} tuples per level, {z} sigma intervals",
+            "tuples": int(len(flat)), "time_ms": round(t_total * 1e3, 1),
+            "tuples_per_s": round(len(flat) / t_total, 1), "GLUPS": round(lups / t_total / 1e9, 3),
+            "sizes": sizes, "clusters": int(len(clusters)), "decided": int(decided),
+            "cluster_time_ms": round(t_cl * 1e3, 1),
+            "fitted_rule": {"t_low": t_low, "t_high": t_high, "agree": int(agree)},
+            "paper_rule": {"t_low": 0.2, "t_high": 0.4, "agree": agreement(0.2, 0.4)},
+            "per_level": per_level,
+            "cpu_reference_sample": {"N": 100, "trials": 64, "tuples": n_ref,
+                                     "time_ms": round(t_ref * 1e3, 1),
+                                     "tuples_per_s": round(n_ref / t_ref, 1),
+                                     "threads": oracle.num_threads(),
+                                     "gpu_tuples_per_s_N100": round(gpu100["tuples"] * 1e3 /
+                                                                    gpu100["time_ms"], 1)}}
+
+
 def run_leg(s, x, kw, steps, warmup, label):
     """warmup + timed solves; returns per-step times, results and the sweep profile."""
     import torch
@@ -353,7 +428,7 @@ def main():
     del x
     if not args.no_extras:
         rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
-                         "c5_batch_3d": extra_batch("c5")}
+                         "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training()}
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"])
     print(json.dumps(rec), flush=True)

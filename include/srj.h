@@ -251,6 +251,79 @@ srj_status srj_batch_get_plan(srj_batch *batch, int32_t *tile_rows, int32_t *swe
 srj_status srj_batch_solve(srj_batch *batch, double *const *xs, const srj_solve_opts *opts,
                            srj_solve_result *res, int32_t *levels_out);
 
+/* ---- Training data for the scheme selector (section 3) ----------------
+ *
+ * Data collection as in section 3: a trial starts from x = 0 and applies one
+ * level-0 cycle; then, at every step, the cycles of the levels one up, the
+ * same and one down (those within 0..max_level) are each applied to a copy
+ * of the current iterate, and one of them is taken at random.  Every branch
+ * is recorded with the state it started from (the current level and the
+ * residual ratio of the previous cycle) and the L2 residual norms before and
+ * after its cycle; the average convergence rate of the branch is
+ * -log(r_after / r_before) / M.  A trial ends once the residual norm of the
+ * iterate falls below tol (the paper uses 1e-8), or after max_steps steps. */
+typedef struct {
+    int32_t trial;       /* trial index */
+    int32_t step;        /* step within the trial (0 = the first step after the level-0 start) */
+    int32_t level;       /* state: scheme level before the step */
+    int32_t action;      /* +1 (level up), 0 (same level), -1 (level down) */
+    int32_t M;           /* factors of the branch's level; 0: action not available (no data) */
+    int32_t chosen;      /* 1 for the branch the trial continued with */
+    double prev_ratio;   /* state: residual ratio (after / before) of the previous cycle */
+    double r_before;     /* L2 residual norm of the iterate before the cycle */
+    double r_after;      /* L2 residual norm after the branch's cycle */
+} srj_sample;
+
+/* Runs `trials` independent trials on the context's problem (at most 1024
+ * grid points; x0 = 0; one workgroup per trial with the grid in LDS) and
+ * writes their samples to DEVICE memory: samples[(t * max_steps + s) * 3 + j]
+ * holds trial t, step s, action 1 - j (slots of actions that are not
+ * available have M = 0); steps[t] (DEVICE) receives the number of steps
+ * trial t took, and slots of later steps are left untouched.  u (DEVICE,
+ * trials * max_steps binary64 values in [0, 1)) supplies the random draws:
+ * step s of trial t takes available action floor(u[t * max_steps + s] * k)
+ * of the k available ones, in the order up, same, down.  Samples are
+ * bit-identical to a sequential reference (the library's sweep expression;
+ * every norm sums its squares in index order).  Synchronises the context's
+ * stream before returning.  SRJ_ERR_UNSUPPORTED for more than 1024 points;
+ * SRJ_ERR_INVALID for bad counts, tol <= 0 or max_level outside 0..24. */
+srj_status srj_collect(srj_ctx *ctx, int32_t trials, int32_t max_steps, const double *u, double tol,
+                       int32_t max_level, srj_sample *samples, int32_t *steps);
+
+#define SRJ_ACTION_NONE 2 /* srj_cluster.best when no action is confidently best */
+
+typedef struct {
+    int32_t level;        /* scheme level (state) of the cluster's samples */
+    int32_t count;        /* samples in the cluster (= n_set) */
+    double mean_ratio;    /* mean previous residual ratio of the cluster */
+    int32_t best;         /* best action (+1, 0, -1), or SRJ_ACTION_NONE */
+    int32_t n[3];         /* samples per action; index 0: up, 1: same, 2: down */
+    double mean_rate[3];  /* mean average convergence rate per action */
+    double half_width[3]; /* confidence half-width z * s / sqrt(n) (infinite for n < 2) */
+} srj_cluster;
+
+/* Post-processing of section 3 (host memory in and out, no GPU work):
+ * usable samples (M > 0, positive finite norms) are grouped by level, sorted
+ * by prev_ratio (stable, so ties keep input order) and cut into consecutive
+ * clusters of n_set samples (a trailing partial cluster is dropped; the
+ * paper uses n_set = 10000).  Per cluster and action: the mean rate and the
+ * half-width z * s / sqrt(n) of its confidence interval (z = 1.96 for 95 %).
+ * The action with the largest mean rate is the cluster's best if its
+ * interval lies strictly above the interval of every other action present;
+ * otherwise best = SRJ_ACTION_NONE.  Writes up to cap clusters (levels
+ * ascending, ratios ascending) and their total number to *n_out. */
+srj_status srj_cluster_samples(const srj_sample *samples, int64_t count, int32_t n_set, double z,
+                               srj_cluster *out, int32_t cap, int32_t *n_out);
+
+/* Fits the rule of Algorithm 1 (host memory): over the clusters with a best
+ * action, sorted by mean_ratio, chooses thresholds t_low <= t_high (halfway
+ * between neighbouring clusters) for "ratio > t_high: up; t_low < ratio <
+ * t_high: down; otherwise same" that agree with the most clusters (the
+ * first such split in ascending order).  *agree: clusters the rule agrees
+ * with; *decided: clusters with a best action. */
+srj_status srj_fit_rule(const srj_cluster *clusters, int32_t count, double *t_low, double *t_high,
+                        int32_t *agree, int32_t *decided);
+
 /* Batch autotuner: times every tile plan for `precision` on this batch,
  * `sweeps` sweeps of its 2D instances from x0 = 0 on the batch's own
  * buffers (no caller memory is touched), sets the fastest plan and writes its

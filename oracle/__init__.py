@@ -93,6 +93,9 @@ def load() -> ctypes.CDLL:
         lib.srjo_round_bf16.restype = ctypes.c_float
         lib.srjo_round_bf16.argtypes = [ctypes.c_float]
         lib.srjo_num_threads.restype = ctypes.c_int32
+        lib.srjo_collect.argtypes = [P(_Problem), ctypes.c_int32, ctypes.c_int32,
+                                     P(ctypes.c_double), ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_void_p, P(ctypes.c_int32)]
         _lib = lib
     return _lib
 
@@ -218,3 +221,24 @@ def round_bf16(v: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(load().srjo_num_threads())
+
+
+# Record layout of srjo_sample (section 3 tuples, one per branch).
+SAMPLE_DTYPE = np.dtype([("trial", "<i4"), ("step", "<i4"), ("level", "<i4"),
+                         ("action", "<i4"), ("M", "<i4"), ("chosen", "<i4"),
+                         ("prev_ratio", "<f8"), ("r_before", "<f8"), ("r_after", "<f8")])
+
+
+def collect(prob, u: np.ndarray, tol: float = 1e-8, max_level: int = 24) -> dict:
+    """Section 3 data collection: one trial per row of u (draws in [0, 1)).
+
+    Returns samples (SAMPLE_DTYPE, shape (trials, max_steps, 3); slots of
+    steps a trial did not take are zero) and steps (int32 per trial)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    trials, max_steps = u.shape
+    cp, keep = _cproblem(prob)
+    out = np.zeros((trials, max_steps, 3), dtype=SAMPLE_DTYPE)
+    steps = np.zeros(trials, dtype=np.int32)
+    load().srjo_collect(ctypes.byref(cp), trials, max_steps, _dptr(u), float(tol), int(max_level),
+                        out.ctypes.data, steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return {"samples": out, "steps": steps}

@@ -15,12 +15,15 @@
  *   - one SRJ cycle: M sweeps with the scheme's factors (section 2, Eq. 7);
  *   - residual: L2 norm of b - A x after each cycle (section 3) and the
  *     relative residual of section 4.2.3, Eq. (27);
- *   - selector: section 3, Algorithm 1.
+ *   - selector: section 3, Algorithm 1;
+ *   - training data for the selector: section 3, data collection (three
+ *     branches per step from the same iterate, one taken at random).
  * Arithmetic: IEEE binary64 (binary32 for the inner cycles of the
  * refinement modes, which are not in the paper), round to nearest even, no
  * contraction into fused multiply-add (-ffp-contract=off), no fast-math.
  * The only parallelism is an OpenMP loop over independent grid points inside
- * a sweep; sums are always taken sequentially in index order.
+ * a sweep, and one over independent trials of the data collection; sums are
+ * always taken sequentially in index order.
  */
 #include "srj_oracle.h"
 
@@ -587,4 +590,88 @@ done:
     free(rhat);
     free(w);
     return status;
+}
+
+/* ---- Section 3: data collection for the scheme selector ---------------- */
+
+/* One SRJ cycle of the given level applied to x in place (tmp: scratch). */
+static void apply_cycle(const srjo_problem *p, int32_t level, double *x, double *tmp)
+{
+    double w[2400];
+    int32_t M = srjo_scheme(level, w);
+    int64_t N = npoints(p);
+    for (int32_t j = 0; j < M; j++) {
+        srjo_sweep(p, x, w[j], tmp);
+        memcpy(x, tmp, sizeof(double) * (size_t)N);
+    }
+}
+
+void srjo_collect(const srjo_problem *p, int32_t trials, int32_t max_steps, const double *u,
+                  double tol, int32_t max_level, srjo_sample *out, int32_t *steps)
+{
+    int64_t N = npoints(p);
+#pragma omp parallel for schedule(dynamic)
+    for (int32_t t = 0; t < trials; t++) {
+        double *x = calloc((size_t)N, sizeof(double));
+        double *z = malloc(sizeof(double) * (size_t)N);
+        double *tmp = malloc(sizeof(double) * (size_t)N);
+        double *next = malloc(sizeof(double) * (size_t)N);
+        /* start: x = 0, one cycle of level 0; its residual ratio is the first state */
+        double r_init = srjo_residual_norm(p, x);
+        apply_cycle(p, 0, x, tmp);
+        double rcur = srjo_residual_norm(p, x);
+        double rho = rcur / r_init;
+        int32_t level = 0, taken = 0;
+        if (rcur >= tol && isfinite(rcur)) {
+            for (int32_t s = 0; s < max_steps; s++) {
+                /* the actions available from this level, in the order up, same, down */
+                int32_t acts[3], k = 0;
+                if (level + 1 <= max_level) acts[k++] = 1;
+                acts[k++] = 0;
+                if (level >= 1) acts[k++] = -1;
+                int32_t idx = (int32_t)(u[(int64_t)t * max_steps + s] * (double)k);
+                if (idx < 0) idx = 0;
+                if (idx > k - 1) idx = k - 1;
+                int32_t chosen = acts[idx];
+                double r_chosen = 0.0;
+                /* every available branch runs one cycle from the same iterate */
+                for (int32_t j = 0; j < 3; j++) {
+                    int32_t act = 1 - j;
+                    int avail = act == 0 || (act == 1 && level + 1 <= max_level) ||
+                                (act == -1 && level >= 1);
+                    srjo_sample *o = &out[((int64_t)t * max_steps + s) * 3 + j];
+                    o->trial = t;
+                    o->step = s;
+                    o->level = level;
+                    o->action = act;
+                    o->M = 0;
+                    o->chosen = act == chosen;
+                    o->prev_ratio = rho;
+                    o->r_before = rcur;
+                    o->r_after = 0.0;
+                    if (!avail) continue;
+                    memcpy(z, x, sizeof(double) * (size_t)N);
+                    apply_cycle(p, level + act, z, tmp);
+                    o->M = srjo_level_M(level + act);
+                    o->r_after = srjo_residual_norm(p, z);
+                    if (act == chosen) {
+                        memcpy(next, z, sizeof(double) * (size_t)N);
+                        r_chosen = o->r_after;
+                    }
+                }
+                /* continue with the branch taken */
+                memcpy(x, next, sizeof(double) * (size_t)N);
+                rho = r_chosen / rcur;
+                rcur = r_chosen;
+                level += chosen;
+                taken = s + 1;
+                if (!(rcur >= tol) || !isfinite(rcur)) break;
+            }
+        }
+        steps[t] = taken;
+        free(x);
+        free(z);
+        free(tmp);
+        free(next);
+    }
 }

@@ -87,6 +87,31 @@ void srjo_apply(const srjo_problem *p, const double *x, double *y);
 int32_t srjo_solve(const srjo_problem *p, double *x, const srjo_opts *o,
                    srjo_result *res, int32_t *levels_out, double *norms_out);
 
+/* Section 3, data collection for the scheme selector.  One record per
+ * branch; field meanings as in the paper's tuples (state: level and the
+ * residual ratio of the previous cycle; action; residual norms before and
+ * after the branch's cycle, from which the average convergence rate
+ * -log(r_after / r_before) / M follows). */
+typedef struct {
+    int32_t trial;
+    int32_t step;
+    int32_t level;
+    int32_t action;      /* +1, 0, -1 */
+    int32_t M;           /* 0: action not available at this level */
+    int32_t chosen;
+    double prev_ratio;
+    double r_before;
+    double r_after;
+} srjo_sample;
+
+/* trials independent trials from x = 0 (one level-0 cycle first), at most
+ * max_steps steps each, until the residual norm falls below tol; step s of
+ * trial t takes available action floor(u[t * max_steps + s] * k) of the k
+ * available ones (order: up, same, down).  out[(t * max_steps + s) * 3 + j]
+ * receives the branch of action 1 - j; steps[t] the steps taken. */
+void srjo_collect(const srjo_problem *p, int32_t trials, int32_t max_steps, const double *u,
+                  double tol, int32_t max_level, srjo_sample *out, int32_t *steps);
+
 /* Storage roundings used by the 16-bit refinement modes. */
 float srjo_round_f16(float v);
 float srjo_round_bf16(float v);

@@ -36,8 +36,11 @@ EXPORTS = [
     "srj_set_profiling",
     "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan", "srj_batch_get_plan",
     "srj_batch_autotune",
-    "srj_batch_solve", "srj_batch_destroy", "srj_last_error",
+    "srj_batch_solve", "srj_batch_destroy", "srj_collect", "srj_cluster_samples",
+    "srj_fit_rule", "srj_last_error",
 ]
+
+SRJ_ACTION_NONE = 2
 
 
 class SrjProblem(ctypes.Structure):
@@ -60,6 +63,28 @@ class SrjSolveResult(ctypes.Structure):
                 ("final_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("sweeps", ctypes.c_int64), ("r0", ctypes.c_double),
                 ("r_final", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+class SrjSample(ctypes.Structure):
+    _fields_ = [("trial", ctypes.c_int32), ("step", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("action", ctypes.c_int32), ("M", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("prev_ratio", ctypes.c_double), ("r_before", ctypes.c_double),
+                ("r_after", ctypes.c_double)]
+
+
+class SrjCluster(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("mean_ratio", ctypes.c_double), ("best", ctypes.c_int32),
+                ("n", ctypes.c_int32 * 3), ("mean_rate", ctypes.c_double * 3),
+                ("half_width", ctypes.c_double * 3)]
+
+
+# numpy views of the same layouts (for device buffers copied to the host)
+SAMPLE_DTYPE = [("trial", "<i4"), ("step", "<i4"), ("level", "<i4"), ("action", "<i4"),
+                ("M", "<i4"), ("chosen", "<i4"), ("prev_ratio", "<f8"), ("r_before", "<f8"),
+                ("r_after", "<f8")]
+CLUSTER_DTYPE = [("level", "<i4"), ("count", "<i4"), ("mean_ratio", "<f8"), ("best", "<i4"),
+                 ("n", "<i4", (3,)), ("mean_rate", "<f8", (3,)), ("half_width", "<f8", (3,))]
 
 
 _lib = None
@@ -98,6 +123,9 @@ def load() -> ctypes.CDLL:
         "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
+        "srj_collect": (i32, [vp, i32, i32, vp, f64, i32, vp, vp]),
+        "srj_cluster_samples": (i32, [vp, ctypes.c_int64, i32, f64, vp, i32, P(i32)]),
+        "srj_fit_rule": (i32, [vp, i32, P(f64), P(f64), P(i32), P(i32)]),
         "srj_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -252,3 +280,35 @@ def srj_batch_solve(batch, x_ptrs, opts: SrjSolveOpts, levels=None):
 def srj_batch_destroy(batch) -> None:
     if batch:
         load().srj_batch_destroy(batch)
+
+
+def srj_collect(ctx, trials: int, max_steps: int, u_ptr: int, tol: float, max_level: int,
+                samples_ptr: int, steps_ptr: int) -> None:
+    """Device pointers: u (trials * max_steps), samples (trials * max_steps * 3), steps."""
+    check(load().srj_collect(ctx, trials, max_steps, u_ptr, tol, max_level, samples_ptr,
+                             steps_ptr), "srj_collect")
+
+
+def srj_cluster_samples(samples, n_set: int = 10000, z: float = 1.96):
+    """samples: numpy array of SAMPLE_DTYPE (host); returns a CLUSTER_DTYPE array."""
+    import numpy as np
+    samples = np.ascontiguousarray(samples, dtype=SAMPLE_DTYPE)
+    n = ctypes.c_int32()
+    cap = len(samples) // max(n_set, 1) + 1  # bound on the number of whole clusters
+    out = np.zeros(cap, dtype=CLUSTER_DTYPE)
+    check(load().srj_cluster_samples(samples.ctypes.data if len(samples) else None, len(samples),
+                                     n_set, z, out.ctypes.data, cap, ctypes.byref(n)),
+          "srj_cluster_samples")
+    return out[:n.value]
+
+
+def srj_fit_rule(clusters):
+    """clusters: CLUSTER_DTYPE array; returns (t_low, t_high, agree, decided)."""
+    import numpy as np
+    clusters = np.ascontiguousarray(clusters, dtype=CLUSTER_DTYPE)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    ag, de = ctypes.c_int32(), ctypes.c_int32()
+    check(load().srj_fit_rule(clusters.ctypes.data if len(clusters) else None, len(clusters),
+                              ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(ag),
+                              ctypes.byref(de)), "srj_fit_rule")
+    return lo.value, hi.value, ag.value, de.value

@@ -148,6 +148,31 @@ class Solver:
             "norms": np.array(norms[:nc + 1], dtype=np.float64),
         }
 
+    def collect(self, u: torch.Tensor, tol: float = 1e-8, max_level: int = 24,
+                compact: bool = False) -> Dict:
+        """Selector training data (srj_collect): one trial per row of u.
+
+        u: float64 tensor (trials, max_steps) of draws in [0, 1) on this device.
+        Returns samples (SAMPLE_DTYPE, shape (trials, max_steps, 3); slots of
+        steps a trial did not take are zeroed) and steps (int32, trials).
+        With compact, samples is the flat array of the steps taken only
+        (trial, step, slot order), gathered on the device before the copy."""
+        trials, max_steps = u.shape
+        u = u.to(device=self.device, dtype=torch.float64).contiguous()
+        nbytes = np.dtype(abi.SAMPLE_DTYPE).itemsize
+        raw = torch.zeros(trials * max_steps * 3 * nbytes, dtype=torch.uint8, device=self.device)
+        steps = torch.zeros(trials, dtype=torch.int32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        abi.srj_collect(self.ctx, trials, max_steps, u.data_ptr(), tol, max_level,
+                        raw.data_ptr(), steps.data_ptr())
+        if compact:
+            rows = raw.view(trials, max_steps, 3 * nbytes)
+            taken = torch.arange(max_steps, device=self.device)[None, :] < steps[:, None]
+            flat = rows[taken].cpu().numpy().reshape(-1).view(abi.SAMPLE_DTYPE)
+            return {"samples": flat, "steps": steps.cpu().numpy()}
+        samples = raw.cpu().numpy().view(abi.SAMPLE_DTYPE).reshape(trials, max_steps, 3)
+        return {"samples": samples, "steps": steps.cpu().numpy()}
+
 
 class BatchSolver:
     """Many problems solved together: wraps srj_batch_setup / srj_batch_solve.

@@ -274,3 +274,19 @@ def c5_instance(i: int, lo: int = 32, hi: int = 128) -> Problem:
 
 def c5(count: int = 128, lo: int = 32, hi: int = 128) -> List[Problem]:
     return [c5_instance(i, lo, hi) for i in range(count)]
+
+
+# Section 3 data collection: the 1D Poisson training sizes and the random
+# draws that pick a branch at every step (the draws are inputs, so the GPU
+# collection and its CPU reference take the same walk).
+TRAINING_SIZES = (2, 5, 10, 20, 30, 40, 50, 60, 70, 80, 90, 100, 200, 300, 400)
+
+
+def training_problem(N: int) -> Problem:
+    """1D Poisson, N unknowns, h = 1/(N+1), b = 1 (section 3)."""
+    return poisson_1d(N, b=np.ones(N))
+
+
+def training_draws(trials: int, max_steps: int, seed: int) -> np.ndarray:
+    """Uniform draws in [0, 1), one per (trial, step)."""
+    return np.random.default_rng(seed).random((trials, max_steps))
