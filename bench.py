@@ -20,7 +20,8 @@ binary32-refined time to 1e-10) and the two batches (512 2D problems,
 binary32-refined; 128 3D anisotropic boxes, bfloat16-stored correction),
 each batched solve against a loop of single-problem binary64 solves, and the
 selector's training data of section 3 collected on the GPU at the paper's
-scale with the rule fitted to it.
+scale with the rule fitted to it, and the Neumann Laplace scaling study of
+section 4.2.2 with the per-sweep update stopping test.
 --copy-probe-mib runs one plain device copy of known size first (a reference
 dispatch for hardware byte counters).
 """
@@ -303,6 +304,49 @@ def extra_training(per_size=1_000_000, n_set=10000, z=1.96):
                                                                     gpu100["time_ms"], 1)}}
 
 
+def extra_neumann(sizes=(32, 64, 128, 256, 512, 1024), trials=10, tol=1e-10):
+    """Section 4.2.2: 2D Laplace with Neumann boundaries from random starts,
+    stopped by the largest update of a sweep; heuristic vs increasing rule."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads
+    from paper_2011_06636_amd.solver import Solver
+    rows = []
+    for n in sizes:
+        prob = workloads.neumann_laplace(n)
+        s = Solver(prob)
+        row = {"n": n, "unknowns": n * n}
+        for rule in ("heuristic", "increasing"):
+            sweeps, times = [], []
+            for t in range(trials):
+                x = s.to_device(workloads.random_start(prob, t))
+                torch.cuda.synchronize()
+                out, dt = _timed(lambda: s.solve(x, rule=rule, tol=tol, tol_mode="update_inf",
+                                                 max_cycles=100000, max_sweeps=2_000_000))
+                assert out["converged"], (n, rule, t)
+                sweeps.append(out["sweeps"])
+                times.append(dt)
+            row[rule] = {"mean_sweeps": float(np.mean(sweeps)), "min_sweeps": int(min(sweeps)),
+                         "max_sweeps": int(max(sweeps)), "mean_time_ms": round(1e3 * float(np.mean(times)), 3),
+                         "GLUPS": round(sum(sweeps) * n * n / sum(times) / 1e9, 3)}
+        s.close()
+        rows.append(row)
+        print(f"# neumann {n}: heuristic {row['heuristic']['mean_sweeps']:.0f} sweeps, increasing "
+              f"{row['increasing']['mean_sweeps']:.0f}", file=sys.stderr, flush=True)
+    prob = workloads.neumann_laplace(256)
+    ref, t_ref = _timed(lambda: oracle.solve(prob, workloads.random_start(prob, 0), rule="heuristic",
+                                             tol=tol, tol_mode="update_inf", max_cycles=100000))
+    return {"workload": "2D Laplace, homogeneous Neumann (ghost-node central differences, rows "
+                        "symmetrised), n x n nodes, b = 0, x0 ~ U(-1, 1) (seeds 0..9), stop when "
+                        f"max |x' - x| of a sweep < {tol:g}", "trials": trials, "sizes": rows,
+            "cpu_reference_sample": {"n": 256, "rule": "heuristic", "sweeps": ref["sweeps"],
+                                     "time_ms": round(t_ref * 1e3, 1),
+                                     "GLUPS": round(ref["sweeps"] * 256 * 256 / t_ref / 1e9, 3),
+                                     "threads": oracle.num_threads()}}
+
+
 def run_leg(s, x, kw, steps, warmup, label):
     """warmup + timed solves; returns per-step times, results and the sweep profile."""
     import torch
@@ -428,7 +472,8 @@ def main():
     del x
     if not args.no_extras:
         rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
-                         "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training()}
+                         "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training(),
+                         "neumann_update_test": extra_neumann()}
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"])
     print(json.dumps(rec), flush=True)

@@ -81,7 +81,14 @@ typedef enum {
     SRJ_RULE_FIXED = 2       /* fixed_level every cycle */
 } srj_rule;
 
-typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1 } srj_tol_mode;
+/* Stopping tests.  RELATIVE: cycle-end ||b - A x||_2 < tol * r0 (section
+ * 4.2.3, Eq. (27)).  ABSOLUTE: cycle-end ||b - A x||_2 < tol (section 4.1).
+ * UPDATE_INF: after every sweep, max_p |x'_p - x_p| < tol, the update norm
+ * of the 2D Laplace test with Neumann boundaries (section 4.2.2, Eq. (25));
+ * the selector still runs on cycle-end residual ratios.  UPDATE_INF needs
+ * precision SRJ_PREC_F64 and runs one sweep per launch, the update's maximum
+ * reduced in the sweep kernel; the solve stops at the exact sweep. */
+typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1, SRJ_TOL_UPDATE_INF = 2 } srj_tol_mode;
 
 #define SRJ_NUM_LEVELS 25
 #define SRJ_MAX_M 2362
@@ -148,9 +155,10 @@ srj_status srj_run_cycle(srj_ctx *ctx, double *x, int32_t level, double *resnorm
 srj_status srj_residual_norm(srj_ctx *ctx, const double *x, double *norm_out);
 
 /* Solve A x = b from the initial guess in x (device, in/out) with cycles
- * whose schemes the rule picks (Algorithm 1 by default), until the cycle-end
- * residual norm is below tol (times r0 for SRJ_TOL_RELATIVE) or a cap is
- * reached.  levels_out (host, max_cycles entries) receives the level of each
+ * whose schemes the rule picks (Algorithm 1 by default), until the stopping
+ * test of opts->tol_mode holds (see srj_tol_mode) or a cap is reached; with
+ * SRJ_TOL_UPDATE_INF, res->sweeps counts the sweeps up to the one that met
+ * the test and x holds that sweep's iterate.  levels_out (host, max_cycles entries) receives the level of each
  * cycle and norms_out (host, max_cycles + 1 entries) the initial norm and
  * each cycle-end norm; either may be NULL.  Returns SRJ_OK when converged,
  * SRJ_ERR_NOT_CONVERGED at a cap and SRJ_ERR_NONFINITE on a NaN/Inf norm,

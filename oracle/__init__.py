@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "srj_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 RULES = {"heuristic": 0, "increasing": 1, "fixed": 2, "jacobi": 3}
-TOL_MODES = {"relative": 0, "absolute": 1}
+TOL_MODES = {"relative": 0, "absolute": 1, "update_inf": 2}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 STATUS = {0: "ok", 1: "invalid", 4: "not_converged", 5: "nonfinite"}
 

@@ -248,7 +248,9 @@ static int32_t validate(const srjo_problem *p, const srjo_opts *o)
     if (o->rule == SRJO_RULE_FIXED && (o->fixed_level < 0 || o->fixed_level > 24))
         return SRJO_INVALID;
     if (o->precision < 0 || o->precision > 3) return SRJO_INVALID;
-    if (o->precision != SRJO_PREC_F64 && (o->stop_per_sweep || o->rule == SRJO_RULE_JACOBI))
+    if (o->tol_mode < 0 || o->tol_mode > 2) return SRJO_INVALID;
+    if (o->precision != SRJO_PREC_F64 &&
+        (o->stop_per_sweep || o->rule == SRJO_RULE_JACOBI || o->tol_mode == SRJO_TOL_UPDATE_INF))
         return SRJO_INVALID;
     return SRJO_OK;
 }
@@ -291,6 +293,9 @@ static int32_t solve_f64(const srjo_problem *p, double *x, const srjo_opts *o,
     res->r_final = r0;
     if (norms_out) norms_out[0] = r0;
     double target = (o->tol_mode == SRJO_TOL_RELATIVE) ? o->tol * r0 : o->tol;
+    /* section 4.2.2, Eq. (25): stop after the first sweep whose largest
+     * update max_p |x'_p - x_p| is below tol (a NaN update never passes) */
+    int update_test = o->tol_mode == SRJO_TOL_UPDATE_INF;
     int32_t status = SRJO_NOT_CONVERGED;
     int32_t level = o->start_level;
     double prev = r0;
@@ -299,7 +304,7 @@ static int32_t solve_f64(const srjo_problem *p, double *x, const srjo_opts *o,
         status = SRJO_NONFINITE;
         goto done;
     }
-    if (r0 == 0.0 || r0 < target) {
+    if (r0 == 0.0 || (!update_test && r0 < target)) {
         res->converged = 1;
         status = SRJO_OK;
         goto done;
@@ -313,14 +318,28 @@ static int32_t solve_f64(const srjo_problem *p, double *x, const srjo_opts *o,
             M = srjo_scheme(o->rule == SRJO_RULE_FIXED ? o->fixed_level : level, w);
         }
         if (res->sweeps + M > o->max_sweeps) break;
-        int stopped_mid_cycle = 0;
+        int stopped_mid_cycle = 0, update_met = 0;
         double norm = 0.0;
         for (int32_t k = 0; k < M; k++) {
             srjo_sweep(p, cur, w[k], nxt);
+            double umax = 0.0;
+            if (update_test) {
+                int nan_seen = 0;
+                for (int64_t i = 0; i < N; i++) {
+                    double d = fabs(nxt[i] - cur[i]);
+                    if (isnan(d)) nan_seen = 1;
+                    else if (d > umax) umax = d;
+                }
+                if (nan_seen) umax = NAN;
+            }
             double *t = cur;
             cur = nxt;
             nxt = t;
             res->sweeps += 1;
+            if (update_test && umax < o->tol) {
+                update_met = 1;
+                break;
+            }
             if (o->stop_per_sweep && k + 1 < M) {
                 double nk = srjo_residual_norm(p, cur);
                 if (nk < target) {
@@ -336,11 +355,16 @@ static int32_t solve_f64(const srjo_problem *p, double *x, const srjo_opts *o,
         res->final_level = (o->rule == SRJO_RULE_FIXED) ? o->fixed_level : level;
         if (levels_out) levels_out[cycle] = (o->rule == SRJO_RULE_JACOBI) ? -1 : res->final_level;
         if (norms_out) norms_out[cycle + 1] = norm;
+        if (update_met) {
+            res->converged = 1;
+            status = SRJO_OK;
+            break;
+        }
         if (!isfinite(norm)) {
             status = SRJO_NONFINITE;
             break;
         }
-        if (norm < target) {
+        if (!update_test && norm < target) {
             res->converged = 1;
             status = SRJO_OK;
             break;

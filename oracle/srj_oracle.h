@@ -37,7 +37,10 @@ typedef struct {
 
 enum { SRJO_RULE_HEURISTIC = 0, SRJO_RULE_INCREASING = 1, SRJO_RULE_FIXED = 2,
        SRJO_RULE_JACOBI = 3 };
-enum { SRJO_TOL_RELATIVE = 0, SRJO_TOL_ABSOLUTE = 1 };
+/* RELATIVE: cycle-end ||b - A x||_2 < tol * r0 (Eq. (27)); ABSOLUTE:
+ * cycle-end ||b - A x||_2 < tol (section 4.1); UPDATE_INF: after every
+ * sweep, max_p |x'_p - x_p| < tol (section 4.2.2, Eq. (25)), binary64 only. */
+enum { SRJO_TOL_RELATIVE = 0, SRJO_TOL_ABSOLUTE = 1, SRJO_TOL_UPDATE_INF = 2 };
 enum { SRJO_PREC_F64 = 0, SRJO_PREC_F32 = 1, SRJO_PREC_F16 = 2, SRJO_PREC_BF16 = 3 };
 enum { SRJO_OK = 0, SRJO_INVALID = 1, SRJO_NOT_CONVERGED = 4, SRJO_NONFINITE = 5 };
 

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "ok", 1: "invalid", 2: "nomem", 3: "hip", 4: "not_converged",
 
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 RULE = {"heuristic": 0, "increasing": 1, "fixed": 2}
-TOL_MODE = {"relative": 0, "absolute": 1}
+TOL_MODE = {"relative": 0, "absolute": 1, "update_inf": 2}
 NUM_LEVELS = 25
 MAX_M = 2362
 

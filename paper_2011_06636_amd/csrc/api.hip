@@ -61,7 +61,8 @@ srj_status validate_opts(const srj_solve_opts *o)
         return fail(SRJ_ERR_INVALID, "unknown rule");
     if (o->rule == SRJ_RULE_FIXED && (o->fixed_level < 0 || o->fixed_level >= SRJ_NUM_LEVELS))
         return fail(SRJ_ERR_INVALID, "fixed_level outside 0..24");
-    if (o->tol_mode != SRJ_TOL_RELATIVE && o->tol_mode != SRJ_TOL_ABSOLUTE)
+    if (o->tol_mode != SRJ_TOL_RELATIVE && o->tol_mode != SRJ_TOL_ABSOLUTE &&
+        o->tol_mode != SRJ_TOL_UPDATE_INF)
         return fail(SRJ_ERR_INVALID, "unknown tol_mode");
     if (!(o->tol > 0.0)) return fail(SRJ_ERR_INVALID, "tol must be > 0");
     if (o->max_cycles < 1) return fail(SRJ_ERR_INVALID, "max_cycles must be >= 1");
@@ -238,6 +239,7 @@ srj_status srj_destroy(srj_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     refine_free(c);
+    (void)hipFree(c->upd);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     (void)hipFree(c->ws);
@@ -402,6 +404,99 @@ srj_status srj_residual_norm(srj_ctx *c, const double *x, double *norm_out)
     return residual_norm(c, x, norm_out);
 }
 
+// Solve with the per-sweep update test (section 4.2.2, Eq. (25)): one sweep
+// per launch, sweep g reading buffer g % 2 and writing buffer (g + 1) % 2
+// (buffer 0 is x); the selector runs on cycle-end residual ratios as usual.
+// After each cycle the host reads the test state: a launch inside the cycle
+// may have found that an earlier sweep met the test (later launches then did
+// nothing), or the cycle's last sweep met it.
+static srj_status solve_update_inf(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                                   int32_t *levels_out, double *norms_out)
+{
+    if (!c->upd && hipMalloc(&c->upd, sizeof(UpdState)) != hipSuccess) {
+        c->upd = nullptr;
+        return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the update test state");
+    }
+    SRJ_HIP_CHECK(hipMemsetAsync(c->upd, 0, sizeof(UpdState), c->stream));
+    double *buf[2] = {x, c->ws};
+    double norm0 = 0.0;
+    srj_status st = residual_norm(c, x, &norm0);
+    if (st != SRJ_OK) return st;
+    res->r0 = o->r0 > 0.0 ? o->r0 : norm0;
+    res->r_final = norm0;
+    if (norms_out) norms_out[0] = norm0;
+    if (!isfinite(norm0)) return fail(SRJ_ERR_NONFINITE, "initial residual norm is not finite");
+    if (norm0 == 0.0) {
+        res->converged = 1;  // x solves the system: every update is zero
+        return SRJ_OK;
+    }
+    srj_status status = SRJ_ERR_NOT_CONVERGED;
+    int level = o->start_level;
+    double prev = norm0;
+    int64_t g = 0;       // sweeps enqueued
+    int64_t last = -1;   // the sweep whose iterate is the result
+    for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
+        const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
+        const std::vector<double> &w = level_factors(lv);
+        const int M = static_cast<int>(w.size());
+        if (g + M > o->max_sweeps) break;
+        for (int k = 0; k < M; ++k, ++g)
+            SRJ_HIP_CHECK(launch_sweep_upd(c->P, buf[g % 2], buf[(g + 1) % 2], w[k], o->tol, c->upd,
+                                           g, c->stream));
+        double norm = 0.0;
+        st = residual_norm(c, buf[g % 2], &norm);  // synchronises the stream
+        if (st != SRJ_OK) return st;
+        static thread_local UpdState h;
+        SRJ_HIP_CHECK(hipMemcpy(&h, c->upd, sizeof(h), hipMemcpyDeviceToHost));
+        unsigned long long lastmax = 0;  // fold the stripes of the cycle's last sweep
+        for (int k = 0; k < kUpdStripes; ++k)
+            lastmax = std::max(lastmax, h.maxbits[((g - 1) % 3) * kUpdStripes * kUpdStride + k * kUpdStride]);
+        int64_t stop = -1;
+        if (h.flag)
+            stop = h.stop;
+        else if (__builtin_bit_cast(double, lastmax) < o->tol)
+            stop = g - 1;
+        res->cycles = cycle + 1;
+        res->final_level = lv;
+        if (levels_out) levels_out[cycle] = lv;
+        if (stop >= 0) {
+            last = stop;
+            res->sweeps = stop + 1;
+            if (stop != g - 1) {  // the cycle-end norm belongs to a later, skipped sweep
+                st = residual_norm(c, buf[(stop + 1) % 2], &norm);
+                if (st != SRJ_OK) return st;
+            }
+            res->r_final = norm;
+            if (norms_out) norms_out[cycle + 1] = norm;
+            res->converged = 1;
+            status = SRJ_OK;
+            break;
+        }
+        last = g - 1;
+        res->sweeps = g;
+        res->r_final = norm;
+        if (norms_out) norms_out[cycle + 1] = norm;
+        if (!isfinite(norm)) {
+            status = fail(SRJ_ERR_NONFINITE, "residual norm is not finite");
+            break;
+        }
+        const double ratio = norm / prev;
+        prev = norm;
+        if (o->rule == SRJ_RULE_HEURISTIC) {
+            const double m = std::min(fabs(ratio - 0.2), fabs(ratio - 0.4));
+            res->min_margin = std::min(res->min_margin, m);
+        }
+        level = next_level(o->rule, level, ratio, o->max_level);
+    }
+    if (status == SRJ_ERR_NOT_CONVERGED) set_error("cycle or sweep cap reached");
+    double *result = last >= 0 ? buf[(last + 1) % 2] : x;
+    if (result != x)
+        SRJ_HIP_CHECK(hipMemcpyAsync(x, result, sizeof(double) * (size_t)c->npoints,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return status;
+}
+
 srj_status srj_run_cycle(srj_ctx *c, double *x, int32_t level, double *resnorm_out)
 {
     if (!c || !x || !resnorm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
@@ -423,6 +518,11 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     if (st != SRJ_OK) return st;
     memset(res, 0, sizeof(*res));
     res->min_margin = INFINITY;
+    if (o->tol_mode == SRJ_TOL_UPDATE_INF) {
+        if (o->precision != SRJ_PREC_F64)
+            return fail(SRJ_ERR_UNSUPPORTED, "the update test needs precision F64");
+        return solve_update_inf(c, x, o, res, levels_out, norms_out);
+    }
     if (o->precision != SRJ_PREC_F64) return refine_solve(c, x, o, res, levels_out, norms_out);
     if (c->resident && resident_fits(c->P)) return resident_solve(c, x, o, res, levels_out, norms_out);
 

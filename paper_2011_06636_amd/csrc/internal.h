@@ -83,6 +83,22 @@ struct SweepPlan {
 };
 hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo, double w,
                                 hipStream_t s);
+// Device state of the per-sweep update test: the largest |x' - x| of sweep g
+// accumulates in slot g % 3, spread over kUpdStripes stripes one 128-byte
+// line apart so that the blocks' atomic merges do not all hit one address
+// (bit patterns of non-negative doubles order like the values; a NaN orders
+// above everything).  The first launch that finds the previous sweep's
+// maximum below tol sets flag and stop = g - 1.
+constexpr int kUpdStripes = 64, kUpdStride = 16;
+struct UpdState {
+    unsigned long long maxbits[3 * kUpdStripes * kUpdStride];
+    int32_t flag, pad_;
+    int64_t stop;
+};
+// One sweep (global index g) that also reduces max |x' - x| and exits early
+// once an earlier sweep met the test.
+hipError_t launch_sweep_upd(const DevProblem &P, const double *x, double *xo, double w, double tol,
+                            UpdState *st, int64_t g, hipStream_t s);
 // Fused sweeps: applies w[0..T-1] (device pointer into the scheme table).
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
                               double *xo, const double *w_dev, int T, hipStream_t s);
@@ -123,6 +139,7 @@ struct srj_ctx {
     bool resident = false;      // binary64 solves of small grids run in one workgroup
     srj::SweepPlan plan_inner;  // inner sweeps of the refinement modes
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
+    srj::UpdState *upd = nullptr;          // per-sweep update test (lazily allocated)
     // Profiling: HIP events around the sweep launches of each cycle.
     bool profiling = false;
     bool prof_pending = false;

@@ -56,6 +56,78 @@ __global__ __launch_bounds__(kGenericBlock) void k_sweep_generic(DevProblem P,
     xo[p] = xc + w * t;
 }
 
+// The generic sweep with the update test of the Neumann Laplace problem
+// (section 4.2.2, Eq. (25)): the same per-point expression, plus the largest
+// |x' - x| of the sweep, reduced per block and merged with one 64-bit atomic
+// max into one of 64 stripes (a maximum does not depend on the order or the
+// grouping of the merges).  A launch whose
+// predecessor's maximum is below tol does nothing but record the stop; so do
+// all later launches.
+template <int ND>
+__global__ __launch_bounds__(kGenericBlock) void k_sweep_upd(DevProblem P, const double *__restrict__ x,
+                                                             double *__restrict__ xo, double w,
+                                                             double tol, UpdState *st, int64_t g)
+{
+    __shared__ unsigned long long red[kGenericBlock / 64];
+    constexpr int kSlot = kUpdStripes * kUpdStride;
+    const int lane = threadIdx.x & 63;
+    const bool lead_block = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
+    if (st->flag) return;  // an earlier sweep met the test
+    if (g > 0) {
+        // every wave folds the previous sweep's stripes (one per lane)
+        unsigned long long m = st->maxbits[((g - 1) % 3) * kSlot + lane * kUpdStride];
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m, off);
+            m = o > m ? o : m;
+        }
+        if (__longlong_as_double((long long)m) < tol) {
+            if (lead_block && threadIdx.x == 0) {
+                st->flag = 1;
+                st->stop = g - 1;
+            }
+            return;
+        }
+    }
+    if (lead_block && threadIdx.x < 64)  // the slot of the next sweep
+        st->maxbits[((g + 1) % 3) * kSlot + lane * kUpdStride] = 0ull;
+    const int64_t i0 = (int64_t)blockIdx.x * kGenericBlock + threadIdx.x;
+    unsigned long long d = 0ull;
+    if (i0 < P.n0) {
+        const int64_t i1 = blockIdx.y, i2 = blockIdx.z;
+        const int64_t s1 = P.n0, s2 = P.n0 * P.n1;
+        const int64_t p = i0 + s1 * i1 + s2 * i2;
+        const double xc = x[p];
+        double s = (P.diag ? P.diag[p] : P.dconst) * xc;
+        if (i0 > 0) s = s - (P.face[0] ? P.face[0][p - 1] : P.c[0]) * x[p - 1];
+        if (i0 < P.n0 - 1) s = s - (P.face[0] ? P.face[0][p] : P.c[0]) * x[p + 1];
+        if (ND >= 2) {
+            if (i1 > 0) s = s - (P.face[1] ? P.face[1][p - s1] : P.c[1]) * x[p - s1];
+            if (i1 < P.n1 - 1) s = s - (P.face[1] ? P.face[1][p] : P.c[1]) * x[p + s1];
+        }
+        if (ND >= 3) {
+            if (i2 > 0) s = s - (P.face[2] ? P.face[2][p - s2] : P.c[2]) * x[p - s2];
+            if (i2 < P.n2 - 1) s = s - (P.face[2] ? P.face[2][p] : P.c[2]) * x[p + s2];
+        }
+        const double r = P.b[p] - s;
+        const double t = (P.diag ? P.dinv[p] : P.dinvconst) * r;
+        const double xn = xc + w * t;
+        xo[p] = xn;
+        d = (unsigned long long)__double_as_longlong(fabs(xn - xc));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(d, off);
+        d = o > d ? o : d;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = red[0];
+        for (int i = 1; i < kGenericBlock / 64; ++i) m = red[i] > m ? red[i] : m;
+        const int stripe = (int)((blockIdx.x + (uint64_t)gridDim.x * (blockIdx.y + (uint64_t)gridDim.y * blockIdx.z)) % kUpdStripes);
+        atomicMax(&st->maxbits[(g % 3) * kSlot + stripe * kUpdStride], m);
+    }
+}
+
 __global__ void k_dinv(const double *__restrict__ d, double *__restrict__ dinv, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,6 +155,19 @@ hipError_t compute_dinv(const double *diag, double *dinv, int64_t n, hipStream_t
 {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_dinv, dim3((unsigned)blocks), dim3(256), 0, s, diag, dinv, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_upd(const DevProblem &P, const double *x, double *xo, double w, double tol,
+                            UpdState *st, int64_t g, hipStream_t s)
+{
+    const dim3 grid((unsigned)((P.n0 + kGenericBlock - 1) / kGenericBlock), (unsigned)P.n1,
+                    (unsigned)P.n2);
+    switch (P.ndim) {
+    case 1: hipLaunchKernelGGL(k_sweep_upd<1>, grid, dim3(kGenericBlock), 0, s, P, x, xo, w, tol, st, g); break;
+    case 2: hipLaunchKernelGGL(k_sweep_upd<2>, grid, dim3(kGenericBlock), 0, s, P, x, xo, w, tol, st, g); break;
+    default: hipLaunchKernelGGL(k_sweep_upd<3>, grid, dim3(kGenericBlock), 0, s, P, x, xo, w, tol, st, g); break;
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,82 @@
+"""GPU parity of the update stopping test on the Neumann Laplace problem
+(section 4.2.2, Eq. (25)).
+
+srj_solve with SRJ_TOL_UPDATE_INF runs one sweep per launch and reduces the
+largest |x' - x| inside the sweep kernel; it must stop at the same sweep as
+the CPU reference, after the same levels, with the same iterate (the
+per-point expression is the reference's, so bit for bit).  Grids are ragged
+against the 256-point launch rows; one case stops inside a cycle, the full
+256 x 256 case of the paper runs both rules.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _both(orc, n, rule, seed, **kw):
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.neumann_laplace(n)
+    x0 = workloads.random_start(prob, seed)
+    s = Solver(prob)
+    try:
+        x = s.to_device(x0)
+        got = s.solve(x, rule=rule, tol=TOL, tol_mode="update_inf", **kw)
+        gx = x.cpu().numpy()
+    finally:
+        s.close()
+    ref = orc.solve(prob, x0, rule=rule, tol=TOL, tol_mode="update_inf", **kw)
+    return got, gx, ref
+
+
+@pytest.mark.parametrize("n,rule,seed", [(17, "heuristic", 0), (17, "increasing", 1),
+                                         (64, "heuristic", 2), (130, "heuristic", 3),
+                                         (257, "increasing", 4)])
+def test_update_stop_matches_reference(torch_cuda, orc, n, rule, seed):
+    got, gx, ref = _both(orc, n, rule, seed, max_cycles=100000)
+    assert got["status"] == ref["status"] == "ok"
+    assert got["sweeps"] == ref["sweeps"] and got["cycles"] == ref["cycles"]
+    assert np.array_equal(got["levels"], ref["levels"])
+    assert np.array_equal(gx.reshape(-1), ref["x"].reshape(-1))
+    assert got["r_final"] == pytest.approx(ref["r_final"], rel=1e-9)
+    # the stop almost never falls on a cycle's last sweep: it did stop inside one
+    assert got["sweeps"] <= sum(len(orc.scheme(int(lv))) for lv in got["levels"])
+
+
+def test_paper_grid_256(torch_cuda, orc):
+    for rule in ("heuristic", "increasing"):
+        got, gx, ref = _both(orc, 256, rule, 7, max_cycles=100000)
+        assert got["sweeps"] == ref["sweeps"]
+        assert np.array_equal(got["levels"], ref["levels"])
+        assert np.array_equal(gx.reshape(-1), ref["x"].reshape(-1))
+
+
+def test_sweep_cap(torch_cuda, orc):
+    got, gx, ref = _both(orc, 40, "heuristic", 9, max_sweeps=60)
+    assert got["status"] == ref["status"] == "not_converged"
+    assert got["sweeps"] == ref["sweeps"]
+    assert np.array_equal(gx.reshape(-1), ref["x"].reshape(-1))
+
+
+def test_update_test_needs_binary64(torch_cuda):
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.neumann_laplace(16)
+    s = Solver(prob)
+    with pytest.raises(abi.SrjError) as e:
+        s.solve(s.to_device(workloads.random_start(prob, 0)), tol=TOL, tol_mode="update_inf",
+                precision="f32")
+    assert e.value.status == abi.SRJ_ERR_UNSUPPORTED
+    s.close()

@@ -290,3 +290,40 @@ def training_problem(N: int) -> Problem:
 def training_draws(trials: int, max_steps: int, seed: int) -> np.ndarray:
     """Uniform draws in [0, 1), one per (trial, step)."""
     return np.random.default_rng(seed).random((trials, max_steps))
+
+
+def neumann_laplace(n: int) -> Problem:
+    """2D Laplace on the unit square with homogeneous Neumann boundaries
+    (section 4.2.2): n x n grid nodes, boundary nodes included, h = 1/(n-1).
+
+    Central differences with ghost nodes give the row 4 u_p - sum of the four
+    neighbours (times 1/h^2), where a boundary node's inward neighbour stands
+    in for the ghost and counts twice.  Halving every edge row and quartering
+    the corner rows (exact in binary arithmetic, and without effect on Jacobi
+    iterates, which are invariant under row scaling) makes the matrix
+    symmetric: couplings 1/h^2 between interior faces, 1/(2 h^2) along the
+    boundary, and D = the sum of a node's couplings, so A 1 = 0 (singular,
+    constant null space).  b = 0."""
+    assert n >= 2
+    c = float((n - 1) ** 2)
+    f0 = np.full((n, n), c)
+    f1 = np.full((n, n), c)
+    f0[0, :] *= 0.5       # faces along x on the rows y = 0 and y = 1
+    f0[-1, :] *= 0.5
+    f1[:, 0] *= 0.5       # faces along y on the columns x = 0 and x = 1
+    f1[:, -1] *= 0.5
+    f0[:, -1] = 0.0       # no neighbour beyond the last column / row
+    f1[-1, :] = 0.0
+    diag = np.zeros((n, n))
+    diag[:, :-1] += f0[:, :-1]
+    diag[:, 1:] += f0[:, :-1]
+    diag[:-1, :] += f1[:-1, :]
+    diag[1:, :] += f1[:-1, :]
+    faces = [f0.reshape(1, n, n), f1.reshape(1, n, n), None]
+    return Problem(2, (n, n, 1), (0.0, 0.0, 0.0), 0.0, np.zeros((1, n, n)), faces=faces,
+                   diag=diag.reshape(1, n, n), name=f"neumann_laplace_{n}")
+
+
+def random_start(prob: Problem, seed: int) -> np.ndarray:
+    """Random initial guess U(-1, 1) (section 4.2.2 starts from a random vector)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, prob.shape)
