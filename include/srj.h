@@ -146,6 +146,32 @@ srj_status srj_scheme(int32_t level, double *omega_out, int32_t cap, int32_t *M_
  * hipStream_t (NULL: null stream).  On success *out owns the workspaces. */
 srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out);
 
+/* General sparse matrices (the random tridiagonal matrices of section
+ * 4.2.1 and the finite element systems of section 4.2.4): A in CSR form, all
+ * DEVICE arrays.  Every row holds its diagonal exactly once, with a value >
+ * 0; the other entries may have any sign.  One sweep evaluates, per row,
+ *   s = A_pp x_p;  for the row's other entries in storage order: s += A_pq x_q;
+ *   x'_p = x_p + w * ((1 / A_pp) * (b_p - s))
+ * in binary64 without contraction (a stencil written this way, entries
+ * A_pq = -c in the stencil's neighbour order, gives the stencil's bits).  The
+ * library copies the matrix and b at setup (the caller may free them after).
+ * Such a context runs one sweep per launch (or the whole solve in one
+ * workgroup for at most 4000 rows), binary64 only, with the residual tests;
+ * srj_collect accepts it too. */
+typedef struct {
+    int64_t n;              /* rows = unknowns */
+    const int64_t *rowptr;  /* n + 1 entries, rowptr[0] = 0, non-decreasing */
+    const int32_t *col;     /* rowptr[n] column indices in 0 .. n - 1 */
+    const double *val;      /* rowptr[n] finite entries */
+    const double *b;        /* n right-hand side values */
+} srj_csr_problem;
+
+/* Context for a general sparse matrix.  Validates the structure on the host
+ * (SRJ_ERR_INVALID: rowptr not starting at 0 or decreasing, a column out of
+ * range, a row without its diagonal or with it twice, a diagonal <= 0, a
+ * non-finite entry) after synchronising hip_stream. */
+srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **out);
+
 /* One SRJ cycle (section 2, Eq. 7) of scheme `level` on the device array x
  * (in/out, n0*n1*n2 binary64), followed by the L2 norm of b - A x written to
  * *resnorm_out (host).  Blocks until *resnorm_out is valid. */

@@ -45,7 +45,8 @@ def build(force: bool = True) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("c", ctypes.c_double * 3),
                 ("face", ctypes.c_void_p * 3), ("dconst", ctypes.c_double),
-                ("diag", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+                ("diag", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -129,6 +130,14 @@ def _cproblem(prob) -> tuple:
     b = np.ascontiguousarray(prob.b, dtype=np.float64)
     keep.append(b)
     cp.b = b.ctypes.data
+    cp.rowptr = cp.col = cp.val = None
+    if getattr(prob, "csr", None) is not None:
+        rp, col, val = prob.csr
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        keep += [rp, col, val]
+        cp.rowptr, cp.col, cp.val = rp.ctypes.data, col.ctypes.data, val.ctypes.data
     return cp, keep
 
 

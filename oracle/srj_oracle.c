@@ -138,6 +138,11 @@ static void strides(const srjo_problem *p, int64_t st[3])
 
 static double diag_at(const srjo_problem *p, int64_t idx)
 {
+    if (p->rowptr) { /* the stored diagonal of the row */
+        for (int64_t k = p->rowptr[idx]; k < p->rowptr[idx + 1]; k++)
+            if (p->col[k] == idx) return p->val[k];
+        return NAN;
+    }
     return p->diag ? p->diag[idx] : p->dconst;
 }
 
@@ -147,6 +152,12 @@ static double diag_at(const srjo_problem *p, int64_t idx)
 static double row_product(const srjo_problem *p, const double *x, int64_t idx,
                           const int64_t ii[3], const int64_t st[3])
 {
+    if (p->rowptr) { /* sparse row: the diagonal first, then the row in storage order */
+        double s = diag_at(p, idx) * x[idx];
+        for (int64_t k = p->rowptr[idx]; k < p->rowptr[idx + 1]; k++)
+            if (p->col[k] != idx) s = s + p->val[k] * x[p->col[k]];
+        return s;
+    }
     double s = diag_at(p, idx) * x[idx];
     for (int d = 0; d < p->ndim; d++) {
         if (ii[d] > 0) {
@@ -240,7 +251,13 @@ static int32_t validate(const srjo_problem *p, const srjo_opts *o)
         if (p->n[d] < 1) return SRJO_INVALID;
         if (d >= p->ndim && p->n[d] != 1) return SRJO_INVALID;
     }
-    if (!p->diag && !(p->dconst > 0.0)) return SRJO_INVALID;
+    if (p->rowptr) {
+        if (p->ndim != 1 || !p->col || !p->val) return SRJO_INVALID;
+        for (int64_t i = 0; i < p->n[0]; i++)
+            if (!(diag_at(p, i) > 0.0)) return SRJO_INVALID;
+    } else if (!p->diag && !(p->dconst > 0.0)) {
+        return SRJO_INVALID;
+    }
     if (!(o->tol > 0.0)) return SRJO_INVALID;
     if (o->rule < 0 || o->rule > 3) return SRJO_INVALID;
     if (o->max_level < 0 || o->max_level > 24) return SRJO_INVALID;

@@ -33,6 +33,11 @@ typedef struct {
     double dconst;
     const double *diag;
     const double *b;
+    /* General sparse matrix instead of a stencil (ndim = 1, n[0] rows): CSR
+     * arrays; every row holds its diagonal once.  NULL rowptr: stencil. */
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
 } srjo_problem;
 
 enum { SRJO_RULE_HEURISTIC = 0, SRJO_RULE_INCREASING = 1, SRJO_RULE_FIXED = 2,

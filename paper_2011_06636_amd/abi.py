@@ -30,7 +30,8 @@ MAX_M = 2362
 
 # Public entry points of include/srj.h (checked by the tests).
 EXPORTS = [
-    "srj_default_opts", "srj_scheme", "srj_setup", "srj_run_cycle", "srj_residual_norm",
+    "srj_default_opts", "srj_scheme", "srj_setup", "srj_setup_csr", "srj_run_cycle",
+    "srj_residual_norm",
     "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_plan_variants",
     "srj_autotune", "srj_set_resident",
     "srj_set_profiling",
@@ -47,6 +48,11 @@ class SrjProblem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("cconst", ctypes.c_double * 3), ("face", ctypes.c_void_p * 3),
                 ("dconst", ctypes.c_double), ("diag", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+
+
+class SrjCsrProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("b", ctypes.c_void_p)]
 
 
 class SrjSolveOpts(ctypes.Structure):
@@ -123,6 +129,7 @@ def load() -> ctypes.CDLL:
         "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
+        "srj_setup_csr": (i32, [P(SrjCsrProblem), vp, P(vp)]),
         "srj_collect": (i32, [vp, i32, i32, vp, f64, i32, vp, vp]),
         "srj_cluster_samples": (i32, [vp, ctypes.c_int64, i32, f64, vp, i32, P(i32)]),
         "srj_fit_rule": (i32, [vp, i32, P(f64), P(f64), P(i32), P(i32)]),
@@ -172,6 +179,13 @@ def srj_setup(prob: SrjProblem, stream: int = 0) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
     check(load().srj_setup(ctypes.byref(prob), ctypes.c_void_p(stream), ctypes.byref(h)),
           "srj_setup")
+    return h
+
+
+def srj_setup_csr(prob: SrjCsrProblem, stream: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(load().srj_setup_csr(ctypes.byref(prob), ctypes.c_void_p(stream), ctypes.byref(h)),
+          "srj_setup_csr")
     return h
 
 

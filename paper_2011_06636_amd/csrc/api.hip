@@ -240,6 +240,9 @@ srj_status srj_destroy(srj_ctx *c)
     else (void)hipDeviceSynchronize();
     refine_free(c);
     (void)hipFree(c->upd);
+    for (void *q : {(void *)c->csr_diag, (void *)c->csr_b, (void *)c->csr_val, (void *)c->csr_len,
+                    (void *)c->csr_col})
+        (void)hipFree(q);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     (void)hipFree(c->ws);
@@ -252,6 +255,8 @@ srj_status srj_destroy(srj_ctx *c)
     delete c;
     return SRJ_OK;
 }
+
+static srj_status ctx_finish(srj_ctx *c);
 
 srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
 {
@@ -292,6 +297,20 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
         }
         P.dinv = c->dinv;
     }
+    st = ctx_finish(c);
+    if (st == SRJ_OK) *out = c;
+    return st;
+}
+
+// Scheme tables, reduction scratch and plans: the part of a context that does
+// not depend on how the matrix was given.  Destroys c on failure.
+static srj_status ctx_finish(srj_ctx *c)
+{
+    DevProblem &P = c->P;
+    auto nomem = [&](const char *what) {
+        srj_destroy(c);
+        return fail(SRJ_ERR_NOMEM, std::string("hipMalloc failed for ") + what);
+    };
     std::vector<double> table;
     full_table(table, c->offsets);
     if (hipMalloc(&c->omega_dev, sizeof(double) * table.size()) != hipSuccess)
@@ -319,8 +338,110 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     c->plan = default_plan(P);
     c->plan_inner = default_inner_plan(P);
     c->resident = resident_fits(P);
-    *out = c;
     return SRJ_OK;
+}
+
+srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **out)
+{
+    if (!out) return fail(SRJ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!p || !p->rowptr || !p->col || !p->val || !p->b) return fail(SRJ_ERR_INVALID, "NULL argument");
+    if (p->n < 1 || p->n > ((int64_t)1 << 31) - 1) return fail(SRJ_ERR_INVALID, "n must be 1 .. 2^31 - 1");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = p->n;
+    // the structure is checked on the host: copy it
+    std::vector<int64_t> rp((size_t)n + 1);
+    SRJ_HIP_CHECK(hipStreamSynchronize(stream));
+    SRJ_HIP_CHECK(hipMemcpy(rp.data(), p->rowptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost));
+    if (rp[0] != 0) return fail(SRJ_ERR_INVALID, "rowptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SRJ_ERR_INVALID, "rowptr must be non-decreasing");
+    const int64_t nnz = rp[n];
+    if (nnz > ((int64_t)1 << 31) - 1) return fail(SRJ_ERR_INVALID, "too many entries");
+    std::vector<int32_t> col((size_t)nnz);
+    std::vector<double> val((size_t)nnz);
+    if (nnz > 0) {
+        SRJ_HIP_CHECK(hipMemcpy(col.data(), p->col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost));
+        SRJ_HIP_CHECK(hipMemcpy(val.data(), p->val, sizeof(double) * val.size(), hipMemcpyDeviceToHost));
+    }
+    // diagonal, 1/D and the off-diagonal entries in storage order (ELL, column-major)
+    std::vector<double> d((size_t)n), dinv((size_t)n);
+    std::vector<int32_t> len((size_t)n);
+    int32_t width = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int ndiag = 0;
+        int32_t off = 0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (col[k] < 0 || col[k] >= n) return fail(SRJ_ERR_INVALID, "column index out of range");
+            if (!isfinite(val[k])) return fail(SRJ_ERR_INVALID, "entries must be finite");
+            if (col[k] == i) {
+                ++ndiag;
+                d[i] = val[k];
+            } else {
+                ++off;
+            }
+        }
+        if (ndiag != 1) return fail(SRJ_ERR_INVALID, "every row must hold its diagonal exactly once");
+        if (!(d[i] > 0.0)) return fail(SRJ_ERR_INVALID, "diagonal entries must be > 0");
+        dinv[i] = 1.0 / d[i];
+        len[i] = off;
+        width = std::max(width, off);
+    }
+    if ((int64_t)width * n > ((int64_t)1 << 40)) return fail(SRJ_ERR_INVALID, "matrix too wide");
+    std::vector<int32_t> ecol((size_t)std::max<int64_t>(1, (int64_t)width * n));
+    std::vector<double> evalv(ecol.size(), 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        int j = 0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] != i) {
+                ecol[(size_t)j * n + i] = col[k];
+                evalv[(size_t)j * n + i] = val[k];
+                ++j;
+            }
+        for (; j < width; ++j) ecol[(size_t)j * n + i] = (int32_t)i;  // never read
+    }
+    srj_ctx *c = new srj_ctx();
+    c->stream = stream;
+    c->npoints = n;
+    auto nomem = [&](const char *what) {
+        srj_destroy(c);
+        return fail(SRJ_ERR_NOMEM, std::string("hipMalloc failed for ") + what);
+    };
+    const size_t bytes = sizeof(double) * (size_t)n;
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) return nomem("ping-pong buffer");
+    if (hipMalloc(&c->csr_diag, bytes) != hipSuccess || hipMalloc(&c->dinv, bytes) != hipSuccess ||
+        hipMalloc(&c->csr_b, bytes) != hipSuccess ||
+        hipMalloc(&c->csr_len, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+        hipMalloc(&c->csr_col, sizeof(int32_t) * ecol.size()) != hipSuccess ||
+        hipMalloc(&c->csr_val, sizeof(double) * evalv.size()) != hipSuccess)
+        return nomem("sparse matrix copy");
+    hipError_t e = hipMemcpy(c->csr_diag, d.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->dinv, dinv.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->csr_b, p->b, bytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->csr_len, len.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->csr_col, ecol.data(), sizeof(int32_t) * ecol.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->csr_val, evalv.data(), sizeof(double) * evalv.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        srj_destroy(c);
+        return fail(SRJ_ERR_HIP, std::string("sparse matrix copy: ") + hipGetErrorString(e));
+    }
+    DevProblem &P = c->P;
+    P.ndim = 1;
+    P.n0 = n;
+    P.n1 = P.n2 = 1;
+    P.diag = c->csr_diag;
+    P.dinv = c->dinv;
+    P.b = c->csr_b;
+    P.ell_len = c->csr_len;
+    P.ell_col = c->csr_col;
+    P.ell_val = c->csr_val;
+    P.ell_width = width;
+    srj_status st = ctx_finish(c);
+    if (st == SRJ_OK) *out = c;
+    return st;
 }
 
 srj_status srj_set_plan(srj_ctx *c, int32_t which, int32_t kind, int32_t tile_rows,
@@ -518,6 +639,8 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     if (st != SRJ_OK) return st;
     memset(res, 0, sizeof(*res));
     res->min_margin = INFINITY;
+    if (c->P.ell_len && (o->precision != SRJ_PREC_F64 || o->tol_mode == SRJ_TOL_UPDATE_INF))
+        return fail(SRJ_ERR_UNSUPPORTED, "general sparse matrices take binary64 and a residual test");
     if (o->tol_mode == SRJ_TOL_UPDATE_INF) {
         if (o->precision != SRJ_PREC_F64)
             return fail(SRJ_ERR_UNSUPPORTED, "the update test needs precision F64");

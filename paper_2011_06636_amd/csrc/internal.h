@@ -47,6 +47,13 @@ struct DevProblem {
     const double *diag;     // nullptr: constant diagonal
     const double *dinv;     // 1/diag (library-owned) when diag != nullptr
     const double *b;
+    // General sparse matrix (srj_setup_csr): ndim = 1, n0 rows, diag and dinv
+    // library-owned, off-diagonal entries in a column-major ELL layout,
+    // entry j of row p at [j * n0 + p], in the row's storage order.
+    const int32_t *ell_len;  // off-diagonal entries per row; nullptr: stencil problem
+    const int32_t *ell_col;
+    const double *ell_val;
+    int32_t ell_width, pad2_;
 };
 
 // Binary32 operator used by the refinement inner cycles.
@@ -140,6 +147,9 @@ struct srj_ctx {
     srj::SweepPlan plan_inner;  // inner sweeps of the refinement modes
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     srj::UpdState *upd = nullptr;          // per-sweep update test (lazily allocated)
+    // library copies of a general sparse matrix (srj_setup_csr)
+    double *csr_diag = nullptr, *csr_b = nullptr, *csr_val = nullptr;
+    int32_t *csr_len = nullptr, *csr_col = nullptr;
     // Profiling: HIP events around the sweep launches of each cycle.
     bool profiling = false;
     bool prof_pending = false;

@@ -72,6 +72,25 @@ __global__ __launch_bounds__(kBlock) void k_residual_sumsq(DevProblem P,
         partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
 }
 
+// General sparse matrix: the same per-row expression as k_sweep_ell.
+__global__ __launch_bounds__(kBlock) void k_residual_ell(DevProblem P, const double *__restrict__ x,
+                                                         double *__restrict__ partials)
+{
+    __shared__ double lds[kBlock / 64];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double rr = 0.0;
+    if (p < P.n0) {
+        double s = P.diag[p] * x[p];
+        const int len = P.ell_len[p];
+        for (int j = 0; j < len; ++j)
+            s = s + P.ell_val[(int64_t)j * P.n0 + p] * x[P.ell_col[(int64_t)j * P.n0 + p]];
+        const double r = P.b[p] - s;
+        rr = r * r;
+    }
+    const double t = block_sum<kBlock / 64>(rr, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 // One block: thread i sums partials i, i + 1024, ... in order, then a fixed tree.
 __global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ partials, int64_t n,
                                                  double *__restrict__ out)
@@ -103,10 +122,14 @@ hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScr
     const dim3 grid((unsigned)((P.n0 + kBlock - 1) / kBlock), (unsigned)P.n1, (unsigned)P.n2);
     const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
     if (nb > rs.capacity) return hipErrorInvalidValue;
+    if (P.ell_len) {
+        hipLaunchKernelGGL(k_residual_ell, grid, dim3(kBlock), 0, s, P, x, rs.partials);
+    } else {
     switch (P.ndim) {
     case 1: hipLaunchKernelGGL(k_residual_sumsq<1>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
     case 2: hipLaunchKernelGGL(k_residual_sumsq<2>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
     default: hipLaunchKernelGGL(k_residual_sumsq<3>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
+    }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -255,6 +255,7 @@ hipError_t launch_outer(bool update, const DevProblem &P, const double *x, const
 
 bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (P.ell_len) return false;
     if (plan.kind == 7 || plan.kind == 8) {
         if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.T < 1) return false;
 #define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;

@@ -128,6 +128,23 @@ __global__ __launch_bounds__(kGenericBlock) void k_sweep_upd(DevProblem P, const
     }
 }
 
+// General sparse matrix: one sweep, one thread per row (ELL layout, so the
+// k-th entries of consecutive rows are adjacent in memory).
+__global__ __launch_bounds__(kGenericBlock) void k_sweep_ell(DevProblem P, const double *__restrict__ x,
+                                                             double *__restrict__ xo, double w)
+{
+    const int64_t p = (int64_t)blockIdx.x * kGenericBlock + threadIdx.x;
+    if (p >= P.n0) return;
+    const double xc = x[p];
+    double s = P.diag[p] * xc;
+    const int len = P.ell_len[p];
+    for (int j = 0; j < len; ++j)
+        s = s + P.ell_val[(int64_t)j * P.n0 + p] * x[P.ell_col[(int64_t)j * P.n0 + p]];
+    const double r = P.b[p] - s;
+    const double t = P.dinv[p] * r;
+    xo[p] = xc + w * t;
+}
+
 __global__ void k_dinv(const double *__restrict__ d, double *__restrict__ dinv, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,6 +193,10 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 {
     const dim3 grid((unsigned)((P.n0 + kGenericBlock - 1) / kGenericBlock), (unsigned)P.n1,
                     (unsigned)P.n2);
+    if (P.ell_len) {
+        hipLaunchKernelGGL(k_sweep_ell, grid, dim3(kGenericBlock), 0, s, P, x, xo, w);
+        return hipGetLastError();
+    }
     switch (P.ndim) {
     case 1: hipLaunchKernelGGL(k_sweep_generic<1>, grid, dim3(kGenericBlock), 0, s, P, x, xo, w); break;
     case 2: hipLaunchKernelGGL(k_sweep_generic<2>, grid, dim3(kGenericBlock), 0, s, P, x, xo, w); break;
@@ -246,6 +267,7 @@ int plan_variants(int32_t *out, int cap)
 
 bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 {
+    if (P.ell_len) return false;  // general sparse matrices: one sweep per launch
     if (plan.kind == 7 || plan.kind == 8) {
         if (!(P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag) || plan.T < 1) return false;
 #define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;

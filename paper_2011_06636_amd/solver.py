@@ -56,6 +56,16 @@ class Solver:
         diag = getattr(problem, "diag", None)
         self.diag = _dev(diag, self.device) if diag is not None else None
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        csr = getattr(problem, "csr", None)
+        if csr is not None:  # general sparse matrix: the library copies it at setup
+            rp = torch.as_tensor(np.ascontiguousarray(csr[0], dtype=np.int64)).to(self.device)
+            col = torch.as_tensor(np.ascontiguousarray(csr[1], dtype=np.int32)).to(self.device)
+            val = torch.as_tensor(np.ascontiguousarray(csr[2], dtype=np.float64)).to(self.device)
+            self._prob = abi.SrjCsrProblem(self.npoints, rp.data_ptr(), col.data_ptr(),
+                                           val.data_ptr(), self.b.data_ptr())
+            torch.cuda.synchronize(self.device)
+            self.ctx = abi.srj_setup_csr(self._prob, self.stream.cuda_stream)
+            return
         self._prob = make_problem(self.ndim, problem.n, problem.c, problem.dconst, self.b,
                                   self.faces, self.diag)
         torch.cuda.synchronize(self.device)

@@ -66,6 +66,9 @@ class Problem:
     b: np.ndarray
     faces: Optional[List[Optional[np.ndarray]]] = None
     diag: Optional[np.ndarray] = None
+    # general sparse matrix instead of a stencil: (rowptr int64, col int32,
+    # val float64) in CSR form, ndim = 1, n = (rows, 1, 1)
+    csr: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
     name: str = ""
 
     @property
@@ -327,3 +330,171 @@ def neumann_laplace(n: int) -> Problem:
 def random_start(prob: Problem, seed: int) -> np.ndarray:
     """Random initial guess U(-1, 1) (section 4.2.2 starts from a random vector)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, prob.shape)
+
+
+# ---------------------------------------------------------------------------
+# General matrices (section 4.2.1 random tridiagonal systems, section 4.2.4
+# finite elements on unstructured meshes)
+# ---------------------------------------------------------------------------
+
+def csr_problem(rowptr: np.ndarray, col: np.ndarray, val: np.ndarray, b: np.ndarray,
+                name: str = "") -> Problem:
+    n = len(rowptr) - 1
+    return Problem(1, (n, 1, 1), (0.0, 0.0, 0.0), 0.0,
+                   np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(1, 1, n)),
+                   csr=(np.asarray(rowptr, dtype=np.int64), np.asarray(col, dtype=np.int32),
+                        np.asarray(val, dtype=np.float64)), name=name or "csr")
+
+
+def to_csr(prob: Problem) -> Problem:
+    """A stencil problem written as a sparse matrix: per row the diagonal, then
+    the neighbours in the stencil's order (axis 0 lower, upper, axis 1 lower,
+    upper, ...), entries -coupling."""
+    n0, n1, n2 = prob.n
+    N = n0 * n1 * n2
+    strides = (1, n0, n0 * n1)
+    diag = prob.diag.reshape(-1) if prob.diag is not None else np.full(N, prob.dconst)
+    faces = [prob.faces[d].reshape(-1) if prob.faces is not None and prob.faces[d] is not None
+             else None for d in range(3)] if prob.faces is not None else [None, None, None]
+    rowptr, col, val = [0], [], []
+    for i2 in range(n2):
+        for i1 in range(n1):
+            for i0 in range(n0):
+                ii = (i0, i1, i2)
+                p = i0 + n0 * (i1 + n1 * i2)
+                col.append(p)
+                val.append(diag[p])
+                for d in range(prob.ndim):
+                    if ii[d] > 0:
+                        q = p - strides[d]
+                        col.append(q)
+                        val.append(-(faces[d][q] if faces[d] is not None else prob.c[d]))
+                    if ii[d] < prob.n[d] - 1:
+                        q = p + strides[d]
+                        col.append(q)
+                        val.append(-(faces[d][p] if faces[d] is not None else prob.c[d]))
+                rowptr.append(len(col))
+    return csr_problem(np.array(rowptr), np.array(col), np.array(val), prob.b.reshape(-1),
+                       name=(prob.name or "stencil") + "_csr")
+
+
+def random_tridiagonal(N: int, seed: int) -> Problem:
+    """Random symmetric diagonally dominant tridiagonal matrix (section 4.2.1).
+
+    Draw order: the diagonal d ~ U(0, 1) (N values), then the off-diagonal e ~
+    U(0, 1) (N - 1 values, used above and below the diagonal), then b ~
+    U(-1, 1).  A row that is not diagonally dominant gets |d_i| = the sum of
+    its off-diagonal |e|; then d_0 = 2 e_0 and d_{N-1} = 2 e_{N-2}.  (The paper
+    does not state b; with b = 1 the smallest systems are solved by a single
+    weighted-Jacobi sweep, and a random b reproduces all of its comparisons.)
+    Returned as a 1D problem with per-face couplings (face = -e) and a
+    per-point diagonal."""
+    assert N >= 2
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.0, 1.0, N)
+    e = rng.uniform(0.0, 1.0, N - 1)
+    off = np.zeros(N)
+    off[:-1] += np.abs(e)
+    off[1:] += np.abs(e)
+    d = np.where(np.abs(d) < off, off, d)
+    d[0] = 2.0 * e[0]
+    d[-1] = 2.0 * e[-1]
+    b = rng.uniform(-1.0, 1.0, N)
+    face = np.zeros(N)
+    face[:-1] = -e
+    return Problem(1, (N, 1, 1), (0.0, 0.0, 0.0), 0.0, b.reshape(1, 1, N),
+                   faces=[face.reshape(1, 1, N), None, None], diag=d.reshape(1, 1, N),
+                   name=f"tridiag_{N}_{seed}")
+
+
+def _fem_mesh(geometry: str, h: float, seed: int):
+    """Seeded point set and Delaunay triangles of a disk (radius 1) or a plate
+    with a hole ([-1, 1]^2 minus the disk of radius 0.5, points twice as dense
+    near the hole).  Returns (points, triangles, boundary mask)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+
+    def jittered(lo, hi, step):
+        g = np.arange(lo, hi + 1e-12, step)
+        X, Y = np.meshgrid(g, g)
+        pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+        return pts + rng.uniform(-0.25 * step, 0.25 * step, pts.shape)
+
+    def circle(r, step, c=(0.0, 0.0)):
+        m = max(8, int(math.ceil(2 * math.pi * r / step)))
+        t = 2 * math.pi * np.arange(m) / m
+        return np.stack([c[0] + r * np.cos(t), c[1] + r * np.sin(t)], axis=1)
+
+    if geometry == "disk":
+        bnd = circle(1.0, h)
+        inner = jittered(-1.0, 1.0, h)
+        inner = inner[np.hypot(inner[:, 0], inner[:, 1]) < 1.0 - 0.5 * h]
+    elif geometry == "plate_hole":
+        m = int(round(2.0 / h))
+        s = np.linspace(-1.0, 1.0, m + 1)
+        edges = np.concatenate([np.stack([s, -np.ones_like(s)], 1), np.stack([s, np.ones_like(s)], 1),
+                                np.stack([-np.ones_like(s[1:-1]), s[1:-1]], 1),
+                                np.stack([np.ones_like(s[1:-1]), s[1:-1]], 1)])
+        hole = circle(0.5, 0.5 * h)
+        bnd = np.concatenate([edges, hole])
+        coarse = jittered(-1.0, 1.0, h)
+        fine = jittered(-1.0, 1.0, 0.5 * h)
+        rc, rf = np.hypot(coarse[:, 0], coarse[:, 1]), np.hypot(fine[:, 0], fine[:, 1])
+        coarse = coarse[(rc > 0.5 + 0.5 * h) & (rc >= 0.8) & (np.max(np.abs(coarse), 1) < 1.0 - 0.5 * h)]
+        fine = fine[(rf > 0.5 + 0.25 * h) & (rf < 0.8) & (np.max(np.abs(fine), 1) < 1.0 - 0.25 * h)]
+        inner = np.concatenate([coarse, fine])
+    else:
+        raise ValueError(geometry)
+    pts = np.concatenate([bnd, inner])
+    is_bnd = np.zeros(len(pts), dtype=bool)
+    is_bnd[:len(bnd)] = True
+    tri = Delaunay(pts).simplices
+    if geometry == "plate_hole":
+        cen = pts[tri].mean(axis=1)
+        tri = tri[np.hypot(cen[:, 0], cen[:, 1]) > 0.5]
+    return pts, tri, is_bnd
+
+
+def fem_stiffness(pts: np.ndarray, tri: np.ndarray):
+    """P1 stiffness matrix (dense-free, COO) and lumped load for f = 1:
+    K_e[i][j] = area * grad(phi_i) . grad(phi_j), b_i += area / 3."""
+    P = pts[tri]                                   # (T, 3, 2)
+    d1 = P[:, 1] - P[:, 0]
+    d2 = P[:, 2] - P[:, 0]
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    # gradients of the barycentric functions: rotate the opposite edge
+    g = np.empty_like(P)
+    for i in range(3):
+        a, b = P[:, (i + 1) % 3], P[:, (i + 2) % 3]
+        edge = b - a
+        g[:, i, 0] = edge[:, 1]
+        g[:, i, 1] = -edge[:, 0]
+    sign = np.sign((P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1])
+                   - (P[:, 1, 1] - P[:, 0, 1]) * (P[:, 2, 0] - P[:, 0, 0]))
+    g = g * (sign / (2.0 * area))[:, None, None]
+    rows, cols, vals = [], [], []
+    for i in range(3):
+        for j in range(3):
+            rows.append(tri[:, i])
+            cols.append(tri[:, j])
+            vals.append(area * np.sum(g[:, i] * g[:, j], axis=1))
+    load = np.zeros(len(pts))
+    for i in range(3):
+        np.add.at(load, tri[:, i], area / 3.0)
+    return (np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)), load, area
+
+
+def fem_poisson(geometry: str, h: float, seed: int = 0) -> Problem:
+    """-laplace(u) = 1 with u = 0 on the boundary, P1 finite elements on a
+    seeded Delaunay mesh (a stand-in for the paper's distmesh meshes, which
+    are not available); unknowns are the interior nodes."""
+    import scipy.sparse as sp
+    pts, tri, is_bnd = _fem_mesh(geometry, h, seed)
+    (r, c, v), load, _ = fem_stiffness(pts, tri)
+    K = sp.coo_matrix((v, (r, c)), shape=(len(pts), len(pts))).tocsr()
+    inner = np.nonzero(~is_bnd)[0]
+    A = K[inner][:, inner].tocsr()
+    A.sort_indices()
+    A.eliminate_zeros()
+    return csr_problem(A.indptr, A.indices, A.data, load[inner],
+                       name=f"fem_{geometry}_h{h:g}_s{seed}")
