@@ -21,7 +21,8 @@ binary32-refined; 128 3D anisotropic boxes, bfloat16-stored correction),
 each batched solve against a loop of single-problem binary64 solves, and the
 selector's training data of section 3 collected on the GPU at the paper's
 scale with the rule fitted to it, and the Neumann Laplace scaling study of
-section 4.2.2 with the per-sweep update stopping test.
+section 4.2.2 with the per-sweep update stopping test, and the general
+sparse matrices of sections 4.2.1 and 4.2.4.
 --copy-probe-mib runs one plain device copy of known size first (a reference
 dispatch for hardware byte counters).
 """
@@ -347,6 +348,89 @@ def extra_neumann(sizes=(32, 64, 128, 256, 512, 1024), trials=10, tol=1e-10):
                                      "threads": oracle.num_threads()}}
 
 
+def extra_general(big_h=0.003125):
+    """Sections 4.2.1 and 4.2.4: random tridiagonal systems and finite element
+    systems on unstructured meshes (heuristic vs increasing rule), and the
+    sparse-matrix sweep's throughput on a large mesh."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    from paper_2011_06636_amd.solver import Solver
+
+    def run(prob, rule, tol):
+        s = Solver(prob)
+        x = s.zeros()
+        s.solve(x, rule=rule, tol=tol, tol_mode="absolute", max_cycles=100000)
+        x.zero_()
+        out, dt = _timed(lambda: s.solve(x, rule=rule, tol=tol, tol_mode="absolute",
+                                         max_cycles=100000))
+        s.close()
+        assert out["converged"], (prob.name, rule)
+        return out["sweeps"], dt
+
+    tri = []
+    for N in (2, 5, 10, 20, 30, 40, 50, 60, 70, 80, 90, 100, 200, 300, 400, 500, 600, 700,
+              800, 900, 1000):
+        row = {"N": N}
+        for rule in ("heuristic", "increasing"):
+            sw = [run(workloads.random_tridiagonal(N, seed=k), rule, 1e-7)[0] for k in range(20)]
+            row[rule] = float(np.mean(sw))
+        tri.append(row)
+    print("# tridiagonal: " + ", ".join(f"{r['N']}: {r['heuristic']:.0f}/{r['increasing']:.0f}"
+                                        for r in tri), file=sys.stderr, flush=True)
+    fem = []
+    for geometry in ("disk", "plate_hole"):
+        for h in (0.1, 0.05, 0.025):
+            prob = workloads.fem_poisson(geometry, h, seed=0)
+            row = {"geometry": geometry, "h": h, "unknowns": prob.npoints,
+                   "nnz": int(len(prob.csr[2]))}
+            for rule in ("heuristic", "increasing"):
+                sw, dt = run(prob, rule, 1e-9)
+                row[rule] = {"sweeps": sw, "time_ms": round(dt * 1e3, 3)}
+            fem.append(row)
+            print(f"# fem {geometry} h={h}: {prob.npoints} unknowns, heuristic "
+                  f"{row['heuristic']['sweeps']} / increasing {row['increasing']['sweeps']} sweeps",
+                  file=sys.stderr, flush=True)
+    # throughput of the sparse sweep on a large mesh (one sweep per launch)
+    big = workloads.fem_poisson("plate_hole", big_h, seed=0)
+    n, nnz = big.npoints, int(len(big.csr[2]))
+    s = Solver(big)
+    x = s.zeros()
+    s.run_cycle(x, 12)
+    s.set_profiling(True)
+    s.run_cycle(x, 12)
+    ms, launches, sweeps = s.profile()
+    s.set_profiling(False)
+    kw = dict(tol=1e-9, tol_mode="absolute", max_cycles=100000)
+    x.zero_()
+    out, dt = _timed(lambda: s.solve(x, **kw))
+    s.close()
+    per_launch = ms / 1e3 / max(launches, 1)
+    # compulsory bytes per row: x, b, D, 1/D, the row length, x' (8+8+8+8+4+8) and
+    # 4 + 8 bytes per off-diagonal entry
+    alg = 44.0 * n + 12.0 * (nnz - n)
+    small = workloads.fem_poisson("plate_hole", 0.025, seed=0)
+    ref, t_ref = _timed(lambda: oracle.solve(small, **kw))
+    return {"workload": "random symmetric diagonally dominant tridiagonal systems (section "
+                        "4.2.1, 20 per size, b ~ U(-1, 1), residual norm 1e-7) and -laplace(u) = 1 "
+                        "with P1 finite elements on seeded Delaunay meshes of a disk and a plate "
+                        "with a hole (section 4.2.4, residual norm 1e-9); sweeps counted at cycle "
+                        "ends",
+            "tridiagonal_mean_sweeps": tri, "fem": fem,
+            "sparse_sweep": {"mesh": f"plate_hole h={big_h}", "rows": n, "nnz": nnz,
+                             "avg_launch_us": round(per_launch * 1e6, 3),
+                             "GLUPS": round(n / per_launch / 1e9, 3),
+                             "alg_bytes_per_launch": alg,
+                             "achieved_GBps": round(alg / per_launch / 1e9, 1),
+                             "frac_of_8TBps": round(alg / per_launch / 1e9 / HBM_PEAK_GBS, 4),
+                             "solve_sweeps": out["sweeps"], "solve_time_ms": round(dt * 1e3, 2)},
+            "cpu_reference_sample": {"mesh": "plate_hole h=0.025", "rows": small.npoints,
+                                     "sweeps": ref["sweeps"], "time_ms": round(t_ref * 1e3, 1),
+                                     "GLUPS": round(ref["sweeps"] * small.npoints / t_ref / 1e9, 3),
+                                     "threads": oracle.num_threads()}}
+
+
 def run_leg(s, x, kw, steps, warmup, label):
     """warmup + timed solves; returns per-step times, results and the sweep profile."""
     import torch
@@ -473,7 +557,8 @@ def main():
     if not args.no_extras:
         rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
                          "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training(),
-                         "neumann_update_test": extra_neumann()}
+                         "neumann_update_test": extra_neumann(),
+                         "general_matrices": extra_general()}
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"])
     print(json.dumps(rec), flush=True)
