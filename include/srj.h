@@ -172,6 +172,19 @@ typedef struct {
  * non-finite entry) after synchronising hip_stream. */
 srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **out);
 
+/* Replaces the context's scheme family (host arrays, copied): level l has
+ * M[l] factors, omegas holds the factors of level 0, then level 1, ... each
+ * in the order a cycle applies them.  nlevels = 0 restores the paper's family
+ * (Appendix B levels, Eq. (17) factors in the library's execution order, as
+ * srj_scheme returns them).  Later solves clamp max_level to nlevels - 1;
+ * a start or fixed level beyond it, or a run_cycle level beyond it, is
+ * SRJ_ERR_INVALID.  Batched solves always use the paper's family.
+ * Synchronises the context's stream.  SRJ_ERR_INVALID for nlevels outside
+ * 0..25, M[l] outside 1..2^20, more than 2^24 factors or a non-finite
+ * factor. */
+srj_status srj_set_scheme_family(srj_ctx *ctx, int32_t nlevels, const int32_t *M,
+                                 const double *omegas);
+
 /* One SRJ cycle (section 2, Eq. 7) of scheme `level` on the device array x
  * (in/out, n0*n1*n2 binary64), followed by the L2 norm of b - A x written to
  * *resnorm_out (host).  Blocks until *resnorm_out is valid. */

@@ -38,7 +38,7 @@ EXPORTS = [
     "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan", "srj_batch_get_plan",
     "srj_batch_autotune",
     "srj_batch_solve", "srj_batch_destroy", "srj_collect", "srj_cluster_samples",
-    "srj_fit_rule", "srj_last_error",
+    "srj_fit_rule", "srj_set_scheme_family", "srj_last_error",
 ]
 
 SRJ_ACTION_NONE = 2
@@ -130,6 +130,7 @@ def load() -> ctypes.CDLL:
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
         "srj_setup_csr": (i32, [P(SrjCsrProblem), vp, P(vp)]),
+        "srj_set_scheme_family": (i32, [vp, i32, P(i32), P(f64)]),
         "srj_collect": (i32, [vp, i32, i32, vp, f64, i32, vp, vp]),
         "srj_cluster_samples": (i32, [vp, ctypes.c_int64, i32, f64, vp, i32, P(i32)]),
         "srj_fit_rule": (i32, [vp, i32, P(f64), P(f64), P(i32), P(i32)]),
@@ -326,3 +327,15 @@ def srj_fit_rule(clusters):
                               ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(ag),
                               ctypes.byref(de)), "srj_fit_rule")
     return lo.value, hi.value, ag.value, de.value
+
+
+def srj_set_scheme_family(ctx, levels=None) -> None:
+    """levels: list of factor sequences (one per level, in application order);
+    None or [] restores the paper's family."""
+    if not levels:
+        check(load().srj_set_scheme_family(ctx, 0, None, None), "srj_set_scheme_family")
+        return
+    M = (ctypes.c_int32 * len(levels))(*[len(w) for w in levels])
+    flat = [float(v) for w in levels for v in w]
+    om = (ctypes.c_double * len(flat))(*flat)
+    check(load().srj_set_scheme_family(ctx, len(levels), M, om), "srj_set_scheme_family")

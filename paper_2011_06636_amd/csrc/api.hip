@@ -133,7 +133,7 @@ namespace srj {
 // after every launch so that *cur always names the latest iterate.
 srj_status run_sweeps(srj_ctx *c, double **cur, double **nxt, int level)
 {
-    const std::vector<double> &w = level_factors(level);
+    const std::vector<double> &w = c->factors[level];
     const int M = static_cast<int>(w.size());
     const double *wdev = c->omega_dev + c->offsets[level];
     int64_t launches = 0;
@@ -258,6 +258,47 @@ srj_status srj_destroy(srj_ctx *c)
 
 static srj_status ctx_finish(srj_ctx *c);
 
+// The paper's family: Appendix B levels, Eq. (17) factors in execution order.
+static void paper_family(srj_ctx *c)
+{
+    c->nlevels = SRJ_NUM_LEVELS;
+    c->levelM.resize(SRJ_NUM_LEVELS);
+    c->factors.resize(SRJ_NUM_LEVELS);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) {
+        c->levelM[l] = level_m(l);
+        c->factors[l] = level_factors(l);
+    }
+}
+
+// Concatenates the family into the device tables (binary64 and binary32) and
+// the per-level offsets; replaces earlier tables.  Synchronises the stream.
+static srj_status upload_family(srj_ctx *c)
+{
+    std::vector<double> table;
+    std::vector<int32_t> offs;
+    for (int l = 0; l < c->nlevels; ++l) {
+        offs.push_back((int32_t)table.size());
+        table.insert(table.end(), c->factors[l].begin(), c->factors[l].end());
+    }
+    offs.push_back((int32_t)table.size());
+    std::vector<float> table32(table.size());
+    for (size_t i = 0; i < table.size(); ++i) table32[i] = static_cast<float>(table[i]);
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));  // no kernel may still read the old tables
+    (void)hipFree(c->omega_dev);
+    (void)hipFree(c->omega32_dev);
+    c->omega_dev = nullptr;
+    c->omega32_dev = nullptr;
+    if (hipMalloc(&c->omega_dev, sizeof(double) * table.size()) != hipSuccess ||
+        hipMalloc(&c->omega32_dev, sizeof(float) * table.size()) != hipSuccess)
+        return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the scheme tables");
+    SRJ_HIP_CHECK(hipMemcpy(c->omega_dev, table.data(), sizeof(double) * table.size(),
+                            hipMemcpyHostToDevice));
+    SRJ_HIP_CHECK(hipMemcpy(c->omega32_dev, table32.data(), sizeof(float) * table32.size(),
+                            hipMemcpyHostToDevice));
+    c->offsets = offs;
+    return SRJ_OK;
+}
+
 srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
 {
     if (!out) return fail(SRJ_ERR_INVALID, "out is NULL");
@@ -311,19 +352,13 @@ static srj_status ctx_finish(srj_ctx *c)
         srj_destroy(c);
         return fail(SRJ_ERR_NOMEM, std::string("hipMalloc failed for ") + what);
     };
-    std::vector<double> table;
-    full_table(table, c->offsets);
-    if (hipMalloc(&c->omega_dev, sizeof(double) * table.size()) != hipSuccess)
-        return nomem("scheme table");
-    std::vector<float> table32(table.size());
-    for (size_t i = 0; i < table.size(); ++i) table32[i] = static_cast<float>(table[i]);
-    if (hipMalloc(&c->omega32_dev, sizeof(float) * table.size()) != hipSuccess)
-        return nomem("scheme table (binary32)");
-    hipError_t e = hipMemcpyAsync(c->omega_dev, table.data(), sizeof(double) * table.size(),
-                                  hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->omega32_dev, table32.data(), sizeof(float) * table32.size(),
-                           hipMemcpyHostToDevice, c->stream);
+    paper_family(c);
+    srj_status fs = upload_family(c);
+    if (fs != SRJ_OK) {
+        srj_destroy(c);
+        return fs;
+    }
+    hipError_t e = hipSuccess;
     c->rs.capacity = residual_blocks(P);
     if (e == hipSuccess && hipMalloc(&c->rs.partials, sizeof(double) * c->rs.capacity) != hipSuccess)
         return nomem("reduction partials");
@@ -339,6 +374,31 @@ static srj_status ctx_finish(srj_ctx *c)
     c->plan_inner = default_inner_plan(P);
     c->resident = resident_fits(P);
     return SRJ_OK;
+}
+
+srj_status srj_set_scheme_family(srj_ctx *c, int32_t nlevels, const int32_t *M, const double *omegas)
+{
+    if (!c) return fail(SRJ_ERR_INVALID, "ctx is NULL");
+    if (nlevels == 0) {  // back to the paper's family
+        paper_family(c);
+        return upload_family(c);
+    }
+    if (nlevels < 0 || nlevels > SRJ_NUM_LEVELS) return fail(SRJ_ERR_INVALID, "nlevels outside 0..25");
+    if (!M || !omegas) return fail(SRJ_ERR_INVALID, "NULL argument");
+    int64_t total = 0;
+    for (int l = 0; l < nlevels; ++l) {
+        if (M[l] < 1 || M[l] > (1 << 20)) return fail(SRJ_ERR_INVALID, "M must be 1 .. 2^20");
+        total += M[l];
+    }
+    if (total > (1 << 24)) return fail(SRJ_ERR_INVALID, "too many factors");
+    for (int64_t i = 0; i < total; ++i)
+        if (!isfinite(omegas[i])) return fail(SRJ_ERR_INVALID, "factors must be finite");
+    c->nlevels = nlevels;
+    c->levelM.assign(M, M + nlevels);
+    c->factors.assign(nlevels, {});
+    for (int l = 0, k = 0; l < nlevels; k += M[l], ++l)
+        c->factors[l].assign(omegas + k, omegas + k + M[l]);
+    return upload_family(c);
 }
 
 srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **out)
@@ -558,7 +618,7 @@ static srj_status solve_update_inf(srj_ctx *c, double *x, const srj_solve_opts *
     int64_t last = -1;   // the sweep whose iterate is the result
     for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
         const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
-        const std::vector<double> &w = level_factors(lv);
+        const std::vector<double> &w = c->factors[lv];
         const int M = static_cast<int>(w.size());
         if (g + M > o->max_sweeps) break;
         for (int k = 0; k < M; ++k, ++g)
@@ -621,7 +681,7 @@ static srj_status solve_update_inf(srj_ctx *c, double *x, const srj_solve_opts *
 srj_status srj_run_cycle(srj_ctx *c, double *x, int32_t level, double *resnorm_out)
 {
     if (!c || !x || !resnorm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
-    if (level < 0 || level >= SRJ_NUM_LEVELS) return fail(SRJ_ERR_INVALID, "level outside 0..24");
+    if (level < 0 || level >= c->nlevels) return fail(SRJ_ERR_INVALID, "level outside the scheme family");
     double *cur = x, *nxt = c->ws;
     srj_status st = run_sweeps(c, &cur, &nxt, level);
     if (st != SRJ_OK) return st;
@@ -637,6 +697,13 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     if (!c || !x || !res) return fail(SRJ_ERR_INVALID, "NULL argument");
     srj_status st = validate_opts(o);
     if (st != SRJ_OK) return st;
+    // the context's scheme family bounds the levels: the top level is clamped
+    // to it, a start or fixed level beyond it is an error
+    if (o->start_level >= c->nlevels || (o->rule == SRJ_RULE_FIXED && o->fixed_level >= c->nlevels))
+        return fail(SRJ_ERR_INVALID, "level outside the scheme family");
+    srj_solve_opts oc = *o;
+    oc.max_level = std::min(o->max_level, c->nlevels - 1);
+    o = &oc;
     memset(res, 0, sizeof(*res));
     res->min_margin = INFINITY;
     if (c->P.ell_len && (o->precision != SRJ_PREC_F64 || o->tol_mode == SRJ_TOL_UPDATE_INF))
@@ -669,7 +736,7 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     } else {
         for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
             const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
-            const int M = level_m(lv);
+            const int M = c->levelM[lv];
             if (res->sweeps + M > o->max_sweeps) break;
             st = run_sweeps(c, &cur, &nxt, lv);
             if (st != SRJ_OK) return st;

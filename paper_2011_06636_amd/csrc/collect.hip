@@ -180,11 +180,12 @@ srj_status srj_collect(srj_ctx *c, int32_t trials, int32_t max_steps, const doub
     if (!(tol > 0.0)) return fail(SRJ_ERR_INVALID, "tol must be > 0");
     if (max_level < 0 || max_level >= SRJ_NUM_LEVELS)
         return fail(SRJ_ERR_INVALID, "max_level outside 0..24");
+    max_level = std::min(max_level, c->nlevels - 1);  // the context's scheme family
     if (c->npoints > kCollectMax)
         return fail(SRJ_ERR_UNSUPPORTED, "collection problems hold at most 1024 points");
     const int64_t N = c->npoints;
     std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
-    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = level_m(l);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
     int32_t *lm = nullptr, *offs = nullptr;
     srj_status st = SRJ_OK;
     if (hipMalloc(&lm, sizeof(int32_t) * SRJ_NUM_LEVELS) != hipSuccess ||

@@ -141,6 +141,11 @@ struct srj_ctx {
     double *omega_dev = nullptr;   // all levels, execution order (binary64)
     float *omega32_dev = nullptr;  // the same table rounded to binary32
     std::vector<int32_t> offsets;  // level -> first factor in the tables
+    // the scheme family in use: the paper's Appendix B levels with the Eq.
+    // (17) factors in execution order, or one set by srj_set_scheme_family
+    int nlevels = 0;
+    std::vector<int32_t> levelM;
+    std::vector<std::vector<double>> factors;
     srj::ReduceScratch rs;
     srj::SweepPlan plan;        // binary64 sweeps
     bool resident = false;      // binary64 solves of small grids run in one workgroup

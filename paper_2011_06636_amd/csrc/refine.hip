@@ -509,7 +509,7 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
         void *da = R->da, *db = R->db;
         for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
             const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
-            const int M = level_m(lv);
+            const int M = c->levelM[lv];
             if (res->sweeps + M > o->max_sweeps) break;
             st = zero_storage<St>(c, da);
             if (st != SRJ_OK) return st;
@@ -526,7 +526,7 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
                     ++launches;
                 }
             } else {
-                const std::vector<double> &w = level_factors(lv);
+                const std::vector<double> &w = c->factors[lv];
                 for (int k = 0; k < M; ++k) {
                     SRJ_HIP_CHECK(launch_inner<St>(Q, da, db, R->rhat, static_cast<float>(w[k]),
                                                    c->stream));

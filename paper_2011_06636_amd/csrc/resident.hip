@@ -199,7 +199,7 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
     ResidentOut *dout = nullptr;
     int32_t *lm = nullptr;
     std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
-    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = level_m(l);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
     srj_status st = SRJ_OK;
     if (hipMalloc(&lh, sizeof(int32_t) * (size_t)o->max_cycles) != hipSuccess ||
         hipMalloc(&nh, sizeof(double) * ((size_t)o->max_cycles + 1)) != hipSuccess ||

@@ -158,6 +158,12 @@ class Solver:
             "norms": np.array(norms[:nc + 1], dtype=np.float64),
         }
 
+    def set_scheme_family(self, levels=None) -> None:
+        """Replace the scheme family (list of per-level factor lists, applied
+        in the given order); None restores the paper's family."""
+        torch.cuda.synchronize(self.device)
+        abi.srj_set_scheme_family(self.ctx, levels)
+
     def collect(self, u: torch.Tensor, tol: float = 1e-8, max_level: int = 24,
                 compact: bool = False) -> Dict:
         """Selector training data (srj_collect): one trial per row of u.
