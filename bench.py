@@ -37,11 +37,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the binary64 tile kernel on the 2048 x 2048 grid,
+# HBM bytes per launch of the binary64 block kernel on the 2048 x 2048 grid,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB device copy
 # (fetch x2.000, write x1.000).  Valid only for the kernel plan and source they
 # were taken with; any other plan reports null.
-MEASURED_TRAFFIC = {(7, 8, 8, 8): 104.8e6}
+MEASURED_TRAFFIC = {(8, 8, 10, 8): 106.8e6}
 # the same for the one-sweep reference kernel (plan kind 0)
 MEASURED_TRAFFIC_UNFUSED = 104.4e6
 

@@ -117,9 +117,14 @@ SweepPlan default_plan(const DevProblem &P)
         return pl;
     }
     if (P.ndim == 2 && !P.face[0] && !P.face[1] && !P.diag && P.n0 >= 64 && P.n1 >= 64) {
-        pl.kind = 7;  // blocks of 8 waves x 8 rows, 8 sweeps per launch
+        // blocks of 8 waves x 8 rows.  Grids of at least 512 blocks of 108 x 44
+        // written points (two per CU) take two columns per lane and 10 sweeps
+        // per launch; smaller grids, where a launch lasts about one block, take
+        // one column per lane and 8 sweeps per launch (shorter blocks).
+        const int64_t wide_blocks = ((P.n0 + 107) / 108) * ((P.n1 + 43) / 44);
+        pl.kind = wide_blocks >= 512 ? 8 : 7;
         pl.by = 8;
-        pl.T = 8;
+        pl.T = wide_blocks >= 512 ? 10 : 8;
         pl.occ = 8;
     }
     return pl;

@@ -100,123 +100,109 @@ __device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
     }
 }
 
-// Where one wave's part of block (bx, by) lies.
+// Block geometry: BW x BH values per block, halo included, of which the
+// centre OW x OH is written.
 template <int HW, int HALO, int NW, int C>
-struct BlockPos {
-    static constexpr int BW = 64 * C;         // columns per block, halo included
-    static constexpr int OW = BW - 2 * HALO;  // output columns per block
-    static constexpr int BH = NW * HW;        // rows per block, halo included
-    static constexpr int OH = BH - 2 * HALO;  // output rows per block
+struct BlockShape {
+    static constexpr int BW = 64 * C;
+    static constexpr int OW = BW - 2 * HALO;
+    static constexpr int BH = NW * HW;
+    static constexpr int OH = BH - 2 * HALO;
     static_assert(HW <= 32, "row validity is a 32-bit mask");
     static_assert(OH > 0 && OW > 0, "halo larger than the block");
     static_assert(HALO % C == 0, "lane columns must stay aligned");
-    int64_t gx, gy0, p0;  // first column of the lane, first row of the wave, flat index
-    bool interior;        // uniform over the block: both paths run the same barriers
-    bool col_in[C];
-    uint32_t rowbits;
-    int rlo, rhi;         // rows of this wave written back: block rows HALO .. BH - HALO - 1
-    bool lane_out;        // all C columns of the lane are output columns
+};
 
-    __device__ __forceinline__ BlockPos(int64_t n0, int64_t n1, int bx, int by, int wave, int lane)
-    {
-        const int64_t bx0 = (int64_t)bx * OW - HALO;
-        const int64_t by0 = (int64_t)by * OH - HALO;
-        gx = bx0 + (int64_t)lane * C;
-        gy0 = by0 + (int64_t)wave * HW;
-        p0 = gy0 * n0 + gx;
-        interior = bx0 >= 0 && bx0 + BW <= n0 && by0 >= 0 && by0 + BH <= n1;
+// One wave's part of one block: load, T sweeps, store.  Row addresses are a
+// wave-uniform row start plus a per-lane 32-bit column offset, so they cost
+// one vector register for all rows.  EDGE blocks cross the grid's edge: rows
+// outside it read a valid row (a wave-uniform clamp) and lanes outside it
+// read column 0, so every load stays in bounds and needs no branch, and a
+// select then makes every value outside the grid zero; such values stay zero
+// and are not written.  kbase continues the LDS buffer parity of the
+// workgroup's previous sweeps (0 for a fresh workgroup).
+template <class V, int HW, int HALO, int NW, int C, bool EDGE>
+__device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1,
+                                            const typename V::T *__restrict__ x,
+                                            typename V::T *__restrict__ xo,
+                                            const typename V::T *__restrict__ b,
+                                            const typename V::A *__restrict__ wlist, int T,
+                                            Coef2D<typename V::A> k2, int64_t bx0, int64_t by0,
+                                            bool vec, int wv, int lane, typename V::A *edge,
+                                            int kbase)
+{
+    using A = typename V::A;
+    using ST = typename V::T;
+    using VT = BlockVec<ST, C>;
+    using S = BlockShape<HW, HALO, NW, C>;
+    const int64_t gy0 = by0 + (int64_t)wv * HW;
+    // with C-wide vectors n0 is a multiple of C and so is bx0 + lane C: the C
+    // columns of a lane are inside or outside the grid together
+    bool col_in[C];
+    uint32_t off[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) col_in[c] = gx + c >= 0 && gx + c < n0;
+    for (int c = 0; c < C; ++c) {
+        const int64_t gx = bx0 + (int64_t)lane * C + c;
+        col_in[c] = !EDGE || (gx >= 0 && gx < n0);
+        off[c] = col_in[c] ? (uint32_t)gx : 0u;
+    }
+    uint32_t rowbits = ~0u;
+    if (EDGE) {
         rowbits = 0;
 #pragma unroll
         for (int r = 0; r < HW; ++r)
             if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= 1u << r;
-        rlo = HALO - wave * HW;
-        rhi = BH - HALO - wave * HW;
-        lane_out = lane * C >= HALO && lane * C < BW - HALO;
     }
-};
-
-template <class V, int HW, int HALO, int NW, int C>
-__device__ __forceinline__ void block_load(const BlockPos<HW, HALO, NW, C> &q, int64_t n0,
-                                           const typename V::T *__restrict__ x,
-                                           const typename V::T *__restrict__ b, bool vec,
-                                           typename V::A (&xr)[HW][C], typename V::A (&br)[HW][C])
-{
-    using A = typename V::A;
-    using ST = typename V::T;
-    if (q.interior) {
+    auto row_of = [&](int r) -> int64_t {  // a row inside the grid
+        const int64_t gy = gy0 + r;
+        return EDGE ? (gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy)) : gy;
+    };
+    A xr[HW][C], br[HW][C];
+#pragma unroll
+    for (int r = 0; r < HW; ++r) {
+        const ST *xrow = x + row_of(r) * n0;
+        const ST *brow = b + row_of(r) * n0;
+        const bool rin = (rowbits >> r) & 1;
         if (C > 1 && vec) {
-            using VT = BlockVec<ST, C>;
+            const VT qx = *reinterpret_cast<const VT *>(xrow + off[0]);
+            const VT qb = *reinterpret_cast<const VT *>(brow + off[0]);
 #pragma unroll
-            for (int r = 0; r < HW; ++r) {
-                const VT qx = *reinterpret_cast<const VT *>(x + q.p0 + r * n0);
-                const VT qb = *reinterpret_cast<const VT *>(b + q.p0 + r * n0);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    xr[r][c] = V::load(qx.v[c]);
-                    br[r][c] = V::load(qb.v[c]);
-                }
+            for (int c = 0; c < C; ++c) {
+                xr[r][c] = (!EDGE || (rin && col_in[c])) ? V::load(qx.v[c]) : A(0);
+                br[r][c] = (!EDGE || (rin && col_in[c])) ? V::load(qb.v[c]) : A(0);
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < HW; ++r)
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    xr[r][c] = V::load(x[q.p0 + r * n0 + c]);
-                    br[r][c] = V::load(b[q.p0 + r * n0 + c]);
-                }
+            for (int c = 0; c < C; ++c) {
+                const ST vx = xrow[off[c]], vb = brow[off[c]];
+                xr[r][c] = (!EDGE || (rin && col_in[c])) ? V::load(vx) : A(0);
+                br[r][c] = (!EDGE || (rin && col_in[c])) ? V::load(vb) : A(0);
+            }
         }
-        return;
     }
+    block_sweeps<V, HW, NW, C, EDGE>(xr, br, col_in, rowbits, wlist, T, k2, edge, wv, lane, kbase);
+    if (!(lane * C >= HALO && lane * C < S::BW - HALO)) return;
+    const int rlo = HALO - wv * HW, rhi = S::BH - HALO - wv * HW;
 #pragma unroll
-    for (int r = 0; r < HW; ++r)
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const bool in = q.col_in[c] && ((q.rowbits >> r) & 1);
-            const int64_t p = (q.gy0 + r) * n0 + q.gx + c;
-            xr[r][c] = in ? V::load(x[p]) : A(0);
-            br[r][c] = in ? V::load(b[p]) : A(0);
-        }
-}
-
-template <class V, int HW, int HALO, int NW, int C>
-__device__ __forceinline__ void block_store(const BlockPos<HW, HALO, NW, C> &q, int64_t n0,
-                                            typename V::T *__restrict__ xo, bool vec,
-                                            const typename V::A (&xr)[HW][C])
-{
-    using ST = typename V::T;
-    if (!q.lane_out) return;
-    if (q.interior) {
+    for (int r = 0; r < HW; ++r) {
+        if (r < rlo || r >= rhi || !((rowbits >> r) & 1)) continue;
+        ST *orow = xo + row_of(r) * n0;
         if (C > 1 && vec) {
-            using VT = BlockVec<ST, C>;
+            if (col_in[0]) {
+                VT v;
 #pragma unroll
-            for (int r = 0; r < HW; ++r)
-                if (r >= q.rlo && r < q.rhi) {
-                    VT v;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) v.v[c] = V::store(xr[r][c]);
-                    *reinterpret_cast<VT *>(xo + q.p0 + r * n0) = v;
-                }
+                for (int c = 0; c < C; ++c) v.v[c] = V::store(xr[r][c]);
+                *reinterpret_cast<VT *>(orow + off[0]) = v;
+            }
         } else {
 #pragma unroll
-            for (int r = 0; r < HW; ++r)
-                if (r >= q.rlo && r < q.rhi)
-#pragma unroll
-                    for (int c = 0; c < C; ++c) xo[q.p0 + r * n0 + c] = V::store(xr[r][c]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int r = 0; r < HW; ++r)
-        if (r >= q.rlo && r < q.rhi && ((q.rowbits >> r) & 1))
-#pragma unroll
             for (int c = 0; c < C; ++c)
-                if (q.col_in[c]) xo[(q.gy0 + r) * n0 + q.gx + c] = V::store(xr[r][c]);
+                if (col_in[c]) orow[off[c]] = V::store(xr[r][c]);
+        }
+    }
 }
 
-// One block: load, T sweeps, store.  kbase continues the LDS buffer parity
-// of the workgroup's previous sweeps (0 for a fresh workgroup).
+// One block (bx, by): interior blocks take the path without masks.
 template <class V, int HW, int HALO, int NW, int C>
 __device__ __forceinline__ void block2d_item(int64_t n0, int64_t n1,
                                              const typename V::T *__restrict__ x,
@@ -226,47 +212,16 @@ __device__ __forceinline__ void block2d_item(int64_t n0, int64_t n1,
                                              Coef2D<typename V::A> k2, int bx, int by, bool vec,
                                              int wave, int lane, typename V::A *edge, int kbase)
 {
-    using A = typename V::A;
-    A xr[HW][C], br[HW][C];
-    {
-        // interior blocks: straight-line loads and stores, no masks
-        const BlockPos<HW, HALO, NW, C> q(n0, n1, bx, by, wave, lane);
-        if (q.interior) {
-            const int64_t p0 = q.p0;
-            const int rlo = q.rlo, rhi = q.rhi;
-            const bool lane_out = q.lane_out;
-            block_load<V, HW, HALO, NW, C>(q, n0, x, b, vec, xr, br);
-            bool all[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) all[c] = true;
-            block_sweeps<V, HW, NW, C, false>(xr, br, all, ~0u, wlist, T, k2, edge, wave, lane,
-                                              kbase);
-            if (!lane_out) return;
-            if (C > 1 && vec) {
-                using VT = BlockVec<typename V::T, C>;
-#pragma unroll
-                for (int r = 0; r < HW; ++r)
-                    if (r >= rlo && r < rhi) {
-                        VT v;
-#pragma unroll
-                        for (int c = 0; c < C; ++c) v.v[c] = V::store(xr[r][c]);
-                        *reinterpret_cast<VT *>(xo + p0 + r * n0) = v;
-                    }
-            } else {
-#pragma unroll
-                for (int r = 0; r < HW; ++r)
-                    if (r >= rlo && r < rhi)
-#pragma unroll
-                        for (int c = 0; c < C; ++c) xo[p0 + r * n0 + c] = V::store(xr[r][c]);
-            }
-            return;
-        }
-    }
-    const BlockPos<HW, HALO, NW, C> q(n0, n1, bx, by, wave, lane);
-    block_load<V, HW, HALO, NW, C>(q, n0, x, b, vec, xr, br);
-    block_sweeps<V, HW, NW, C, true>(xr, br, q.col_in, q.rowbits, wlist, T, k2, edge, wave, lane,
-                                     kbase);
-    block_store<V, HW, HALO, NW, C>(q, n0, xo, vec, xr);
+    using S = BlockShape<HW, HALO, NW, C>;
+    const int64_t bx0 = (int64_t)bx * S::OW - HALO;
+    const int64_t by0 = (int64_t)by * S::OH - HALO;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    if (bx0 >= 0 && bx0 + S::BW <= n0 && by0 >= 0 && by0 + S::BH <= n1)
+        block2d_run<V, HW, HALO, NW, C, false>(n0, n1, x, xo, b, wlist, T, k2, bx0, by0, vec, wv,
+                                               lane, edge, kbase);
+    else
+        block2d_run<V, HW, HALO, NW, C, true>(n0, n1, x, xo, b, wlist, T, k2, bx0, by0, vec, wv,
+                                              lane, edge, kbase);
 }
 
 // One block per workgroup.
@@ -296,8 +251,9 @@ hipError_t launch_block2d(int64_t n0, int64_t n1, const typename V::T *x, typena
                           const typename V::T *b, const typename V::A *w_dev, int T,
                           Coef2D<typename V::A> k2, hipStream_t s)
 {
-    constexpr int OW = 64 * C - 2 * HALO, OH = NW * HW - 2 * HALO;
+    constexpr int OW = BlockShape<HW, HALO, NW, C>::OW, OH = BlockShape<HW, HALO, NW, C>::OH;
     if (T < 1 || T > HALO) return hipErrorInvalidValue;
+    if (n0 > INT32_MAX) return hipErrorInvalidValue;  // column offsets are 32-bit
     const int64_t bxn = (n0 + OW - 1) / OW, byn = (n1 + OH - 1) / OH;
     const int64_t nblocks = bxn * byn;
     if (nblocks > (int64_t)1 << 28) return hipErrorInvalidValue;

@@ -13,8 +13,9 @@
 // registers), and walks ZC planes along axis 2.  It keeps the previous,
 // current and next plane of u in registers, plus the rows just above and
 // below its H rows; neighbours along axis 0 come from DPP wave shifts.  Each
-// value of u, f, D, 1/D and each coupling is loaded once per plane (rows and
-// lanes of the halo aside).  Value policy V as in tile2d.h; FACE selects
+// value of u, f, D and each coupling is loaded once per plane (rows and
+// lanes of the halo aside); in binary64 a per-point 1/D is computed, not
+// loaded.  Value policy V as in tile2d.h; FACE selects
 // per-face couplings (all three axes) and DIAG a per-point diagonal.
 #pragma once
 
@@ -34,6 +35,7 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
                                             typename V::A w, int tx, int ty, int tz, int lane)
 {
     using A = typename V::A;
+    constexpr bool kRecipInPlace = sizeof(A) == sizeof(double);
     const int64_t n0 = S.n0, n1 = S.n1, n2 = S.n2;
     const int64_t s1 = n0, s2 = n0 * n1;
     const int64_t gx = (int64_t)tx * 62 - 1 + lane;
@@ -79,7 +81,14 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
             f1[r] = FACE ? ldc(S.face[1], S.c[1], z, gy) : S.c[1];
             f2c[r] = FACE ? ldc(S.face[2], S.c[2], z, gy) : S.c[2];
             dd[r] = DIAG ? ldc(S.diag, S.dconst, z, gy) : S.dconst;
-            di[r] = DIAG ? ldc(S.dinv, S.dinvconst, z, gy) : S.dinvconst;
+            // binary64: 1/D is formed here (a correctly rounded division, as
+            // the stored array holds) instead of being read, 8 bytes less per
+            // point; binary32 keeps the stored binary64 reciprocal rounded to
+            // binary32, which a binary32 division would not reproduce
+            if (DIAG && kRecipInPlace)
+                di[r] = row_ok(gy) ? A(1) / dd[r] : A(0);
+            else
+                di[r] = DIAG ? ldc(S.dinv, S.dinvconst, z, gy) : S.dinvconst;
         }
         const A u_above = ldu(z, gy0 - 1);   // row gy0 - 1 of this plane
         const A u_below = ldu(z, gy0 + H);   // row gy0 + H of this plane
