@@ -101,10 +101,13 @@ def test_solve_matches_oracle(torch_cuda, orc, case):
     s.close()
 
 
-def test_fused_plans_bit_identical(torch_cuda, orc):
-    # every 2D plan gives the same bits as one sweep per launch, on a grid
-    # that leaves ragged tiles in both directions
-    prob = workloads.poisson([517, 263], b=np.random.default_rng(4).uniform(-1, 1, (1, 263, 517)))
+@pytest.mark.parametrize("n0,n1", [(517, 263), (518, 262), (30, 20), (130, 1), (1, 77), (64, 64)])
+def test_fused_plans_bit_identical(torch_cuda, orc, n0, n1):
+    # every 2D plan gives the same bits as one sweep per launch: grids that
+    # leave ragged blocks in both directions (odd and even widths: two-column
+    # lanes load vectors only on even widths), grids smaller than one block,
+    # single rows and columns, and a grid of exactly one block side
+    prob = workloads.poisson([n0, n1], b=np.random.default_rng(4).uniform(-1, 1, (1, n1, n0)))
     s = _solver(prob)
     x0 = np.random.default_rng(5).uniform(-1, 1, prob.shape)
     results = {}
@@ -203,6 +206,18 @@ def test_error_paths(torch_cuda):
     assert zo["status"] == "ok" and zo["cycles"] == 0
     for h in (s, sb, sd, z):
         h.close()
+
+
+def test_default_2d_plan_follows_grid_size(torch_cuda):
+    # two columns per lane and 10 sweeps per launch once the grid holds at
+    # least 512 such blocks (108 x 44 written points each); one column per
+    # lane and 8 sweeps per launch below that
+    from paper_2011_06636_amd.solver import Solver
+    for n0, n1, want in ((2048, 2048, (8, 8, 10, 8)), (1024, 1024, (7, 8, 8, 8)),
+                         (108 * 32, 44 * 15 + 1, (8, 8, 10, 8)), (108 * 32, 44 * 15, (7, 8, 8, 8))):
+        s = Solver(workloads.poisson([n0, n1], b=np.zeros((1, n1, n0))))
+        assert tuple(s.get_plan(0)) == want, (n0, n1, s.get_plan(0))
+        s.close()
 
 
 def test_c2_full_size_first_cycles(torch_cuda, orc):
