@@ -44,6 +44,10 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {(8, 8, 10, 8): 106.8e6}
 # the same for the one-sweep reference kernel (plan kind 0)
 MEASURED_TRAFFIC_UNFUSED = 104.4e6
+# the single-sweep plan timed beside them (wavefront strips, T = 1) and its
+# HBM bytes per launch, taken the same way
+ONE_SWEEP_PLAN = (5, 16, 1, 1)
+MEASURED_TRAFFIC_ONE_SWEEP = 107.0e6
 
 
 def parse():
@@ -105,22 +109,33 @@ KERNEL_NAMES = {
 }
 
 
-def unfused_reference(s, x, prob, level=12):
-    """One sweep per launch (kind 0) on the same grid: GLUPS and algorithmic GB/s."""
-    plan = s.get_plan(0)
-    assert s.set_plan(0, 0, 1, 1) == 0
+def one_sweep_rate(s, x, prob, plan, traffic, level=12):
+    """One sweep per launch with `plan` on the same grid: GLUPS and algorithmic GB/s."""
+    keep = s.get_plan(0)
+    assert s.set_plan(*plan) == 0
     s.run_cycle(x, level)
     s.set_profiling(True)
     s.run_cycle(x, level)
     ms, launches, sweeps = s.profile()
     s.set_profiling(False)
-    assert s.set_plan(*plan) == 0
+    assert s.set_plan(*keep) == 0
     t = ms / 1e3 / max(launches, 1)
-    return {"kernel": KERNEL_NAMES[0], "avg_launch_us": round(t * 1e6, 3),
+    return {"kernel": KERNEL_NAMES[plan[0]], "plan": list(plan), "avg_launch_us": round(t * 1e6, 3),
             "GLUPS": round(prob.npoints / t / 1e9, 3),
             "achieved_GBps": round(24.0 * prob.npoints / t / 1e9, 1),
             "frac": round(24.0 * prob.npoints / t / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": MEASURED_TRAFFIC_UNFUSED if prob.n[0] == 2048 and prob.n[1] == 2048 else None}
+            "traffic": traffic if prob.n[0] == 2048 and prob.n[1] == 2048 else None}
+
+
+def unfused_reference(s, x, prob):
+    """The generic one-sweep kernel (kind 0)."""
+    return one_sweep_rate(s, x, prob, (0, 0, 1, 1), MEASURED_TRAFFIC_UNFUSED)
+
+
+def single_sweep_best(s, x, prob):
+    """The fastest single-sweep form of the 2D binary64 sweep: wavefront strips
+    of 16 output rows with a one-column halo, one sweep per launch."""
+    return one_sweep_rate(s, x, prob, ONE_SWEEP_PLAN, MEASURED_TRAFFIC_ONE_SWEEP)
 
 
 def copy_ceiling(mib=1024, reps=3):
@@ -512,6 +527,7 @@ def main():
     alg_bytes = 24.0 * prob.npoints
     achieved = alg_bytes / avg_launch_s / 1e9
     unfused = unfused_reference(s, x, prob)
+    single = single_sweep_best(s, x, prob)
     ceiling = copy_ceiling()
     f64_time = total / args.steps
     f32_time = sum(t32) / args.steps
@@ -550,7 +566,8 @@ def main():
                      "effective_GBps_per_sweep": round(24.0 * glups, 1),
                      "copy_ceiling_GBps": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4),
-                     "unfused_one_sweep": unfused},
+                     "unfused_one_sweep": unfused,
+                     "single_sweep_best": single},
     }
     s.close()
     del x
