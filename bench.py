@@ -67,11 +67,14 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(prob, target_s, levels):
+def cpu_baseline(prob, target_s, levels, norms):
     """The oracle on the first cycles of the same solve, about target_s seconds.
 
-    levels: the level of every cycle of the GPU solve (the oracle takes the
-    same ones), used only to size the sample."""
+    levels, norms: the level of every cycle and the residual norms of the GPU
+    solve.  The levels size the sample; the oracle chooses its own, and the
+    record states whether they, and the norms, agree with the GPU's."""
+    import numpy as np
+
     import oracle
     rate_probe = prob.zeros()
     rate_probe = oracle.sweep(prob, rate_probe, 0.6)
@@ -90,9 +93,14 @@ def cpu_baseline(prob, target_s, levels):
     t = time.perf_counter()
     out = oracle.solve(prob, tol=1e-300, max_cycles=cycles)
     dt = time.perf_counter() - t
+    k = int(out["cycles"])
+    gpu_n = np.asarray(norms[:k + 1], dtype=np.float64)
+    agree = {"cycles": k,
+             "same_levels": bool(np.array_equal(out["levels"], np.asarray(levels[:k]))),
+             "max_rel_norm_diff": float(np.max(np.abs(out["norms"] - gpu_n) / out["norms"]))}
     return {
         "value": out["sweeps"] * prob.npoints / dt / 1e9, "unit": "GLUPS",
-        "cores": oracle.num_threads(), "kind": "oracle",
+        "cores": oracle.num_threads(), "kind": "oracle", "agrees_with_gpu": agree,
         "sample": f"first {out['cycles']} cycles (levels {out['levels'][0]}..{out['levels'][-1]}, "
                   f"{out['sweeps']} sweeps, residual after each cycle) of the same solve, "
                   f"{dt:.1f} s",
@@ -577,7 +585,7 @@ def main():
                          "neumann_update_test": extra_neumann(),
                          "general_matrices": extra_general()}
     if args.cpu_seconds > 0:
-        rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"])
+        rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"], last["norms"])
     print(json.dumps(rec), flush=True)
 
 
