@@ -113,13 +113,13 @@ struct BlockShape {
     static_assert(HALO % C == 0, "lane columns must stay aligned");
 };
 
-// One wave's part of one block: load, T sweeps, store.  Row addresses are a
-// wave-uniform row start plus a per-lane 32-bit column offset, so they cost
-// one vector register for all rows.  EDGE blocks cross the grid's edge: rows
-// outside it read a valid row (a wave-uniform clamp) and lanes outside it
-// read column 0, so every load stays in bounds and needs no branch, and a
-// select then makes every value outside the grid zero; such values stay zero
-// and are not written.  kbase continues the LDS buffer parity of the
+// One wave's part of one block: load, T sweeps, store.  Row starts are
+// wave-uniform and each lane adds its 32-bit column offset.  EDGE blocks
+// cross the grid's edge: rows outside it read a valid row (a wave-uniform
+// clamp) and lanes outside it read column 0, so every load stays in bounds
+// and needs no branch, and a select then makes every value outside the grid
+// zero; such values stay zero and are not written.  Written this way the
+// boundary path needs no more registers than the interior one.  kbase continues the LDS buffer parity of the
 // workgroup's previous sweeps (0 for a fresh workgroup).
 template <class V, int HW, int HALO, int NW, int C, bool EDGE>
 __device__ __forceinline__ void block2d_run(int64_t n0, int64_t n1,
