@@ -226,8 +226,11 @@ def extra_batch(which):
         conv_b = sum(i["converged"] for i in out["instances"])
         sweeps_b = sum(i["sweeps"] * p.npoints for i, p in zip(out["instances"], probs))
         rec = {"precision": prec, "time_ms": round(dt_b * 1e3, 3), "converged": conv_b,
-               "GLUPS": round(sweeps_b / dt_b / 1e9, 3), "plan": list(bs.get_plan()),
-               "autotune_us_per_sweep": round(tune_us, 3)}
+               "GLUPS": round(sweeps_b / dt_b / 1e9, 3)}
+        if which == "c4":
+            rec |= {"plan": list(bs.get_plan()), "autotune_us_per_sweep": round(tune_us, 3)}
+        else:
+            rec |= {"plane_tile": list(bs.get_plan3d()), "autotune_us_per_step": round(tune_us, 3)}
         batched.append(rec)
         xs_by_prec[prec] = [x.clone() for x in out["xs"]]
         if best is None or dt_b < best[0]:

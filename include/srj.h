@@ -377,10 +377,21 @@ srj_status srj_cluster_samples(const srj_sample *samples, int64_t count, int32_t
 srj_status srj_fit_rule(const srj_cluster *clusters, int32_t count, double *t_low, double *t_high,
                         int32_t *agree, int32_t *decided);
 
-/* Batch autotuner: times every tile plan for `precision` on this batch,
- * `sweeps` sweeps of its 2D instances from x0 = 0 on the batch's own
- * buffers (no caller memory is touched), sets the fastest plan and writes its
- * time per sweep (us) to *best_us_per_sweep. */
+/* 3D plane tile of a batch: 3D instances are swept by waves that each own
+ * 62 written columns x tile_rows rows and walk `planes` planes along axis 2
+ * (tile_rows, planes) in {(2, 16), (4, 8), (4, 16), (8, 8), (8, 16)}; default
+ * (4, 8).  SRJ_ERR_UNSUPPORTED for any other shape.  Iterates do not depend
+ * on the tile. */
+srj_status srj_batch_set_plan3d(srj_batch *batch, int32_t tile_rows, int32_t planes);
+srj_status srj_batch_get_plan3d(srj_batch *batch, int32_t *tile_rows, int32_t *planes);
+
+/* Batch autotuner: for `precision`, times every tile or block plan of the
+ * batch's 2D/1D instances (when it has any; `sweeps` sweeps of them) and then
+ * every 3D plane tile (when it has 3D instances; `sweeps` steps, one sweep of
+ * every 3D instance each), from x0 = 0 on the batch's own buffers (no caller
+ * memory is touched), and sets the fastest of each.  *best_us_per_sweep: the
+ * time per sweep of the 2D/1D instances, or, when the batch has 3D instances,
+ * the time per step.  Iterates do not depend on the choice. */
 srj_status srj_batch_autotune(srj_batch *batch, int32_t precision, int32_t sweeps,
                               double *best_us_per_sweep);
 

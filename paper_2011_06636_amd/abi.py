@@ -36,6 +36,7 @@ EXPORTS = [
     "srj_autotune", "srj_set_resident",
     "srj_set_profiling",
     "srj_get_profile", "srj_batch_setup", "srj_batch_set_plan", "srj_batch_get_plan",
+    "srj_batch_set_plan3d", "srj_batch_get_plan3d",
     "srj_batch_autotune",
     "srj_batch_solve", "srj_batch_destroy", "srj_collect", "srj_cluster_samples",
     "srj_fit_rule", "srj_set_scheme_family", "srj_last_error",
@@ -126,6 +127,8 @@ def load() -> ctypes.CDLL:
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
         "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
         "srj_batch_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
+        "srj_batch_set_plan3d": (i32, [vp, i32, i32]),
+        "srj_batch_get_plan3d": (i32, [vp, P(i32), P(i32)]),
         "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
@@ -274,6 +277,16 @@ def srj_batch_set_plan(batch, tile_rows: int, sweeps: int, waves_per_block: int 
 def srj_batch_get_plan(batch):
     v = [ctypes.c_int32() for _ in range(5)]
     check(load().srj_batch_get_plan(batch, *[ctypes.byref(a) for a in v]), "srj_batch_get_plan")
+    return tuple(a.value for a in v)
+
+
+def srj_batch_set_plan3d(batch, tile_rows: int, planes: int) -> None:
+    check(load().srj_batch_set_plan3d(batch, tile_rows, planes), "srj_batch_set_plan3d")
+
+
+def srj_batch_get_plan3d(batch):
+    v = [ctypes.c_int32() for _ in range(2)]
+    check(load().srj_batch_get_plan3d(batch, *[ctypes.byref(a) for a in v]), "srj_batch_get_plan3d")
     return tuple(a.value for a in v)
 
 

@@ -40,8 +40,8 @@ namespace srj {
 namespace {
 
 constexpr int kOuterPts = 2048;  // points per outer-pass work item (256 threads x 8)
-constexpr int kPH = 4;           // rows per 3D plane tile
-constexpr int kZC = 8;           // planes per 3D sweep work item
+// 3D plane tiles of the batched sweep (rows per tile, planes per work item)
+#define SRJ_BATCH_PLANE(X) X(2, 16) X(4, 8) X(4, 16) X(8, 8) X(8, 16)
 
 struct BDesc {
     int32_t ndim;
@@ -170,8 +170,9 @@ __global__ __launch_bounds__(64 * NW) void k_bsweep2d_blk(const BDesc *__restric
     }
 }
 
-// 1'. sweeps, 3D instances: one wave per (instance, plane tile) item
-template <class V>
+// 1'. sweeps, 3D instances: one wave per (instance, plane tile) item; a
+// tile is 62 written columns x PH rows x ZC planes
+template <class V, int PH, int ZC>
 __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc,
                                                   const BState *__restrict__ st,
                                                   const int2 *__restrict__ items, int nitems,
@@ -189,8 +190,8 @@ __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc
         const A w = Sel<A>::omega(prm)[prm.offsets[s.level] + s.pos];
         const typename V::T *uin = (s.pu ? ub : ua) + d.off;
         typename V::T *uout = (s.pu ? ua : ub) + d.off;
-        plane3d_run<V, kPH, kZC, false, false>(Sel<A>::sten(d), uin, uout, rhs + d.off, w, tx, ty,
-                                               tz, threadIdx.x & 63);
+        plane3d_run<V, PH, ZC, false, false>(Sel<A>::sten(d), uin, uout, rhs + d.off, w, tx, ty,
+                                             tz, threadIdx.x & 63);
     }
 }
 
@@ -444,6 +445,7 @@ struct srj_batch {
     // plan
     int tile_rows = 24, halo = 4, T2 = 4, waves = 1, steps_per_graph = 16;
     bool use_graph = true;
+    int ph3 = 4, zc3 = 8;  // 3D plane tile: rows, planes per work item
 };
 
 namespace {
@@ -542,9 +544,18 @@ srj_status enqueue_step(srj_batch *B, const BParams &prm)
     }
     if (!B->hitems3.empty()) {
         const int grid = (int)std::min<int64_t>((B->hitems3.size() + 3) / 4, (int64_t)cus * 8);
-        hipLaunchKernelGGL((k_bsweep3d<V>), dim3(grid), dim3(256), 0, B->stream, B->desc,
-                           B->state, B->items3, (int)B->hitems3.size(), (typename V::T *)ua,
-                           (typename V::T *)ub, (const typename V::T *)rhs, prm);
+        bool launched = false;
+#define SRJ_GO3(PH, ZC)                                                                           \
+        if (!launched && B->ph3 == PH && B->zc3 == ZC) {                                          \
+            hipLaunchKernelGGL((k_bsweep3d<V, PH, ZC>), dim3(grid), dim3(256), 0, B->stream,     \
+                               B->desc, B->state, B->items3, (int)B->hitems3.size(),            \
+                               (typename V::T *)ua, (typename V::T *)ub,                         \
+                               (const typename V::T *)rhs, prm);                                 \
+            launched = true;                                                                       \
+        }
+        SRJ_BATCH_PLANE(SRJ_GO3)
+#undef SRJ_GO3
+        if (!launched) return fail(SRJ_ERR_INVALID, "3D plane tile not available");
         SRJ_HIP_CHECK(hipGetLastError());
     }
     const int og = (int)std::min<int64_t>(B->hoitems.size(), (int64_t)cus * 8);
@@ -954,8 +965,8 @@ srj_status srj_batch_set_plan(srj_batch *B, int32_t tile_rows, int32_t sweeps_pe
         BDesc &d = B->hdesc[i];
         if (d.ndim == 3) {
             d.gx3 = (int)((d.n0 + 61) / 62);
-            d.gy3 = (int)((d.n1 + kPH - 1) / kPH);
-            const int gz = (int)((d.n2 + kZC - 1) / kZC);
+            d.gy3 = (int)((d.n1 + B->ph3 - 1) / B->ph3);
+            const int gz = (int)((d.n2 + B->zc3 - 1) / B->zc3);
             for (int k = 0; k < d.gx3 * d.gy3 * gz; ++k) B->hitems3.push_back({i, k});
         } else {
             d.tiles_x = (int)((d.n0 + OW - 1) / OW);
@@ -1027,6 +1038,29 @@ srj_status srj_batch_get_plan(srj_batch *B, int32_t *tile_rows, int32_t *sweeps_
     return SRJ_OK;
 }
 
+srj_status srj_batch_set_plan3d(srj_batch *B, int32_t tile_rows, int32_t planes)
+{
+    if (!B) return fail(SRJ_ERR_INVALID, "batch is NULL");
+    bool ok = false;
+#define SRJ_OK3(PH, ZC) ok = ok || (tile_rows == PH && planes == ZC);
+    SRJ_BATCH_PLANE(SRJ_OK3)
+#undef SRJ_OK3
+    if (!ok) return fail(SRJ_ERR_UNSUPPORTED, "3D plane tile not available");
+    B->ph3 = tile_rows;
+    B->zc3 = planes;
+    // rebuild the work items with the current 2D plan
+    return srj_batch_set_plan(B, B->tile_rows, B->T2, B->waves, B->steps_per_graph,
+                              B->use_graph ? 1 : 0);
+}
+
+srj_status srj_batch_get_plan3d(srj_batch *B, int32_t *tile_rows, int32_t *planes)
+{
+    if (!B || !tile_rows || !planes) return fail(SRJ_ERR_INVALID, "NULL argument");
+    *tile_rows = B->ph3;
+    *planes = B->zc3;
+    return SRJ_OK;
+}
+
 srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
                               double *best_us_per_sweep)
 {
@@ -1043,43 +1077,80 @@ srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
     o.max_sweeps = (int64_t)1 << 60;
     const int steps_per_graph = B->steps_per_graph;
     const bool use_graph = B->use_graph;
-    int best_rows = B->tile_rows, best_T = B->T2, best_waves = B->waves;
-    double best = INFINITY;
-    struct Cand {
-        int rows, T, waves;
+    auto time_steps = [&](int steps, float *ms) -> srj_status {
+        switch (o.precision) {
+        case SRJ_PREC_F64: return batch_time_steps<StF32, false>(B, &o, steps, ms);
+        case SRJ_PREC_F32_REFINE: return batch_time_steps<StF32, true>(B, &o, steps, ms);
+        case SRJ_PREC_F16_REFINE: return batch_time_steps<StF16, true>(B, &o, steps, ms);
+        default: return batch_time_steps<StBF16, true>(B, &o, steps, ms);
+        }
     };
-    std::vector<Cand> cands;
+    double best = INFINITY;
+    // 2D/1D instances: tile or block plan, timed per sweep
+    if (!B->hitems2.empty()) {
+        int best_rows = B->tile_rows, best_T = B->T2, best_waves = B->waves;
+        struct Cand {
+            int rows, T, waves;
+        };
+        std::vector<Cand> cands;
 #define SRJ_C(R, HL)                                        \
     cands.push_back({R, HL, 1});                            \
     if ((HL + 1) / 2 != HL) cands.push_back({R, (HL + 1) / 2, 1});
-    SRJ_BATCH_2D(SRJ_C)
+        SRJ_BATCH_2D(SRJ_C)
 #undef SRJ_C
 #define SRJ_CB(HW, HL, NW) cands.push_back({HW, HL, NW});
-    SRJ_BATCH_BLOCK(SRJ_CB)
+        SRJ_BATCH_BLOCK(SRJ_CB)
 #undef SRJ_CB
-    for (const Cand &cd : cands) {
-        srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, cd.waves, steps_per_graph, use_graph);
-        if (st != SRJ_OK) return st;
-        // every step moves 2D instances by T sweeps and 3D instances by one
-        const int steps = std::max(1, (sweeps + cd.T - 1) / cd.T);
-        float ms = 0.f;
-        switch (o.precision) {
-        case SRJ_PREC_F64: st = batch_time_steps<StF32, false>(B, &o, steps, &ms); break;
-        case SRJ_PREC_F32_REFINE: st = batch_time_steps<StF32, true>(B, &o, steps, &ms); break;
-        case SRJ_PREC_F16_REFINE: st = batch_time_steps<StF16, true>(B, &o, steps, &ms); break;
-        default: st = batch_time_steps<StBF16, true>(B, &o, steps, &ms); break;
+        for (const Cand &cd : cands) {
+            srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, cd.waves, steps_per_graph, use_graph);
+            if (st != SRJ_OK) return st;
+            // every step moves 2D instances by T sweeps and 3D instances by one
+            const int steps = std::max(1, (sweeps + cd.T - 1) / cd.T);
+            float ms = 0.f;
+            st = time_steps(steps, &ms);
+            if (st != SRJ_OK) return st;
+            const double us = 1e3 * ms / (steps * cd.T);
+            if (us < best) {
+                best = us;
+                best_rows = cd.rows;
+                best_T = cd.T;
+                best_waves = cd.waves;
+            }
         }
+        srj_status st = srj_batch_set_plan(B, best_rows, best_T, best_waves, steps_per_graph,
+                                           use_graph ? 1 : 0);
         if (st != SRJ_OK) return st;
-        const double us = 1e3 * ms / (steps * cd.T);
-        if (us < best) {
-            best = us;
-            best_rows = cd.rows;
-            best_T = cd.T;
-            best_waves = cd.waves;
+    }
+    // 3D instances: plane tile, timed per step (one sweep of every 3D instance)
+    if (!B->hitems3.empty()) {
+        int best_ph = B->ph3, best_zc = B->zc3;
+        double best3 = INFINITY;
+        struct Tile {
+            int ph, zc;
+        };
+        std::vector<Tile> tiles;
+#define SRJ_C3(PH, ZC) tiles.push_back({PH, ZC});
+        SRJ_BATCH_PLANE(SRJ_C3)
+#undef SRJ_C3
+        for (const Tile &t : tiles) {
+            srj_status st = srj_batch_set_plan3d(B, t.ph, t.zc);
+            if (st != SRJ_OK) return st;
+            float ms = 0.f;
+            st = time_steps(sweeps, &ms);
+            if (st != SRJ_OK) return st;
+            const double us = 1e3 * ms / sweeps;
+            if (us < best3) {
+                best3 = us;
+                best_ph = t.ph;
+                best_zc = t.zc;
+            }
         }
+        srj_status st = srj_batch_set_plan3d(B, best_ph, best_zc);
+        if (st != SRJ_OK) return st;
+        best = best3;
     }
     *best_us_per_sweep = best;
-    return srj_batch_set_plan(B, best_rows, best_T, best_waves, steps_per_graph, use_graph ? 1 : 0);
+    return SRJ_OK;
 }
 
 srj_status srj_batch_destroy(srj_batch *B)

@@ -82,6 +82,39 @@ def test_batch_plans_identical(torch_cuda, orc):
     bs.close()
 
 
+TILES3D = [(4, 8), (2, 16), (4, 16), (8, 8), (8, 16)]
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("bf16", 1e-8)])
+def test_batch_3d_tiles_identical(torch_cuda, orc, precision, tol):
+    # every plane tile of the 3D instances gives the same bits: boxes wider
+    # than one 62-column tile, ragged in rows and planes
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import BatchSolver
+    probs = [workloads.c5_instance(i, lo=20, hi=70) for i in range(5)]
+    assert max(p.n[0] for p in probs) > 62
+    bs = BatchSolver(probs)
+    assert bs.get_plan3d() == (4, 8)
+    kw = dict(tol=tol, precision=precision, max_cycles=200)
+    base = None
+    for tile in TILES3D:
+        bs.set_plan3d(*tile)
+        assert bs.get_plan3d() == tile
+        out = bs.solve(**kw)
+        got = [x.cpu().numpy() for x in out["xs"]]
+        if base is None:
+            base = got
+            _check(orc, probs, out, kw)
+        else:
+            for a, b in zip(got, base):
+                assert np.array_equal(a, b), tile
+    for bad in ((3, 8), (4, 12), (0, 0)):
+        with pytest.raises(abi.SrjError) as e:
+            bs.set_plan3d(*bad)
+        assert e.value.status == abi.SRJ_ERR_UNSUPPORTED
+    bs.close()
+
+
 def test_batch_caps_and_errors(torch_cuda, orc):
     from paper_2011_06636_amd import abi
     from paper_2011_06636_amd.solver import BatchSolver
@@ -108,6 +141,7 @@ def test_batch_autotune_keeps_results(torch_cuda, orc):
     assert us > 0
     rows, T, waves, _, _ = bs.get_plan()
     assert (rows, waves) in ((16, 1), (24, 1), (32, 1), (48, 1), (8, 8), (12, 8), (16, 4)) and T >= 1
+    assert bs.get_plan3d() in TILES3D
     out = bs.solve(**kw)
     for a, b in zip(out["xs"], ref_x):
         assert np.array_equal(a.cpu().numpy(), b)
