@@ -221,72 +221,93 @@ __global__ __launch_bounds__(256) void k_bouter(const BDesc *__restrict__ desc,
     typename St::T *ua = static_cast<typename St::T *>(uav);
     typename St::T *ub = static_cast<typename St::T *>(ubv);
     __shared__ double lds[4];
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int2 it = items[item];
-        const BState s = st[it.x];
-        if (s.done) continue;  // uniform over the block
-        const BDesc &d = desc[it.x];
-        if (mode == OUT_STEP && s.pos + sweeps_this_step(d, s, prm) != prm.levelM[s.level])
-            continue;
-        // which buffers hold the current iterate
-        const double *x;
-        const typename St::T *dl = nullptr;  // latest correction (REFINE, step)
-        typename St::T *dz = nullptr;        // correction buffer to clear
-        double *xn = nullptr;                // updated x (REFINE, step)
-        double inv_s = 0.0, s_next = 0.0;
-        if (REFINE) {
-            x = (s.px ? xb : xa) + d.off;
-            if (mode == OUT_STEP) {
-                dl = (s.pu ? ua : ub) + d.off;  // the sweep just wrote u[pu ^ 1]
-                dz = (s.pu ? ub : ua) + d.off;  // stale: becomes the next cycle's zero start
-                xn = (s.px ? xa : xb) + d.off;
-                inv_s = 1.0 / s.s;
-                s_next = pow2_scale_dev(s.prev, d.sqrtN, prm.tgt_rms);
-            } else if (mode == OUT_CAST) {
-                dz = (s.pu ? ub : ua) + d.off;  // u[pu] starts the first cycle at zero
-                s_next = s.s;
-            }
-        } else {
-            const double *u64 = static_cast<const double *>(uav);
-            const double *v64 = static_cast<const double *>(ubv);
-            // step: the sweep just wrote u[pu ^ 1]; norm: u[pu] is current
-            const int cur = mode == OUT_STEP ? (s.pu ^ 1) : s.pu;
-            x = (cur ? v64 : u64) + d.off;
+    __shared__ int nact;
+    __shared__ int act[256];
+    // The block owns items blockIdx.x + j gridDim.x.  Most of them have
+    // nothing to do in a given step (their instance is not at a cycle end):
+    // each thread tests one of the next 256 at once, so the state loads
+    // overlap, and the block then works through the active ones.  Every item
+    // writes only its own partial sum, so the order does not matter.
+    for (int first = blockIdx.x; first < nitems; first += gridDim.x * 256) {
+        if (threadIdx.x == 0) nact = 0;
+        __syncthreads();
+        const int mine = first + threadIdx.x * gridDim.x;
+        if (mine < nitems) {
+            const int2 it = items[mine];
+            const BState s = st[it.x];
+            bool on = !s.done;
+            if (on && mode == OUT_STEP)
+                on = s.pos + sweeps_this_step(desc[it.x], s, prm) == prm.levelM[s.level];
+            if (on) act[atomicAdd(&nact, 1)] = mine;
         }
-        const int64_t s1 = d.n0, s2 = d.n0 * d.n1;
-        const int64_t base = (int64_t)(it.y - d.oitem_first) * kOuterPts;
-        double acc = 0.0;
-        for (int k = 0; k < kOuterPts / 256; ++k) {
-            const int64_t q = base + k * 256 + threadIdx.x;
-            if (q >= d.npts) break;
-            const int64_t i0 = q % d.n0, i1 = (q / d.n0) % d.n1, i2 = q / s2;
-            auto xv = [&](int64_t pp) -> double {
-                if (REFINE && mode == OUT_STEP)
-                    return x[pp] + static_cast<double>(St::load(dl[pp])) * inv_s;
-                return x[pp];
-            };
-            const double xc = xv(q);
-            double sacc = d.D * xc;
-            if (i0 > 0) sacc = sacc - d.c[0] * xv(q - 1);
-            if (i0 < d.n0 - 1) sacc = sacc - d.c[0] * xv(q + 1);
-            if (d.ndim >= 2) {
-                if (i1 > 0) sacc = sacc - d.c[1] * xv(q - s1);
-                if (i1 < d.n1 - 1) sacc = sacc - d.c[1] * xv(q + s1);
+        __syncthreads();
+        const int n = nact;
+        for (int a = 0; a < n; ++a) {
+            const int item = act[a];
+            const int2 it = items[item];
+            const BState s = st[it.x];
+            const BDesc &d = desc[it.x];
+            // which buffers hold the current iterate
+            const double *x;
+            const typename St::T *dl = nullptr;  // latest correction (REFINE, step)
+            typename St::T *dz = nullptr;        // correction buffer to clear
+            double *xn = nullptr;                // updated x (REFINE, step)
+            double inv_s = 0.0, s_next = 0.0;
+            if (REFINE) {
+                x = (s.px ? xb : xa) + d.off;
+                if (mode == OUT_STEP) {
+                    dl = (s.pu ? ua : ub) + d.off;  // the sweep just wrote u[pu ^ 1]
+                    dz = (s.pu ? ub : ua) + d.off;  // stale: becomes the next cycle's zero start
+                    xn = (s.px ? xa : xb) + d.off;
+                    inv_s = 1.0 / s.s;
+                    s_next = pow2_scale_dev(s.prev, d.sqrtN, prm.tgt_rms);
+                } else if (mode == OUT_CAST) {
+                    dz = (s.pu ? ub : ua) + d.off;  // u[pu] starts the first cycle at zero
+                    s_next = s.s;
+                }
+            } else {
+                const double *u64 = static_cast<const double *>(uav);
+                const double *v64 = static_cast<const double *>(ubv);
+                // step: the sweep just wrote u[pu ^ 1]; norm: u[pu] is current
+                const int cur = mode == OUT_STEP ? (s.pu ^ 1) : s.pu;
+                x = (cur ? v64 : u64) + d.off;
             }
-            if (d.ndim >= 3) {
-                if (i2 > 0) sacc = sacc - d.c[2] * xv(q - s2);
-                if (i2 < d.n2 - 1) sacc = sacc - d.c[2] * xv(q + s2);
+            const int64_t s1 = d.n0, s2 = d.n0 * d.n1;
+            const int64_t base = (int64_t)(it.y - d.oitem_first) * kOuterPts;
+            double acc = 0.0;
+            for (int k = 0; k < kOuterPts / 256; ++k) {
+                const int64_t q = base + k * 256 + threadIdx.x;
+                if (q >= d.npts) break;
+                const int64_t i0 = q % d.n0, i1 = (q / d.n0) % d.n1, i2 = q / s2;
+                auto xv = [&](int64_t pp) -> double {
+                    if (REFINE && mode == OUT_STEP)
+                        return x[pp] + static_cast<double>(St::load(dl[pp])) * inv_s;
+                    return x[pp];
+                };
+                const double xc = xv(q);
+                double sacc = d.D * xc;
+                if (i0 > 0) sacc = sacc - d.c[0] * xv(q - 1);
+                if (i0 < d.n0 - 1) sacc = sacc - d.c[0] * xv(q + 1);
+                if (d.ndim >= 2) {
+                    if (i1 > 0) sacc = sacc - d.c[1] * xv(q - s1);
+                    if (i1 < d.n1 - 1) sacc = sacc - d.c[1] * xv(q + s1);
+                }
+                if (d.ndim >= 3) {
+                    if (i2 > 0) sacc = sacc - d.c[2] * xv(q - s2);
+                    if (i2 < d.n2 - 1) sacc = sacc - d.c[2] * xv(q + s2);
+                }
+                const double r = b[d.off + q] - sacc;
+                acc += r * r;
+                if (REFINE && mode != OUT_NORM) {
+                    if (mode == OUT_STEP) xn[q] = xc;
+                    rhat[d.off + q] = St::store(static_cast<float>(s_next * r));
+                    dz[q] = St::store(0.0f);
+                }
             }
-            const double r = b[d.off + q] - sacc;
-            acc += r * r;
-            if (REFINE && mode != OUT_NORM) {
-                if (mode == OUT_STEP) xn[q] = xc;
-                rhat[d.off + q] = St::store(static_cast<float>(s_next * r));
-                dz[q] = St::store(0.0f);
-            }
+            const double t = block_sum256(acc, lds);
+            if (threadIdx.x == 0) partials[item] = t;
         }
-        const double t = block_sum256(acc, lds);
-        if (threadIdx.x == 0) partials[item] = t;
+        __syncthreads();  // act and nact are reused by the next group
     }
 }
 
