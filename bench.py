@@ -64,6 +64,10 @@ def parse():
                     help="skip the 3D and batched comparison legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target length of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--only", choices=["c3", "c4", "c5", "training", "neumann", "general"],
+                    default="", help="run one comparison leg alone and print its record")
+    ap.add_argument("--c3-cycles", type=int, default=200,
+                    help="cycle cap of each 3D variable-coefficient solve")
     return ap.parse_args()
 
 
@@ -173,8 +177,9 @@ def _timed(fn):
     return out, time.perf_counter() - t
 
 
-def extra_c3():
-    """3D variable-coefficient 256^3: plain binary64 vs binary32-refined, to 1e-10."""
+def extra_c3(max_cycles=200):
+    """3D variable-coefficient 256^3: plain binary64 vs binary32-refined, to 1e-10
+    (at most max_cycles cycles each)."""
     import workloads
     from paper_2011_06636_amd.solver import Solver
     prob = workloads.c3()
@@ -186,9 +191,9 @@ def extra_c3():
            "plans": {"f64": list(s.get_plan(0)), "inner": list(s.get_plan(1))}}
     for prec in ("f64", "f32"):
         x = s.zeros()
-        s.solve(x, tol=1e-10, precision=prec, max_cycles=200)
+        s.solve(x, tol=1e-10, precision=prec, max_cycles=max_cycles)
         x.zero_()
-        out, dt = _timed(lambda: s.solve(x, tol=1e-10, precision=prec, max_cycles=200))
+        out, dt = _timed(lambda: s.solve(x, tol=1e-10, precision=prec, max_cycles=max_cycles))
         rec[prec] = {"converged": out["converged"], "cycles": out["cycles"],
                      "sweeps": out["sweeps"], "time_ms": round(dt * 1e3, 3),
                      "GLUPS": round(out["sweeps"] * prob.npoints / dt / 1e9, 3),
@@ -513,6 +518,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        legs = {"c3": lambda: extra_c3(args.c3_cycles), "c4": lambda: extra_batch("c4"),
+                "c5": lambda: extra_batch("c5"), "training": extra_training,
+                "neumann": extra_neumann, "general": extra_general}
+        print(json.dumps({"only": args.only, "record": legs[args.only]()}), flush=True)
+        return
     prob = workloads.c2(n=args.n)
     s = Solver(prob)
     if args.plan:
@@ -592,7 +603,7 @@ def main():
     s.close()
     del x
     if not args.no_extras:
-        rec["extras"] = {"c3_3d_varcoef": extra_c3(), "c4_batch_2d": extra_batch("c4"),
+        rec["extras"] = {"c3_3d_varcoef": extra_c3(args.c3_cycles), "c4_batch_2d": extra_batch("c4"),
                          "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training(),
                          "neumann_update_test": extra_neumann(),
                          "general_matrices": extra_general()}
