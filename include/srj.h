@@ -42,7 +42,10 @@
  * those values are valid.  A context must not be used by two threads at once.
  *
  * Errors.  Every call returns an srj_status; no exception crosses the ABI.
- * Arguments are validated before any device work (SRJ_ERR_INVALID).
+ * Arguments are validated before any device work (SRJ_ERR_INVALID), device
+ * arrays included: each must lie, whole, inside one allocation of device (or
+ * managed) memory of the device that was current at setup; host memory,
+ * pinned or not, is refused.
  * srj_last_error() returns a thread-local description of the last non-OK
  * status.
  */

@@ -30,6 +30,31 @@ srj_status fail(srj_status st, const std::string &msg)
     return st;
 }
 
+srj_status check_device_array(const void *p, size_t bytes, int dev, const char *what)
+{
+    if (!p) return fail(SRJ_ERR_INVALID, std::string(what) + " is NULL");
+    hipPointerAttribute_t a{};
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SRJ_ERR_INVALID, std::string(what) + " is not device memory");
+    }
+    const bool devmem = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+    if (!devmem || a.device != dev)
+        return fail(SRJ_ERR_INVALID, std::string(what) + " is not device memory of the context's GPU");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SRJ_ERR_INVALID, std::string(what) + " is not inside a device allocation");
+    }
+    const uintptr_t lo = (uintptr_t)base, at = (uintptr_t)p;
+    if (at < lo || bytes > size - (at - lo))
+        return fail(SRJ_ERR_INVALID, std::string(what) + " extends past the end of its allocation");
+    return SRJ_OK;
+}
+
 }  // namespace srj
 
 using namespace srj;
@@ -310,8 +335,19 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     *out = nullptr;
     srj_status st = validate_problem(p);
     if (st != SRJ_OK) return st;
+    int dev = 0;
+    SRJ_HIP_CHECK(hipGetDevice(&dev));
+    {
+        const size_t nb = sizeof(double) * (size_t)(p->n[0] * p->n[1] * p->n[2]);
+        if ((st = check_device_array(p->b, nb, dev, "b")) != SRJ_OK) return st;
+        if (p->diag && (st = check_device_array(p->diag, nb, dev, "diag")) != SRJ_OK) return st;
+        for (int d = 0; d < p->ndim; ++d)
+            if (p->face[d] && (st = check_device_array(p->face[d], nb, dev, "face[d]")) != SRJ_OK)
+                return st;
+    }
 
     srj_ctx *c = new srj_ctx();
+    c->device = dev;
     c->stream = static_cast<hipStream_t>(hip_stream);
     DevProblem &P = c->P;
     P.ndim = p->ndim;
@@ -414,6 +450,11 @@ srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **o
     if (p->n < 1 || p->n > ((int64_t)1 << 31) - 1) return fail(SRJ_ERR_INVALID, "n must be 1 .. 2^31 - 1");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const int64_t n = p->n;
+    int dev = 0;
+    SRJ_HIP_CHECK(hipGetDevice(&dev));
+    srj_status chk = check_device_array(p->rowptr, sizeof(int64_t) * ((size_t)n + 1), dev, "rowptr");
+    if (chk == SRJ_OK) chk = check_device_array(p->b, sizeof(double) * (size_t)n, dev, "b");
+    if (chk != SRJ_OK) return chk;
     // the structure is checked on the host: copy it
     std::vector<int64_t> rp((size_t)n + 1);
     SRJ_HIP_CHECK(hipStreamSynchronize(stream));
@@ -426,6 +467,9 @@ srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **o
     std::vector<int32_t> col((size_t)nnz);
     std::vector<double> val((size_t)nnz);
     if (nnz > 0) {
+        chk = check_device_array(p->col, sizeof(int32_t) * col.size(), dev, "col");
+        if (chk == SRJ_OK) chk = check_device_array(p->val, sizeof(double) * val.size(), dev, "val");
+        if (chk != SRJ_OK) return chk;
         SRJ_HIP_CHECK(hipMemcpy(col.data(), p->col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost));
         SRJ_HIP_CHECK(hipMemcpy(val.data(), p->val, sizeof(double) * val.size(), hipMemcpyDeviceToHost));
     }
@@ -466,6 +510,7 @@ srj_status srj_setup_csr(const srj_csr_problem *p, void *hip_stream, srj_ctx **o
         for (; j < width; ++j) ecol[(size_t)j * n + i] = (int32_t)i;  // never read
     }
     srj_ctx *c = new srj_ctx();
+    c->device = dev;
     c->stream = stream;
     c->npoints = n;
     auto nomem = [&](const char *what) {
@@ -587,6 +632,8 @@ srj_status srj_get_profile(srj_ctx *c, double *sweep_ms, int64_t *launches, int6
 srj_status srj_residual_norm(srj_ctx *c, const double *x, double *norm_out)
 {
     if (!c || !x || !norm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
+    srj_status st = check_device_array(x, sizeof(double) * (size_t)c->npoints, c->device, "x");
+    if (st != SRJ_OK) return st;
     return residual_norm(c, x, norm_out);
 }
 
@@ -687,6 +734,8 @@ srj_status srj_run_cycle(srj_ctx *c, double *x, int32_t level, double *resnorm_o
 {
     if (!c || !x || !resnorm_out) return fail(SRJ_ERR_INVALID, "NULL argument");
     if (level < 0 || level >= c->nlevels) return fail(SRJ_ERR_INVALID, "level outside the scheme family");
+    srj_status chk = check_device_array(x, sizeof(double) * (size_t)c->npoints, c->device, "x");
+    if (chk != SRJ_OK) return chk;
     double *cur = x, *nxt = c->ws;
     srj_status st = run_sweeps(c, &cur, &nxt, level);
     if (st != SRJ_OK) return st;
@@ -701,6 +750,8 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
 {
     if (!c || !x || !res) return fail(SRJ_ERR_INVALID, "NULL argument");
     srj_status st = validate_opts(o);
+    if (st != SRJ_OK) return st;
+    st = check_device_array(x, sizeof(double) * (size_t)c->npoints, c->device, "x");
     if (st != SRJ_OK) return st;
     // the context's scheme family bounds the levels: the top level is clamped
     // to it, a start or fixed level beyond it is an error

@@ -467,6 +467,7 @@ struct srj_batch {
     int tile_rows = 24, halo = 4, T2 = 4, waves = 1, steps_per_graph = 16;
     bool use_graph = true;
     int ph3 = 4, zc3 = 8;  // 3D plane tile: rows, planes per work item
+    int device = 0;        // current device at setup; caller arrays must live there
 };
 
 namespace {
@@ -862,7 +863,16 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
         if (!(p.dconst > 0.0) || !isfinite(p.dconst)) return fail(SRJ_ERR_INVALID, "dconst must be > 0");
         if (!p.b) return fail(SRJ_ERR_INVALID, "b is NULL");
     }
+    int dev = 0;
+    SRJ_HIP_CHECK(hipGetDevice(&dev));
+    for (int i = 0; i < count; ++i) {
+        const srj_problem &p = probs[i];
+        const size_t nb = sizeof(double) * (size_t)(p.n[0] * p.n[1] * p.n[2]);
+        srj_status chk = check_device_array(p.b, nb, dev, "b");
+        if (chk != SRJ_OK) return chk;
+    }
     srj_batch *B = new srj_batch();
+    B->device = dev;
     B->user_stream = static_cast<hipStream_t>(hip_stream);
     B->cus = device_cus();
     if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1024,8 +1034,12 @@ srj_status srj_batch_solve(srj_batch *B, double *const *xs, const srj_solve_opts
                            srj_solve_result *res, int32_t *levels_out)
 {
     if (!B || !xs || !res || !o) return fail(SRJ_ERR_INVALID, "NULL argument");
-    for (int i = 0; i < B->count; ++i)
+    for (int i = 0; i < B->count; ++i) {
         if (!xs[i]) return fail(SRJ_ERR_INVALID, "xs[i] is NULL");
+        srj_status chk = check_device_array(xs[i], sizeof(double) * (size_t)B->hdesc[i].npts,
+                                            B->device, "xs[i]");
+        if (chk != SRJ_OK) return chk;
+    }
     srj_solve_opts chk = *o;
     if (!(chk.tol > 0.0)) return fail(SRJ_ERR_INVALID, "tol must be > 0");
     if (chk.max_cycles < 1 || chk.max_sweeps < 1) return fail(SRJ_ERR_INVALID, "caps must be >= 1");

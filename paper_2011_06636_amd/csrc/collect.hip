@@ -183,6 +183,9 @@ srj_status srj_collect(srj_ctx *c, int32_t trials, int32_t max_steps, const doub
     max_level = std::min(max_level, c->nlevels - 1);  // the context's scheme family
     if (c->npoints > kCollectMax)
         return fail(SRJ_ERR_UNSUPPORTED, "collection problems hold at most 1024 points");
+    srj_status chk = check_device_array(u, sizeof(double) * (size_t)trials * (size_t)max_steps,
+                                        c->device, "u");
+    if (chk != SRJ_OK) return chk;
     const int64_t N = c->npoints;
     std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
     for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;

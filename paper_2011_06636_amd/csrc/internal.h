@@ -19,6 +19,12 @@ struct Refine;
 void set_error(const std::string &msg);
 srj_status fail(srj_status st, const std::string &msg);
 
+// Does [p, p + bytes) lie inside one allocation of device (or managed)
+// memory of device dev?  Host memory, pinned or not, is refused: the kernels
+// would fault on pageable memory.  Returns SRJ_OK, or SRJ_ERR_INVALID with a
+// message naming `what`.
+srj_status check_device_array(const void *p, size_t bytes, int dev, const char *what);
+
 #define SRJ_HIP_CHECK(expr)                                                              \
     do {                                                                                 \
         hipError_t _e = (expr);                                                          \
@@ -135,6 +141,7 @@ __device__ __forceinline__ double wave_sum64(double v)
 struct srj_ctx {
     srj::DevProblem P{};
     hipStream_t stream = nullptr;
+    int device = 0;                // current device at setup; caller arrays must live there
     int64_t npoints = 0;
     double *ws = nullptr;          // ping-pong partner of the caller's x
     double *dinv = nullptr;        // 1/diag when diag is given

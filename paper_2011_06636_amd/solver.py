@@ -19,6 +19,26 @@ def _dev(a, device) -> torch.Tensor:
     return t.to(device=device, non_blocking=False).contiguous()
 
 
+def check_iterate(x, device, npoints: int, what: str = "x") -> None:
+    """x must be a contiguous float64 tensor of npoints values on `device`:
+    the library reads and writes it in place through its address."""
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    dev = torch.device(device)
+    if x.device.type != dev.type:
+        raise ValueError(f"{what} is on {x.device}, the solver on {dev}")
+    if dev.type == "cuda":
+        want = dev.index if dev.index is not None else torch.cuda.current_device()
+        if x.device.index != want:
+            raise ValueError(f"{what} is on {x.device}, the solver on cuda:{want}")
+    if x.dtype != torch.float64:
+        raise ValueError(f"{what} must be float64, not {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if x.numel() != npoints:
+        raise ValueError(f"{what} holds {x.numel()} values, the problem {npoints}")
+
+
 def make_problem(ndim: int, n: Sequence[int], c: Sequence[float], dconst: float,
                  b: torch.Tensor, faces: Optional[Sequence[Optional[torch.Tensor]]] = None,
                  diag: Optional[torch.Tensor] = None) -> abi.SrjProblem:
@@ -112,11 +132,11 @@ class Solver:
         return abi.srj_get_profile(self.ctx)
 
     def residual_norm(self, x: torch.Tensor) -> float:
-        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
+        check_iterate(x, self.device, self.npoints)
         return abi.srj_residual_norm(self.ctx, x.data_ptr())
 
     def run_cycle(self, x: torch.Tensor, level: int) -> float:
-        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
+        check_iterate(x, self.device, self.npoints)
         return abi.srj_run_cycle(self.ctx, x.data_ptr(), level)
 
     @staticmethod
@@ -142,10 +162,10 @@ class Solver:
         """Solve in place on x (zeros if None); returns counters, levels and norms."""
         if x is None:
             x = self.zeros()
-        assert x.is_contiguous() and x.dtype == torch.float64 and x.numel() == self.npoints
         o = self.opts(**kw)
         levels = (ctypes.c_int32 * o.max_cycles)()
         norms = (ctypes.c_double * (o.max_cycles + 1))()
+        check_iterate(x, self.device, self.npoints)
         st, res = abi.srj_solve(self.ctx, x.data_ptr(), o, levels, norms)
         if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
             raise abi.SrjError(st, "srj_solve")
@@ -254,6 +274,10 @@ class BatchSolver:
             xs = self.zeros()
         o = Solver.opts(**kw)
         levels = (ctypes.c_int32 * (self.count * o.max_cycles))()
+        if len(xs) != self.count:
+            raise ValueError(f"{len(xs)} iterates for {self.count} instances")
+        for k, (x, sh) in enumerate(zip(xs, self.shapes)):
+            check_iterate(x, self.device, int(np.prod(sh)), f"xs[{k}]")
         st, res = abi.srj_batch_solve(self.handle, [x.data_ptr() for x in xs], o, levels)
         if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
             raise abi.SrjError(st, "srj_batch_solve")
