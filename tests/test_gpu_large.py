@@ -1,0 +1,106 @@
+"""A grid of more than 2^31 points (65536 x 32769, the largest axis-1 extent
+is 65535): every index on the path must be 64-bit.
+
+From x0 = 0 with b = 1 and unit couplings, after one level-1 cycle (two
+sweeps) a point's value depends only on its distance to each boundary, up to
+2, and its residual up to 3.  A 9 x 9 grid computed by the CPU reference
+therefore holds every value the big grid can take: big index i maps to i
+near the low boundary, to 8 - (n - 1 - i) near the high one and to 4
+elsewhere.  Sampled points (corners, edges, rows around the 2^31-th value,
+the last row) must equal the mapped reference values bit for bit, and the
+cycle-end norm must equal the weighted sum of the reference residuals.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+N0, N1 = 65536, 32769
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _map(i, n):
+    return i if i < 4 else (8 - (n - 1 - i) if i >= n - 4 else 4)
+
+
+def _hip():
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+    return hip
+
+
+# The arrays are filled and read with HIP runtime copies on their raw
+# addresses: torch's own kernels on this build did not fill, slice or index a
+# tensor of more than 2^31 values correctly (torch.ones left rows unset, an
+# index gather faulted), so none of them touches these arrays.
+def _row(ptr, j):
+    """Row j of a float64 N1 x N0 device array."""
+    assert 0 <= j < N1, j
+    out = np.empty(N0, dtype=np.float64)
+    assert _hip().hipMemcpy(out.ctypes.data, ptr + 8 * j * N0, 8 * N0, 2) == 0  # device to host
+    return out
+
+
+def _fill_ones(ptr):
+    chunk = 512  # rows per copy
+    ones = np.ones(chunk * N0, dtype=np.float64)
+    hip = _hip()
+    for j0 in range(0, N1, chunk):
+        rows = min(chunk, N1 - j0)
+        assert 0 < rows and j0 + rows <= N1
+        assert hip.hipMemcpy(ptr + 8 * j0 * N0, ones.ctypes.data, 8 * rows * N0, 1) == 0  # host to device
+
+
+def test_more_than_2_31_points(torch_cuda, orc):
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import make_problem
+    torch = torch_cuda
+    assert N0 * N1 > 2 ** 31
+    small = workloads.anisotropic([9, 9], (1.0, 1.0), np.ones((1, 9, 9)))
+    xs = np.zeros(small.shape)
+    for w in orc.scheme(1):
+        xs = orc.sweep(small, xs, float(w))
+    rs = (small.b - orc.apply(small, xs)).reshape(9, 9)
+    xs = xs.reshape(9, 9)
+    wt = np.array([1.0] * 4 + [0.0] + [1.0] * 4)
+    w0, w1 = wt.copy(), wt.copy()
+    w0[4], w1[4] = N0 - 8, N1 - 8
+    want_norm = math.sqrt(float(np.sum(w1[:, None] * w0[None, :] * rs * rs)))
+
+    b = torch.empty(N1 * N0, dtype=torch.float64, device="cuda")
+    x = torch.empty(N1 * N0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    assert _hip().hipMemset(x.data_ptr(), 0, 8 * N1 * N0) == 0
+    _fill_ones(b.data_ptr())
+    flat = (2 ** 31) // N0  # the row holding the 2^31-th value (the last row here)
+    assert flat == N1 - 1
+    rows = [0, 1, 2, 3, 4, 5, N1 // 2, N1 - 6, N1 - 5, N1 - 4, N1 - 3, N1 - 2, flat]
+    cols = [0, 1, 2, 3, 4, 7, N0 // 2, N0 - 5, N0 - 4, N0 - 3, N0 - 1]
+    for j in rows:
+        assert np.all(_row(b.data_ptr(), j) == 1.0) and np.all(_row(x.data_ptr(), j) == 0.0), j
+    p = make_problem(2, [N0, N1, 1], [1.0, 1.0, 0.0], 4.0, b)
+    ctx = abi.srj_setup(p, torch.cuda.current_stream().cuda_stream)
+    try:
+        nrm = abi.srj_run_cycle(ctx, x.data_ptr(), 1)
+        torch.cuda.synchronize()
+        got = np.stack([_row(x.data_ptr(), j)[cols] for j in rows])
+        want = np.array([[xs[_map(j, N1), _map(i, N0)] for i in cols] for j in rows])
+        assert np.array_equal(got, want)
+        assert nrm == pytest.approx(want_norm, rel=1e-10)
+    finally:
+        abi.srj_destroy(ctx)
+    del x, b
+    torch.cuda.empty_cache()
