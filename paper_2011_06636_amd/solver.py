@@ -19,28 +19,6 @@ def _dev(a, device) -> torch.Tensor:
     return t.to(device=device, non_blocking=False).contiguous()
 
 
-_HIP = None
-
-
-def zeros_f64(shape, device, stream=None) -> torch.Tensor:
-    """A zeroed float64 device tensor.  Above 2^31 values the memory is cleared
-    with hipMemsetAsync on the stream: torch's fill kernels on this build do
-    not reach every value of such a tensor."""
-    n = int(np.prod(shape))
-    if n < 2 ** 31:
-        return torch.zeros(shape, dtype=torch.float64, device=device)
-    global _HIP
-    if _HIP is None:
-        _HIP = ctypes.CDLL("libamdhip64.so")
-        _HIP.hipMemsetAsync.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
-    t = torch.empty(shape, dtype=torch.float64, device=device)
-    st = stream if stream is not None else torch.cuda.current_stream(t.device)
-    if _HIP.hipMemsetAsync(t.data_ptr(), 0, 8 * n, st.cuda_stream) != 0:
-        raise RuntimeError("hipMemsetAsync failed")
-    st.synchronize()
-    return t
-
-
 def check_iterate(x, device, npoints: int, what: str = "x") -> None:
     """x must be a contiguous float64 tensor of npoints values on `device`:
     the library reads and writes it in place through its address."""
@@ -125,7 +103,7 @@ class Solver:
             pass
 
     def zeros(self) -> torch.Tensor:
-        return zeros_f64(self.shape, self.device, self.stream)
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
 
     def to_device(self, a) -> torch.Tensor:
         return _dev(np.asarray(a).reshape(self.shape), self.device)
