@@ -171,7 +171,9 @@ srj_status run_sweeps(srj_ctx *c, double **cur, double **nxt, int level)
     if (c->plan.kind != 0 && fused_supported(c->P, c->plan)) {
         for (int done = 0; done < M;) {
             const int T = std::min(c->plan.T, M - done);
-            SRJ_HIP_CHECK(launch_sweep_fused(c->P, c->plan, *cur, *nxt, wdev + done, T, c->stream));
+            SRJ_HIP_CHECK(
+                launch_sweep_fused(c->P, c->plan, *cur, *nxt, wdev + done, T, c->stream, c->reverse));
+            c->reverse = !c->reverse;
             std::swap(*cur, *nxt);
             done += T;
             ++launches;

@@ -232,24 +232,29 @@ __global__ __launch_bounds__(64 * NW) void k_block2d(int64_t n0, int64_t n1,
                                                      const typename V::T *__restrict__ b,
                                                      const typename V::A *__restrict__ wlist, int T,
                                                      Coef2D<typename V::A> k2, int blocks_x,
-                                                     int nblocks, int vec)
+                                                     int nblocks, int vec, int reverse)
 {
     using A = typename V::A;
     __shared__ A edge[2 * 2 * NW * C * 64];
     // XCD-aware order: hardware places block i on XCD i % 8; each XCD takes a
     // contiguous range of logical blocks so neighbouring blocks share its L2.
+    // Every other launch walks each range backwards, so a launch starts with
+    // the blocks the previous one finished last, whose data its L2 still holds.
     const int per_xcd = (nblocks + 7) / 8;
-    const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int j = blockIdx.x / 8;
+    const int logical = (blockIdx.x % 8) * per_xcd + (reverse ? per_xcd - 1 - j : j);
     if (logical >= nblocks) return;  // whole block leaves
     block2d_item<V, HW, HALO, NW, C>(n0, n1, x, xo, b, wlist, T, k2, logical % blocks_x,
                                      logical / blocks_x, vec != 0, threadIdx.x >> 6,
                                      threadIdx.x & 63, edge, 0);
 }
 
+// reverse: walk each XCD's range of blocks backwards (callers alternate it
+// from launch to launch; the result does not depend on it).
 template <class V, int HW, int HALO, int NW, int C>
 hipError_t launch_block2d(int64_t n0, int64_t n1, const typename V::T *x, typename V::T *xo,
                           const typename V::T *b, const typename V::A *w_dev, int T,
-                          Coef2D<typename V::A> k2, hipStream_t s)
+                          Coef2D<typename V::A> k2, hipStream_t s, bool reverse = false)
 {
     constexpr int OW = BlockShape<HW, HALO, NW, C>::OW, OH = BlockShape<HW, HALO, NW, C>::OH;
     if (T < 1 || T > HALO) return hipErrorInvalidValue;
@@ -265,7 +270,7 @@ hipError_t launch_block2d(int64_t n0, int64_t n1, const typename V::T *x, typena
     // a multiple of 8 blocks, so the XCD mapping covers every logical block
     const int grid = (int)((nblocks + 7) / 8 * 8);
     hipLaunchKernelGGL((k_block2d<V, HW, HALO, NW, C>), dim3(grid), dim3(64 * NW), 0, s, n0, n1,
-                       x, xo, b, w_dev, T, k2, (int)bxn, (int)nblocks, vec);
+                       x, xo, b, w_dev, T, k2, (int)bxn, (int)nblocks, vec, reverse ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -113,8 +113,11 @@ struct UpdState {
 hipError_t launch_sweep_upd(const DevProblem &P, const double *x, double *xo, double w, double tol,
                             UpdState *st, int64_t g, hipStream_t s);
 // Fused sweeps: applies w[0..T-1] (device pointer into the scheme table).
+// reverse alternates the block order of the block kernels (callers flip it
+// every launch); results do not depend on it.
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
-                              double *xo, const double *w_dev, int T, hipStream_t s);
+                              double *xo, const double *w_dev, int T, hipStream_t s,
+                              bool reverse = false);
 bool fused_supported(const DevProblem &P, const SweepPlan &plan);
 // Lists the fused variants as (kind, rows, halo, occ); returns how many exist.
 int plan_variants(int32_t *out, int cap);
@@ -142,6 +145,7 @@ struct srj_ctx {
     srj::DevProblem P{};
     hipStream_t stream = nullptr;
     int device = 0;                // current device at setup; caller arrays must live there
+    bool reverse = false;          // block order of the next fused launch (flips every launch)
     int64_t npoints = 0;
     double *ws = nullptr;          // ping-pong partner of the caller's x
     double *dinv = nullptr;        // 1/diag when diag is given

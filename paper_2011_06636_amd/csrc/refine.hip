@@ -155,7 +155,8 @@ dim3 row_grid(int64_t n0, int64_t n1, int64_t n2)
 
 template <class St>
 hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, const void *d, void *dout,
-                              const void *rhat, const float *w_dev, int T, hipStream_t s)
+                              const void *rhat, const float *w_dev, int T, hipStream_t s,
+                              bool reverse = false)
 {
     using TT = typename St::T;
     const Coef2D<float> k2{Q.dconst, Q.dinvconst, Q.c[0], Q.c[1]};
@@ -165,10 +166,10 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
     if (plan.kind == 7 || plan.kind == 8) {
 #define SRJ_GO1(HW, HL, NW)                                                         \
     if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
-        return launch_block2d<St, HW, HL, NW, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
+        return launch_block2d<St, HW, HL, NW, 1>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s, reverse);
 #define SRJ_GO2(HW, HL, NW)                                                         \
     if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
-        return launch_block2d<St, HW, HL, NW, 2>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s);
+        return launch_block2d<St, HW, HL, NW, 2>(Q.n0, Q.n1, dd, oo, rr, w_dev, T, k2, s, reverse);
         if (plan.kind == 7) { SRJ_INNER_BLOCK_VARIANTS(SRJ_GO1) }
         else { SRJ_INNER_BLOCK2_VARIANTS(SRJ_GO2) }
 #undef SRJ_GO1
@@ -520,7 +521,8 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
                 for (int done = 0; done < M;) {
                     const int T = std::min(c->plan_inner.T, M - done);
                     SRJ_HIP_CHECK(launch_inner_fused<St>(c->plan_inner, Q, da, db, R->rhat,
-                                                         w32dev + done, T, c->stream));
+                                                         w32dev + done, T, c->stream, c->reverse));
+                    c->reverse = !c->reverse;
                     std::swap(da, db);
                     done += T;
                     ++launches;
@@ -602,13 +604,17 @@ srj_status time_inner_plan(srj_ctx *c, const SweepPlan &plan, int sweeps, const 
     if (st != SRJ_OK) return st;
     st = zero_storage<StF32>(c, R->rhat);
     if (st != SRJ_OK) return st;
+    bool reverse = false;
     auto run = [&](int n) -> srj_status {
         for (int done = 0; done < n;) {
             const int T = fused ? std::min(plan.T, n - done) : 1;
-            if (fused)
-                SRJ_HIP_CHECK(launch_inner_fused<StF32>(plan, Q, da, db, R->rhat, w_dev, T, c->stream));
-            else
+            if (fused) {
+                SRJ_HIP_CHECK(launch_inner_fused<StF32>(plan, Q, da, db, R->rhat, w_dev, T, c->stream,
+                                                        reverse));
+                reverse = !reverse;
+            } else {
                 SRJ_HIP_CHECK(launch_inner<StF32>(Q, da, db, R->rhat, 0.6666667f, c->stream));
+            }
             std::swap(da, db);
             done += T;
         }

@@ -311,16 +311,16 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 }
 
 hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const double *x,
-                              double *xo, const double *w_dev, int T, hipStream_t s)
+                              double *xo, const double *w_dev, int T, hipStream_t s, bool reverse)
 {
     if (plan.kind == 7 || plan.kind == 8) {
         const Coef2D<double> kb{P.dconst, P.dinvconst, P.c[0], P.c[1]};
 #define SRJ_GO1(HW, HL, NW)                                                         \
     if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
-        return launch_block2d<StF64, HW, HL, NW, 1>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s);
+        return launch_block2d<StF64, HW, HL, NW, 1>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s, reverse);
 #define SRJ_GO2(HW, HL, NW)                                                         \
     if (plan.by == HW && plan.occ == NW && plan.T <= HL)                            \
-        return launch_block2d<StF64, HW, HL, NW, 2>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s);
+        return launch_block2d<StF64, HW, HL, NW, 2>(P.n0, P.n1, x, xo, P.b, w_dev, T, kb, s, reverse);
         if (plan.kind == 7) { SRJ_BLOCK_VARIANTS(SRJ_GO1) }
         else { SRJ_BLOCK2_VARIANTS(SRJ_GO2) }
 #undef SRJ_GO1

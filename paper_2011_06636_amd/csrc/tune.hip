@@ -133,13 +133,16 @@ srj_status time_f64_plan(srj_ctx *c, const SweepPlan &plan, int sweeps, double *
     const bool fused = plan.kind != 0;
     double *a = c->ws, *b = scratch;
     SRJ_HIP_CHECK(hipMemsetAsync(a, 0, sizeof(double) * (size_t)c->npoints, c->stream));
+    bool reverse = false;
     auto run = [&](int n) -> srj_status {
         for (int done = 0; done < n;) {
             const int T = fused ? std::min(plan.T, n - done) : 1;
-            if (fused)
-                SRJ_HIP_CHECK(launch_sweep_fused(c->P, plan, a, b, w_dev, T, c->stream));
-            else
+            if (fused) {
+                SRJ_HIP_CHECK(launch_sweep_fused(c->P, plan, a, b, w_dev, T, c->stream, reverse));
+                reverse = !reverse;
+            } else {
                 SRJ_HIP_CHECK(launch_sweep_generic(c->P, a, b, 2.0 / 3.0, c->stream));
+            }
             std::swap(a, b);
             done += T;
         }
