@@ -502,7 +502,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is design-only in this build)", file=sys.stderr)
+              "(the library runs on one GPU; sharding over several is designed, not built)",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -68,7 +68,7 @@ typedef enum {
     SRJ_ERR_HIP = 3,           /* a HIP runtime call failed */
     SRJ_ERR_NOT_CONVERGED = 4, /* a cap was reached; results are filled */
     SRJ_ERR_NONFINITE = 5,     /* a residual norm was NaN/Inf; x holds the last iterate */
-    SRJ_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+    SRJ_ERR_UNSUPPORTED = 6    /* valid request the library does not implement */
 } srj_status;
 
 typedef enum {
