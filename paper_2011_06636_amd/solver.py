@@ -19,6 +19,25 @@ def _dev(a, device) -> torch.Tensor:
     return t.to(device=device, non_blocking=False).contiguous()
 
 
+class _Ordered:
+    """Orders the library's stream after the caller's current stream on entry
+    (the tensors it reads were produced there) and the caller's stream after
+    the library's on exit."""
+
+    def __init__(self, device, stream):
+        self.device, self.stream = device, stream
+
+    def __enter__(self):
+        self.cur = torch.cuda.current_stream(self.device)
+        if self.cur != self.stream:
+            self.stream.wait_stream(self.cur)
+
+    def __exit__(self, *exc):
+        if self.cur != self.stream:
+            self.cur.wait_stream(self.stream)
+        return False
+
+
 def check_iterate(x, device, npoints: int, what: str = "x") -> None:
     """x must be a contiguous float64 tensor of npoints values on `device`:
     the library reads and writes it in place through its address."""
@@ -133,11 +152,13 @@ class Solver:
 
     def residual_norm(self, x: torch.Tensor) -> float:
         check_iterate(x, self.device, self.npoints)
-        return abi.srj_residual_norm(self.ctx, x.data_ptr())
+        with _Ordered(self.device, self.stream):
+            return abi.srj_residual_norm(self.ctx, x.data_ptr())
 
     def run_cycle(self, x: torch.Tensor, level: int) -> float:
         check_iterate(x, self.device, self.npoints)
-        return abi.srj_run_cycle(self.ctx, x.data_ptr(), level)
+        with _Ordered(self.device, self.stream):
+            return abi.srj_run_cycle(self.ctx, x.data_ptr(), level)
 
     @staticmethod
     def opts(rule: str = "heuristic", fixed_level: int = 0, tol: float = 1e-10,
@@ -166,7 +187,8 @@ class Solver:
         levels = (ctypes.c_int32 * o.max_cycles)()
         norms = (ctypes.c_double * (o.max_cycles + 1))()
         check_iterate(x, self.device, self.npoints)
-        st, res = abi.srj_solve(self.ctx, x.data_ptr(), o, levels, norms)
+        with _Ordered(self.device, self.stream):
+            st, res = abi.srj_solve(self.ctx, x.data_ptr(), o, levels, norms)
         if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
             raise abi.SrjError(st, "srj_solve")
         nc = res.cycles
@@ -278,7 +300,8 @@ class BatchSolver:
             raise ValueError(f"{len(xs)} iterates for {self.count} instances")
         for k, (x, sh) in enumerate(zip(xs, self.shapes)):
             check_iterate(x, self.device, int(np.prod(sh)), f"xs[{k}]")
-        st, res = abi.srj_batch_solve(self.handle, [x.data_ptr() for x in xs], o, levels)
+        with _Ordered(self.device, self.stream):
+            st, res = abi.srj_batch_solve(self.handle, [x.data_ptr() for x in xs], o, levels)
         if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
             raise abi.SrjError(st, "srj_batch_solve")
         lv = np.array(levels, dtype=np.int32).reshape(self.count, o.max_cycles)
