@@ -64,7 +64,7 @@ def parse():
                     help="skip the 3D and batched comparison legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target length of the CPU oracle sample (0 = skip)")
-    ap.add_argument("--only", choices=["c3", "c4", "c5", "training", "neumann", "general"],
+    ap.add_argument("--only", choices=["c3", "c4", "c5", "c2vc", "training", "neumann", "general"],
                     default="", help="run one comparison leg alone and print its record")
     ap.add_argument("--c3-cycles", type=int, default=200,
                     help="cycle cap of each 3D variable-coefficient solve")
@@ -201,6 +201,41 @@ def extra_c3(max_cycles=200):
         print(f"# c3 {prec}: {dt * 1e3:.1f} ms {out['status']}", file=sys.stderr, flush=True)
     if rec["f64"]["converged"] and rec["f32"]["converged"]:
         rec["f32_refined_speedup_time_to_tol"] = round(rec["f64"]["time_ms"] / rec["f32"]["time_ms"], 3)
+    s.close()
+    return rec
+
+
+def extra_c2_varcoef(n=2048, cycles=40):
+    """2D variable-coefficient n x n grid (per-face couplings and diagonal):
+    the same capped solve with one sweep per launch and with the default
+    fused per-face block plan (bit-identical iterates)."""
+    import numpy as np
+    import workloads
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.variable_coefficient_2d(n, n, seed=0)
+    s = Solver(prob)
+    default = tuple(s.get_plan(0))
+    rec = {"workload": f"2D -div(k grad u) = 1, 5-point, {n}x{n}, k log-normal (sigma 1, "
+                       f"correlation 8 cells, seed 0), x0 = 0, first {cycles} cycles of "
+                       "Algorithm 1 (relative residual 1e-10 or the cap)",
+           "plan_default": list(default)}
+    runs = {}
+    for name, plan in (("one_sweep", (0, 0, 1, 1)), ("default", default)):
+        assert s.set_plan(*plan) == 0
+        x = s.zeros()
+        s.solve(x, tol=1e-10, max_cycles=2)
+        x.zero_()
+        out, dt = _timed(lambda: s.solve(x, tol=1e-10, max_cycles=cycles))
+        runs[name] = (out, x.cpu().numpy())
+        rec[name] = {"plan": list(plan), "cycles": out["cycles"], "sweeps": out["sweeps"],
+                     "time_ms": round(dt * 1e3, 3),
+                     "GLUPS": round(out["sweeps"] * prob.npoints / dt / 1e9, 3),
+                     "final_rel_residual": float(out["norms"][-1] / out["r0"])}
+        print(f"# c2 varcoef {name} {plan}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    a, b = runs["one_sweep"], runs["default"]
+    rec["bit_identical"] = bool(np.array_equal(a[0]["levels"], b[0]["levels"])
+                                and np.array_equal(a[1], b[1]))
+    rec["speedup"] = round(rec["one_sweep"]["time_ms"] / rec["default"]["time_ms"], 3)
     s.close()
     return rec
 
@@ -521,7 +556,8 @@ def main():
         del src, dst
     if args.only:
         legs = {"c3": lambda: extra_c3(args.c3_cycles), "c4": lambda: extra_batch("c4"),
-                "c5": lambda: extra_batch("c5"), "training": extra_training,
+                "c5": lambda: extra_batch("c5"), "c2vc": extra_c2_varcoef,
+                "training": extra_training,
                 "neumann": extra_neumann, "general": extra_general}
         print(json.dumps({"only": args.only, "record": legs[args.only]()}), flush=True)
         return
@@ -605,7 +641,8 @@ def main():
     del x
     if not args.no_extras:
         rec["extras"] = {"c3_3d_varcoef": extra_c3(args.c3_cycles), "c4_batch_2d": extra_batch("c4"),
-                         "c5_batch_3d": extra_batch("c5"), "selector_training": extra_training(),
+                         "c5_batch_3d": extra_batch("c5"), "c2_2d_varcoef": extra_c2_varcoef(),
+                         "selector_training": extra_training(),
                          "neumann_update_test": extra_neumann(),
                          "general_matrices": extra_general()}
     if args.cpu_seconds > 0:

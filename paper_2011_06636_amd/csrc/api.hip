@@ -152,6 +152,17 @@ SweepPlan default_plan(const DevProblem &P)
         pl.T = wide_blocks >= 512 ? 10 : 8;
         pl.occ = 8;
     }
+    if (P.ndim == 2 && P.face[0] && P.face[1] && P.diag && P.n0 >= 64 && P.n1 >= 64) {
+        // per-face blocks (kind 10): 8 waves x 8 rows, 8 sweeps per launch
+        // (48 x 48 written points) on grids of at least 1024 such blocks;
+        // smaller grids take 16 waves x 4 rows and 12 sweeps (40 x 40 written
+        // points), fewer launches per cycle for about as many blocks
+        const int64_t blocks = ((P.n0 + 47) / 48) * ((P.n1 + 47) / 48);
+        pl.kind = 10;
+        pl.by = blocks >= 1024 ? 8 : 4;
+        pl.T = blocks >= 1024 ? 8 : 12;
+        pl.occ = blocks >= 1024 ? 8 : 16;
+    }
     return pl;
 }
 

@@ -1,0 +1,177 @@
+// 2D relaxed Jacobi sweeps with per-face couplings and a per-point diagonal,
+// fused over blocks of cooperating waves (plan kind 10).
+//
+// Same per-point expression as every other kernel (Islam & Wang, arXiv
+// 2011.06636, section 2, Eq. 3 in residual form, no fused multiply-add):
+//   s = D_p x_p - f0[p-1] x[p-1] - f0[p] x[p+1] - f1[p-n0] x[p-n0] - f1[p] x[p+n0]
+//   x'_p = x_p + w (Dinv_p (b_p - s))
+// so results are bit-identical to the one-sweep kernel and the CPU reference.
+//
+// The block layout is that of block2d.h with one column per lane: NW waves
+// hold HW rows each of 64 columns, halo included, with x, b, both face
+// couplings, D and 1/D of every point in registers.  f0[p-1] x[p-1] is the
+// left lane's own product f0 x, moved one lane by DPP; x[p+1] comes from the
+// right lane by DPP.  f1[p-n0] x[p-n0] is the row below's product f1 x, kept
+// from that row (formed from its value before the sweep) or, for a wave's
+// first row, published in LDS by the wave below; x[p+n0] of a wave's last row
+// is the wave above's first row, also through LDS (one barrier per sweep).
+// Points outside the grid load zero values and zero coefficients, so their
+// terms vanish (f x with x = 0) and they stay zero.
+#pragma once
+
+#include "block2d.h"
+#include "internal.h"
+#include "tile2d.h"
+
+#pragma clang fp contract(off)
+
+namespace srj {
+
+template <int HW, int NW, bool MASK>
+__device__ __forceinline__ void blockf_sweeps(double (&xr)[HW], const double (&br)[HW],
+                                              const double (&fe)[HW], const double (&fn)[HW],
+                                              const double (&dd)[HW], const double (&di)[HW],
+                                              bool col_in, uint32_t rowbits,
+                                              const double *__restrict__ wlist, int T,
+                                              double *edge, int wave, int lane)
+{
+    for (int k = 0; k < T; ++k) {
+        // edge: [2 buffers][0: first row's x, 1: last row's f1 x][NW][64]
+        double *e = edge + (k & 1) * (2 * NW * 64);
+        e[wave * 64 + lane] = xr[0];
+        e[(NW + wave) * 64 + lane] = fn[HW - 1] * xr[HW - 1];
+        __syncthreads();
+        // rows outside the block read zero (they only feed halo rows)
+        double pdown = wave > 0 ? e[(NW + wave - 1) * 64 + lane] : 0.0;
+        const double xup = wave + 1 < NW ? e[(wave + 1) * 64 + lane] : 0.0;
+        const double w = wlist[k];
+#pragma unroll
+        for (int r = 0; r < HW; ++r) {
+            const double xc = xr[r];
+            const double pl = dpp_prev(fe[r] * xc);  // f0[p-1] x[p-1]: the left lane's product
+            const double xrt = dpp_next(xc);          // x[p+1]
+            const double xu = r + 1 < HW ? xr[r + 1] : xup;
+            const double pn = fn[r] * xc;  // f1 x of this row, the down term of the row above
+            double s = dd[r] * xc;
+            s = s - pl;
+            s = s - fe[r] * xrt;
+            s = s - pdown;
+            s = s - fn[r] * xu;
+            const double rr = br[r] - s;
+            const double t = di[r] * rr;
+            const double nx = xc + w * t;
+            pdown = pn;
+            if (MASK)
+                xr[r] = (col_in && ((rowbits >> r) & 1)) ? nx : 0.0;
+            else
+                xr[r] = nx;
+        }
+    }
+}
+
+// One wave's part of one block (see block2d_run for the addressing and the
+// treatment of blocks that cross the grid's edge).
+template <int HW, int HALO, int NW, bool EDGE>
+__device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1, const double *__restrict__ x,
+                                           double *__restrict__ xo, const double *__restrict__ b,
+                                           const double *__restrict__ f0,
+                                           const double *__restrict__ f1,
+                                           const double *__restrict__ dg,
+                                           const double *__restrict__ dgi,
+                                           const double *__restrict__ wlist, int T, int64_t bx0,
+                                           int64_t by0, int wv, int lane, double *edge)
+{
+    using S = BlockShape<HW, HALO, NW, 1>;
+    const int64_t gy0 = by0 + (int64_t)wv * HW;
+    const int64_t gx = bx0 + lane;
+    const bool col_in = !EDGE || (gx >= 0 && gx < n0);
+    const uint32_t off = col_in ? (uint32_t)gx : 0u;
+    uint32_t rowbits = ~0u;
+    if (EDGE) {
+        rowbits = 0;
+#pragma unroll
+        for (int r = 0; r < HW; ++r)
+            if (gy0 + r >= 0 && gy0 + r < n1) rowbits |= 1u << r;
+    }
+    auto row_of = [&](int r) -> int64_t {
+        const int64_t gy = gy0 + r;
+        return EDGE ? (gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy)) : gy;
+    };
+    double xr[HW], br[HW], fe[HW], fn[HW], dd[HW], di[HW];
+#pragma unroll
+    for (int r = 0; r < HW; ++r) {
+        const int64_t base = row_of(r) * n0 + off;
+        const bool in = !EDGE || (((rowbits >> r) & 1) && col_in);
+        const double vx = x[base], vb = b[base], v0 = f0[base], v1 = f1[base], vd = dg[base],
+                     vi = dgi[base];
+        xr[r] = in ? vx : 0.0;
+        br[r] = in ? vb : 0.0;
+        fe[r] = in ? v0 : 0.0;
+        fn[r] = in ? v1 : 0.0;
+        dd[r] = in ? vd : 0.0;
+        di[r] = in ? vi : 0.0;
+    }
+    blockf_sweeps<HW, NW, EDGE>(xr, br, fe, fn, dd, di, col_in, rowbits, wlist, T, edge, wv, lane);
+    if (!(lane >= HALO && lane < S::BW - HALO) || !col_in) return;
+    const int rlo = HALO - wv * HW, rhi = S::BH - HALO - wv * HW;
+#pragma unroll
+    for (int r = 0; r < HW; ++r)
+        if (r >= rlo && r < rhi && ((rowbits >> r) & 1)) xo[row_of(r) * n0 + off] = xr[r];
+}
+
+template <int HW, int HALO, int NW>
+__global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
+                                                      const double *__restrict__ x,
+                                                      double *__restrict__ xo,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ f0,
+                                                      const double *__restrict__ f1,
+                                                      const double *__restrict__ dg,
+                                                      const double *__restrict__ dgi,
+                                                      const double *__restrict__ wlist, int T,
+                                                      int blocks_x, int nblocks, int reverse)
+{
+    __shared__ double edge[2 * 2 * NW * 64];
+    // XCD-aware order, each XCD's range walked backwards on alternate launches
+    // (as in block2d.h)
+    const int per_xcd = (nblocks + 7) / 8;
+    const int j = blockIdx.x / 8;
+    const int logical = (blockIdx.x % 8) * per_xcd + (reverse ? per_xcd - 1 - j : j);
+    if (logical >= nblocks) return;  // whole block leaves
+    using S = BlockShape<HW, HALO, NW, 1>;
+    const int64_t bx0 = (int64_t)(logical % blocks_x) * S::OW - HALO;
+    const int64_t by0 = (int64_t)(logical / blocks_x) * S::OH - HALO;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (bx0 >= 0 && bx0 + S::BW <= n0 && by0 >= 0 && by0 + S::BH <= n1)
+        blockf_run<HW, HALO, NW, false>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0, wv,
+                                        lane, edge);
+    else
+        blockf_run<HW, HALO, NW, true>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0, wv,
+                                       lane, edge);
+}
+
+template <int HW, int HALO, int NW>
+hipError_t launch_blockf2d(int64_t n0, int64_t n1, const double *x, double *xo, const double *b,
+                           const double *f0, const double *f1, const double *dg,
+                           const double *dgi, const double *w_dev, int T, hipStream_t s,
+                           bool reverse)
+{
+    using S = BlockShape<HW, HALO, NW, 1>;
+    if (T < 1 || T > HALO) return hipErrorInvalidValue;
+    if (n0 > INT32_MAX) return hipErrorInvalidValue;  // column offsets are 32-bit
+    if (!f0 || !f1 || !dg || !dgi) return hipErrorInvalidValue;
+    const int64_t bxn = (n0 + S::OW - 1) / S::OW, byn = (n1 + S::OH - 1) / S::OH;
+    const int64_t nblocks = bxn * byn;
+    if (nblocks > (int64_t)1 << 28) return hipErrorInvalidValue;
+    const int grid = (int)((nblocks + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_blockf2d<HW, HALO, NW>), dim3(grid), dim3(64 * NW), 0, s, n0, n1, x, xo,
+                       b, f0, f1, dg, dgi, w_dev, T, (int)bxn, (int)nblocks, reverse ? 1 : 0);
+    return hipGetLastError();
+}
+
+// (rows per wave, halo = most sweeps per launch, waves per block) of the
+// per-face block plans (kind 10)
+#define SRJ_BLOCKF_VARIANTS(X) X(4, 6, 8) X(4, 8, 16) X(4, 12, 16) X(6, 8, 8) X(8, 8, 8)
+
+}  // namespace srj

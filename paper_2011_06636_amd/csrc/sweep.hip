@@ -14,6 +14,7 @@
 #include "wave2d.h"
 #include "plane3d.h"
 #include "block2d.h"
+#include "block2d_face.h"
 
 #pragma clang fp contract(off)
 
@@ -222,6 +223,9 @@ int plan_variants(int32_t *out, int cap)
 #define KIND 8
     SRJ_BLOCK2_VARIANTS(SRJ_LIST7)
 #undef KIND
+#define KIND 10
+    SRJ_BLOCKF_VARIANTS(SRJ_LIST7)
+#undef KIND
 #undef SRJ_LIST7
 #define SRJ_LIST6(HH, ZZ)              \
     if (n < cap) {                     \
@@ -276,6 +280,13 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
 #undef SRJ_CHK
         return false;
     }
+    if (plan.kind == 10) {
+        if (!(P.ndim == 2 && P.face[0] && P.face[1] && P.diag && P.dinv) || plan.T < 1) return false;
+#define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
+        SRJ_BLOCKF_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 6) {
         if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1 ||
             plan.occ < 1)
@@ -325,6 +336,15 @@ hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const 
         else { SRJ_BLOCK2_VARIANTS(SRJ_GO2) }
 #undef SRJ_GO1
 #undef SRJ_GO2
+        return hipErrorInvalidValue;
+    }
+    if (plan.kind == 10) {
+#define SRJ_GOF(HW, HL, NW)                                                                   \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL)                                      \
+        return launch_blockf2d<HW, HL, NW>(P.n0, P.n1, x, xo, P.b, P.face[0], P.face[1], P.diag, \
+                                           P.dinv, w_dev, T, s, reverse);
+        SRJ_BLOCKF_VARIANTS(SRJ_GOF)
+#undef SRJ_GOF
         return hipErrorInvalidValue;
     }
     if (plan.kind == 6) {

@@ -134,6 +134,70 @@ def test_fused_plans_bit_identical(torch_cuda, orc, n0, n1):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["varcoef_517x263", "varcoef_200x97", "varcoef_64x64",
+                                  "varcoef_30x20", "varcoef_130x1", "varcoef_1x77",
+                                  "neumann_70", "neumann_131"])
+def test_face_block_plans_bit_identical(torch_cuda, orc, case):
+    # the 2D per-face block kernels (plan kind 10, every shape and sweep count)
+    # give the bits of the one-sweep kernel on variable-coefficient and
+    # Neumann grids with ragged blocks, grids smaller than one block, and
+    # single rows and columns; the oracle agrees
+    from paper_2011_06636_amd import abi
+    kind_, dims = case.split("_")
+    if kind_ == "neumann":
+        prob = workloads.neumann_laplace(int(dims))
+    else:
+        n0, n1 = (int(v) for v in dims.split("x"))
+        prob = workloads.variable_coefficient_2d(n0, n1, seed=n0 + n1, corr_len=6.0)
+    s = _solver(prob)
+    x0 = np.random.default_rng(8).uniform(-1, 1, prob.shape)
+    plans = [(0, 0, 1, 1)]
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        if kind == 10:
+            plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+    assert len(plans) > 1
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in (0, 3, 8):
+            s.run_cycle(x, level)
+        results[plan] = x.cpu().numpy()
+    base = results[(0, 0, 1, 1)]
+    for plan, v in results.items():
+        assert np.array_equal(v, base), plan
+    x_ref = x0.copy()
+    for level in (0, 3, 8):
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    assert _close(base, x_ref)
+    s.close()
+
+
+def test_face_block_plans_need_faces(torch_cuda):
+    # kind 10 takes per-face couplings and a per-point diagonal only
+    from paper_2011_06636_amd import abi
+    s = _solver(workloads.poisson([40, 30]))
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        if kind == 10:
+            assert s.set_plan(kind, rows, halo, occ) != 0
+    s.close()
+    s = _solver(workloads.variable_coefficient(12, seed=1))
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        if kind == 10:
+            assert s.set_plan(kind, rows, halo, occ) != 0
+    s.close()
+    s = _solver(workloads.variable_coefficient_2d(40, 30, seed=1))
+    most = {}
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        if kind == 10:
+            assert s.set_plan(kind, rows, halo, occ) == 0
+            most[rows, occ] = max(halo, most.get((rows, occ), 0))
+    for (rows, occ), halo in most.items():  # more sweeps than any halo of that shape
+        assert s.set_plan(10, rows, halo + 1, occ) != 0
+    s.close()
+
+
 @pytest.mark.parametrize("case", ["poisson", "varcoef", "aniso"])
 def test_3d_plans_bit_identical(torch_cuda, orc, case):
     # the z-streaming 3D kernels (every chunk length) give the bits of the
@@ -217,6 +281,15 @@ def test_default_2d_plan_follows_grid_size(torch_cuda):
                          (108 * 32, 44 * 15 + 1, (8, 8, 10, 8)), (108 * 32, 44 * 15, (7, 8, 8, 8))):
         s = Solver(workloads.poisson([n0, n1], b=np.zeros((1, n1, n0))))
         assert tuple(s.get_plan(0)) == want, (n0, n1, s.get_plan(0))
+        s.close()
+    # per-face grids: 8 waves x 8 rows and 8 sweeps from 1024 blocks of
+    # 48 x 48 written points, else 16 waves x 4 rows and 12 sweeps; the inner
+    # sweeps of the refinement modes one per launch
+    for n0, n1, want in ((48 * 32, 48 * 32, (10, 8, 8, 8)), (48 * 32, 48 * 31, (10, 4, 12, 16)),
+                         (64, 64, (10, 4, 12, 16)), (63, 200, (0, 0, 1, 1))):
+        s = Solver(workloads.variable_coefficient_2d(n0, n1, seed=0))
+        assert tuple(s.get_plan(0)) == want, (n0, n1, s.get_plan(0))
+        assert s.get_plan(1)[0] == 0
         s.close()
 
 

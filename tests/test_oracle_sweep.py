@@ -32,10 +32,13 @@ def small_problems():
     vc = workloads.variable_coefficient(3, seed=4, corr_len=1.5)
     vc.b = rng.uniform(-1, 1, vc.shape)
     out.append(vc)
+    vc2 = workloads.variable_coefficient_2d(5, 4, seed=5, corr_len=1.5)
+    vc2.b = rng.uniform(-1, 1, vc2.shape)
+    out.append(vc2)
     return out
 
 
-@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("k", range(7))
 def test_apply_matches_dense(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)
@@ -45,7 +48,7 @@ def test_apply_matches_dense(orc, k):
     np.testing.assert_allclose(y, A @ x.ravel(), rtol=1e-13, atol=1e-13 * np.abs(A).max())
 
 
-@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("k", range(7))
 def test_sweep_is_weighted_jacobi_eq3(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)
@@ -62,7 +65,7 @@ def test_sweep_is_weighted_jacobi_eq3(orc, k):
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14 * scale)
 
 
-@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("k", range(7))
 def test_residual_norm_matches_dense(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)

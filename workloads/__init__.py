@@ -245,6 +245,35 @@ def variable_coefficient(n: int, seed: int, corr_len: float = 8.0, sigma: float 
                    diag=np.ascontiguousarray(diag), name=name or f"varcoef3d_{n}")
 
 
+def variable_coefficient_2d(n0: int, n1: int, seed: int, corr_len: float = 8.0,
+                            sigma: float = 1.0, name: str = "") -> Problem:
+    """-div(k grad u) = 1 on the unit square, n0 x n1 interior nodes, Dirichlet
+    zero: the 2D counterpart of variable_coefficient (k on all nodes,
+    boundary nodes included; harmonic-mean face couplings divided by h_d^2;
+    D_p the sum of its four face couplings)."""
+    rng = np.random.default_rng(seed)
+    k = lognormal_field((1, n1 + 2, n0 + 2), rng, corr_len=corr_len, sigma=sigma)[0]
+    inv0, inv1 = float((n0 + 1) ** 2), float((n1 + 1) ** 2)
+    inner = k[1:-1, 1:-1]
+
+    def hmean(a, b):
+        return 2.0 * a * b / (a + b)
+
+    up0 = hmean(inner, k[1:-1, 2:]) * inv0
+    lo0 = hmean(inner, k[1:-1, :-2]) * inv0
+    up1 = hmean(inner, k[2:, 1:-1]) * inv1
+    lo1 = hmean(inner, k[:-2, 1:-1]) * inv1
+    diag = up0 + lo0
+    diag += up1
+    diag += lo1
+    b = np.ones((1, n1, n0), dtype=np.float64)
+    faces = [np.ascontiguousarray(up0).reshape(1, n1, n0), np.ascontiguousarray(up1).reshape(1, n1, n0),
+             None]
+    return Problem(2, (n0, n1, 1), (0.0, 0.0, 0.0), 0.0, b, faces=faces,
+                   diag=np.ascontiguousarray(diag).reshape(1, n1, n0),
+                   name=name or f"varcoef2d_{n0}x{n1}")
+
+
 def c3(seed: int = 0, n: int = 256) -> Problem:
     return variable_coefficient(n, seed, name=f"c3_varcoef3d_{n}")
 
