@@ -205,10 +205,12 @@ def extra_c3(max_cycles=200):
     return rec
 
 
-def extra_c2_varcoef(n=2048, cycles=40):
+def extra_c2_varcoef(n=2048, cycles=40, tol=1e-6, tol_cycles=100):
     """2D variable-coefficient n x n grid (per-face couplings and diagonal):
     the same capped solve with one sweep per launch and with the default
-    fused per-face block plan (bit-identical iterates)."""
+    fused per-face block plan (bit-identical iterates); then plain binary64
+    and binary32-refined solves to a relative residual of tol with the
+    default plans (at most tol_cycles cycles each)."""
     import numpy as np
     import workloads
     from paper_2011_06636_amd.solver import Solver
@@ -236,6 +238,20 @@ def extra_c2_varcoef(n=2048, cycles=40):
     rec["bit_identical"] = bool(np.array_equal(a[0]["levels"], b[0]["levels"])
                                 and np.array_equal(a[1], b[1]))
     rec["speedup"] = round(rec["one_sweep"]["time_ms"] / rec["default"]["time_ms"], 3)
+    # to the tolerance with the default plans: plain binary64 and binary32-refined
+    assert s.set_plan(*default) == 0
+    rec["to_tol"] = {"tol": tol, "cap_cycles": tol_cycles, "plan_inner": list(s.get_plan(1))}
+    for prec in ("f64", "f32"):
+        x = s.zeros()
+        s.solve(x, tol=tol, precision=prec, max_cycles=2)
+        x.zero_()
+        out, dt = _timed(lambda: s.solve(x, tol=tol, precision=prec, max_cycles=tol_cycles))
+        rec["to_tol"][prec] = {"converged": out["converged"], "cycles": out["cycles"],
+                               "sweeps": out["sweeps"], "time_ms": round(dt * 1e3, 3),
+                               "GLUPS": round(out["sweeps"] * prob.npoints / dt / 1e9, 3),
+                               "final_rel_residual_f64": s.residual_norm(x) / out["r0"]}
+        print(f"# c2 varcoef to {tol:g} {prec}: {dt * 1e3:.1f} ms {out['status']}", file=sys.stderr,
+              flush=True)
     s.close()
     return rec
 

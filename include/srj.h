@@ -226,8 +226,8 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * per block), each wave holding tile_rows rows of 64 columns, fusing up to
  * sweeps_per_launch sweeps per launch with the halo paid once per block;
  * kind 8: the same with two adjacent columns per lane (128-column blocks);
- * kind 10 (binary64 only): the blocks of kind 7 for 2D grids with both
- * per-face coupling arrays and a per-point diagonal, one column per lane.
+ * kind 10: the blocks of kind 7 for 2D grids with both per-face coupling
+ * arrays and a per-point diagonal, one column per lane.
  * Otherwise waves_per_simd is the register budget the kernel was compiled
  * for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan.  Defaults at
  * setup, binary64: 2D constant-coefficient grids of at least 64 x 64 take
@@ -237,8 +237,8 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * waves) when they hold at least 1024 blocks of 48 x 48 written points, else
  * (4 rows, 12 sweeps, 16 waves); 3D takes kind 6 (4 rows, 8-plane chunks)
  * where its coefficient layout fits, else kind 3; anything else kind 0.
- * Inner sweeps: the same with kind 7 in place of kind 8 and kind 0 in place
- * of kind 10. */
+ * Inner sweeps: the same with kind 7 in place of kind 8 and kind 10 always
+ * (8 rows, 8 sweeps, 8 waves). */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);
 srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,

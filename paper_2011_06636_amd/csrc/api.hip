@@ -122,6 +122,12 @@ SweepPlan default_inner_plan(const DevProblem &P)
         pl.T = 8;
         pl.occ = 8;
     }
+    if (P.ndim == 2 && P.face[0] && P.face[1] && P.diag && P.n0 >= 64 && P.n1 >= 64) {
+        pl.kind = 10;  // per-face blocks of 8 waves x 8 rows, 8 sweeps per launch
+        pl.by = 8;
+        pl.T = 8;
+        pl.occ = 8;
+    }
     return pl;
 }
 

@@ -6,6 +6,10 @@
 //   s = D_p x_p - f0[p-1] x[p-1] - f0[p] x[p+1] - f1[p-n0] x[p-n0] - f1[p] x[p+n0]
 //   x'_p = x_p + w (Dinv_p (b_p - s))
 // so results are bit-identical to the one-sweep kernel and the CPU reference.
+// The value policy V (storage.h) gives the arithmetic and storage types: binary64
+// for the plain sweeps, binary32 arithmetic with binary32, binary16 or bfloat16
+// storage (rounded after every sweep) for the inner sweeps of the refinement
+// modes, whose couplings, D and 1/D are binary32 copies.
 //
 // The block layout is that of block2d.h with one column per lane: NW waves
 // hold HW rows each of 64 columns, halo included, with x, b, both face
@@ -16,53 +20,60 @@
 // first row, published in LDS by the wave below; x[p+n0] of a wave's last row
 // is the wave above's first row, also through LDS (one barrier per sweep).
 // Points outside the grid load zero values and zero coefficients, so their
-// terms vanish (f x with x = 0) and they stay zero.
+// terms vanish (f x with x = 0) and they stay zero; the couplings stored for
+// the last column and row (towards points outside the grid, never used) are
+// taken as zero too.
 #pragma once
 
 #include "block2d.h"
 #include "internal.h"
+#include "storage.h"
 #include "tile2d.h"
 
 #pragma clang fp contract(off)
 
 namespace srj {
 
-template <int HW, int NW, bool MASK>
-__device__ __forceinline__ void blockf_sweeps(double (&xr)[HW], const double (&br)[HW],
-                                              const double (&fe)[HW], const double (&fn)[HW],
-                                              const double (&dd)[HW], const double (&di)[HW],
-                                              bool col_in, uint32_t rowbits,
-                                              const double *__restrict__ wlist, int T,
-                                              double *edge, int wave, int lane)
+template <class V, int HW, int NW, bool MASK>
+__device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
+                                              const typename V::A (&br)[HW],
+                                              const typename V::A (&fe)[HW],
+                                              const typename V::A (&fn)[HW],
+                                              const typename V::A (&dd)[HW],
+                                              const typename V::A (&di)[HW], bool col_in,
+                                              uint32_t rowbits,
+                                              const typename V::A *__restrict__ wlist, int T,
+                                              typename V::A *edge, int wave, int lane)
 {
+    using A = typename V::A;
     for (int k = 0; k < T; ++k) {
         // edge: [2 buffers][0: first row's x, 1: last row's f1 x][NW][64]
-        double *e = edge + (k & 1) * (2 * NW * 64);
+        A *e = edge + (k & 1) * (2 * NW * 64);
         e[wave * 64 + lane] = xr[0];
         e[(NW + wave) * 64 + lane] = fn[HW - 1] * xr[HW - 1];
         __syncthreads();
         // rows outside the block read zero (they only feed halo rows)
-        double pdown = wave > 0 ? e[(NW + wave - 1) * 64 + lane] : 0.0;
-        const double xup = wave + 1 < NW ? e[(wave + 1) * 64 + lane] : 0.0;
-        const double w = wlist[k];
+        A pdown = wave > 0 ? e[(NW + wave - 1) * 64 + lane] : A(0);
+        const A xup = wave + 1 < NW ? e[(wave + 1) * 64 + lane] : A(0);
+        const A w = wlist[k];
 #pragma unroll
         for (int r = 0; r < HW; ++r) {
-            const double xc = xr[r];
-            const double pl = dpp_prev(fe[r] * xc);  // f0[p-1] x[p-1]: the left lane's product
-            const double xrt = dpp_next(xc);          // x[p+1]
-            const double xu = r + 1 < HW ? xr[r + 1] : xup;
-            const double pn = fn[r] * xc;  // f1 x of this row, the down term of the row above
-            double s = dd[r] * xc;
+            const A xc = xr[r];
+            const A pl = dpp_prev(fe[r] * xc);  // f0[p-1] x[p-1]: the left lane's product
+            const A xrt = dpp_next(xc);          // x[p+1]
+            const A xu = r + 1 < HW ? xr[r + 1] : xup;
+            const A pn = fn[r] * xc;  // f1 x of this row, the down term of the row above
+            A s = dd[r] * xc;
             s = s - pl;
             s = s - fe[r] * xrt;
             s = s - pdown;
             s = s - fn[r] * xu;
-            const double rr = br[r] - s;
-            const double t = di[r] * rr;
-            const double nx = xc + w * t;
+            const A rr = br[r] - s;
+            const A t = di[r] * rr;
+            const A nx = V::round(xc + w * t);
             pdown = pn;
             if (MASK)
-                xr[r] = (col_in && ((rowbits >> r) & 1)) ? nx : 0.0;
+                xr[r] = (col_in && ((rowbits >> r) & 1)) ? nx : A(0);
             else
                 xr[r] = nx;
         }
@@ -71,20 +82,25 @@ __device__ __forceinline__ void blockf_sweeps(double (&xr)[HW], const double (&b
 
 // One wave's part of one block (see block2d_run for the addressing and the
 // treatment of blocks that cross the grid's edge).
-template <int HW, int HALO, int NW, bool EDGE>
-__device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1, const double *__restrict__ x,
-                                           double *__restrict__ xo, const double *__restrict__ b,
-                                           const double *__restrict__ f0,
-                                           const double *__restrict__ f1,
-                                           const double *__restrict__ dg,
-                                           const double *__restrict__ dgi,
-                                           const double *__restrict__ wlist, int T, int64_t bx0,
-                                           int64_t by0, int wv, int lane, double *edge)
+template <class V, int HW, int HALO, int NW, bool EDGE>
+__device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1,
+                                           const typename V::T *__restrict__ x,
+                                           typename V::T *__restrict__ xo,
+                                           const typename V::T *__restrict__ b,
+                                           const typename V::A *__restrict__ f0,
+                                           const typename V::A *__restrict__ f1,
+                                           const typename V::A *__restrict__ dg,
+                                           const typename V::A *__restrict__ dgi,
+                                           const typename V::A *__restrict__ wlist, int T,
+                                           int64_t bx0, int64_t by0, int wv, int lane,
+                                           typename V::A *edge)
 {
+    using A = typename V::A;
     using S = BlockShape<HW, HALO, NW, 1>;
     const int64_t gy0 = by0 + (int64_t)wv * HW;
     const int64_t gx = bx0 + lane;
     const bool col_in = !EDGE || (gx >= 0 && gx < n0);
+    const bool col_last = EDGE && gx == n0 - 1;
     const uint32_t off = col_in ? (uint32_t)gx : 0u;
     uint32_t rowbits = ~0u;
     if (EDGE) {
@@ -97,41 +113,44 @@ __device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1, const double 
         const int64_t gy = gy0 + r;
         return EDGE ? (gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy)) : gy;
     };
-    double xr[HW], br[HW], fe[HW], fn[HW], dd[HW], di[HW];
+    A xr[HW], br[HW], fe[HW], fn[HW], dd[HW], di[HW];
 #pragma unroll
     for (int r = 0; r < HW; ++r) {
         const int64_t base = row_of(r) * n0 + off;
         const bool in = !EDGE || (((rowbits >> r) & 1) && col_in);
-        const double vx = x[base], vb = b[base], v0 = f0[base], v1 = f1[base], vd = dg[base],
-                     vi = dgi[base];
-        xr[r] = in ? vx : 0.0;
-        br[r] = in ? vb : 0.0;
-        fe[r] = in ? v0 : 0.0;
-        fn[r] = in ? v1 : 0.0;
-        dd[r] = in ? vd : 0.0;
-        di[r] = in ? vi : 0.0;
+        const bool row_last = EDGE && gy0 + r == n1 - 1;
+        const A vx = V::load(x[base]), vb = V::load(b[base]), v0 = f0[base], v1 = f1[base],
+                vd = dg[base], vi = dgi[base];
+        xr[r] = in ? vx : A(0);
+        br[r] = in ? vb : A(0);
+        fe[r] = in && !col_last ? v0 : A(0);
+        fn[r] = in && !row_last ? v1 : A(0);
+        dd[r] = in ? vd : A(0);
+        di[r] = in ? vi : A(0);
     }
-    blockf_sweeps<HW, NW, EDGE>(xr, br, fe, fn, dd, di, col_in, rowbits, wlist, T, edge, wv, lane);
+    blockf_sweeps<V, HW, NW, EDGE>(xr, br, fe, fn, dd, di, col_in, rowbits, wlist, T, edge, wv,
+                                   lane);
     if (!(lane >= HALO && lane < S::BW - HALO) || !col_in) return;
     const int rlo = HALO - wv * HW, rhi = S::BH - HALO - wv * HW;
 #pragma unroll
     for (int r = 0; r < HW; ++r)
-        if (r >= rlo && r < rhi && ((rowbits >> r) & 1)) xo[row_of(r) * n0 + off] = xr[r];
+        if (r >= rlo && r < rhi && ((rowbits >> r) & 1)) xo[row_of(r) * n0 + off] = V::store(xr[r]);
 }
 
-template <int HW, int HALO, int NW>
+template <class V, int HW, int HALO, int NW>
 __global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
-                                                      const double *__restrict__ x,
-                                                      double *__restrict__ xo,
-                                                      const double *__restrict__ b,
-                                                      const double *__restrict__ f0,
-                                                      const double *__restrict__ f1,
-                                                      const double *__restrict__ dg,
-                                                      const double *__restrict__ dgi,
-                                                      const double *__restrict__ wlist, int T,
-                                                      int blocks_x, int nblocks, int reverse)
+                                                      const typename V::T *__restrict__ x,
+                                                      typename V::T *__restrict__ xo,
+                                                      const typename V::T *__restrict__ b,
+                                                      const typename V::A *__restrict__ f0,
+                                                      const typename V::A *__restrict__ f1,
+                                                      const typename V::A *__restrict__ dg,
+                                                      const typename V::A *__restrict__ dgi,
+                                                      const typename V::A *__restrict__ wlist,
+                                                      int T, int blocks_x, int nblocks,
+                                                      int reverse)
 {
-    __shared__ double edge[2 * 2 * NW * 64];
+    __shared__ typename V::A edge[2 * 2 * NW * 64];
     // XCD-aware order, each XCD's range walked backwards on alternate launches
     // (as in block2d.h)
     const int per_xcd = (nblocks + 7) / 8;
@@ -144,18 +163,19 @@ __global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (bx0 >= 0 && bx0 + S::BW <= n0 && by0 >= 0 && by0 + S::BH <= n1)
-        blockf_run<HW, HALO, NW, false>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0, wv,
-                                        lane, edge);
+        blockf_run<V, HW, HALO, NW, false>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0,
+                                           wv, lane, edge);
     else
-        blockf_run<HW, HALO, NW, true>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0, wv,
-                                       lane, edge);
+        blockf_run<V, HW, HALO, NW, true>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0,
+                                          wv, lane, edge);
 }
 
-template <int HW, int HALO, int NW>
-hipError_t launch_blockf2d(int64_t n0, int64_t n1, const double *x, double *xo, const double *b,
-                           const double *f0, const double *f1, const double *dg,
-                           const double *dgi, const double *w_dev, int T, hipStream_t s,
-                           bool reverse)
+template <class V, int HW, int HALO, int NW>
+hipError_t launch_blockf2d(int64_t n0, int64_t n1, const typename V::T *x, typename V::T *xo,
+                           const typename V::T *b, const typename V::A *f0,
+                           const typename V::A *f1, const typename V::A *dg,
+                           const typename V::A *dgi, const typename V::A *w_dev, int T,
+                           hipStream_t s, bool reverse)
 {
     using S = BlockShape<HW, HALO, NW, 1>;
     if (T < 1 || T > HALO) return hipErrorInvalidValue;
@@ -165,13 +185,15 @@ hipError_t launch_blockf2d(int64_t n0, int64_t n1, const double *x, double *xo, 
     const int64_t nblocks = bxn * byn;
     if (nblocks > (int64_t)1 << 28) return hipErrorInvalidValue;
     const int grid = (int)((nblocks + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_blockf2d<HW, HALO, NW>), dim3(grid), dim3(64 * NW), 0, s, n0, n1, x, xo,
-                       b, f0, f1, dg, dgi, w_dev, T, (int)bxn, (int)nblocks, reverse ? 1 : 0);
+    hipLaunchKernelGGL((k_blockf2d<V, HW, HALO, NW>), dim3(grid), dim3(64 * NW), 0, s, n0, n1, x,
+                       xo, b, f0, f1, dg, dgi, w_dev, T, (int)bxn, (int)nblocks, reverse ? 1 : 0);
     return hipGetLastError();
 }
 
 // (rows per wave, halo = most sweeps per launch, waves per block) of the
-// per-face block plans (kind 10)
+// per-face block plans (kind 10): binary64 sweeps, and the inner sweeps of
+// the refinement modes
 #define SRJ_BLOCKF_VARIANTS(X) X(4, 6, 8) X(4, 8, 16) X(4, 12, 16) X(6, 8, 8) X(8, 8, 8)
+#define SRJ_INNER_BLOCKF_VARIANTS(X) X(4, 8, 16) X(8, 8, 8) X(8, 10, 8) X(12, 8, 8)
 
 }  // namespace srj

@@ -29,6 +29,7 @@
 #include "wave2d.h"
 #include "plane3d.h"
 #include "block2d.h"
+#include "block2d_face.h"
 
 #pragma clang fp contract(off)
 
@@ -176,6 +177,15 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
 #undef SRJ_GO2
         return hipErrorInvalidValue;
     }
+    if (plan.kind == 10) {
+#define SRJ_GOF(HW, HL, NW)                                                                    \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL)                                       \
+        return launch_blockf2d<St, HW, HL, NW>(Q.n0, Q.n1, dd, oo, rr, Q.face[0], Q.face[1], Q.diag, \
+                                               Q.dinv, w_dev, T, s, reverse);
+        SRJ_INNER_BLOCKF_VARIANTS(SRJ_GOF)
+#undef SRJ_GOF
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 6) {
         const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
                                 {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
@@ -265,6 +275,13 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 #undef SRJ_CHK
         return false;
     }
+    if (plan.kind == 10) {
+        if (!(P.ndim == 2 && P.face[0] && P.face[1] && P.diag) || plan.T < 1) return false;
+#define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
+        SRJ_INNER_BLOCKF_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 6) {
         if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1)
             return false;
@@ -313,6 +330,9 @@ int inner_plan_variants(int32_t *out, int cap)
 #undef KIND
 #define KIND 8
     SRJ_INNER_BLOCK2_VARIANTS(SRJ_LIST7)
+#undef KIND
+#define KIND 10
+    SRJ_INNER_BLOCKF_VARIANTS(SRJ_LIST7)
 #undef KIND
 #undef SRJ_LIST7
 #define SRJ_LIST6(HH, ZZ)              \

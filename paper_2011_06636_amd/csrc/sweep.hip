@@ -341,8 +341,8 @@ hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const 
     if (plan.kind == 10) {
 #define SRJ_GOF(HW, HL, NW)                                                                   \
     if (plan.by == HW && plan.occ == NW && plan.T <= HL)                                      \
-        return launch_blockf2d<HW, HL, NW>(P.n0, P.n1, x, xo, P.b, P.face[0], P.face[1], P.diag, \
-                                           P.dinv, w_dev, T, s, reverse);
+        return launch_blockf2d<StF64, HW, HL, NW>(P.n0, P.n1, x, xo, P.b, P.face[0], P.face[1], \
+                                                  P.diag, P.dinv, w_dev, T, s, reverse);
         SRJ_BLOCKF_VARIANTS(SRJ_GOF)
 #undef SRJ_GOF
         return hipErrorInvalidValue;

@@ -284,12 +284,12 @@ def test_default_2d_plan_follows_grid_size(torch_cuda):
         s.close()
     # per-face grids: 8 waves x 8 rows and 8 sweeps from 1024 blocks of
     # 48 x 48 written points, else 16 waves x 4 rows and 12 sweeps; the inner
-    # sweeps of the refinement modes one per launch
+    # sweeps of the refinement modes 8 waves x 8 rows and 8 sweeps
     for n0, n1, want in ((48 * 32, 48 * 32, (10, 8, 8, 8)), (48 * 32, 48 * 31, (10, 4, 12, 16)),
                          (64, 64, (10, 4, 12, 16)), (63, 200, (0, 0, 1, 1))):
         s = Solver(workloads.variable_coefficient_2d(n0, n1, seed=0))
         assert tuple(s.get_plan(0)) == want, (n0, n1, s.get_plan(0))
-        assert s.get_plan(1)[0] == 0
+        assert tuple(s.get_plan(1)) == ((10, 8, 8, 8) if want[0] else (0, 0, 1, 1))
         s.close()
 
 

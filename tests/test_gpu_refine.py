@@ -106,6 +106,36 @@ def test_inner_plans_bit_identical(torch_cuda, orc, precision):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(301, 137), (70, 90)])
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+def test_inner_face_plans_bit_identical(torch_cuda, orc, precision, shape):
+    # the per-face block kernels (kind 10) in the inner sweeps: every variant
+    # gives the bits of one sweep per launch on a 2D variable-coefficient grid
+    # with ragged blocks, and the oracle agrees
+    from paper_2011_06636_amd import abi
+    prob = workloads.variable_coefficient_2d(*shape, seed=shape[0], corr_len=5.0)
+    s = _solver(prob)
+    kw = dict(tol=1e-300, precision=precision, max_cycles=10)
+    plans = [(0, 0, 1, 1)]
+    for kind, rows, halo, occ in abi.srj_plan_variants(which=1):
+        if kind == 10:
+            plans += [(kind, rows, t, occ) for t in sorted({1, halo // 2 + 1, halo})]
+    assert len(plans) > 1
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan, which=1) == 0, plan
+        out = s.solve(**kw)
+        results[plan] = (out["levels"].copy(), out["x"].cpu().numpy())
+    base_lv, base_x = results[(0, 0, 1, 1)]
+    for plan, (lv, xv) in results.items():
+        assert np.array_equal(lv, base_lv), plan
+        assert np.array_equal(xv, base_x), plan
+    ref = orc.solve(prob, **kw)
+    np.testing.assert_array_equal(ref["levels"], base_lv)
+    assert np.max(np.abs(base_x - ref["x"])) <= 1e-12 * np.max(np.abs(ref["x"]))
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
 def test_inner_3d_plans_bit_identical(torch_cuda, orc, precision):
     from paper_2011_06636_amd import abi
