@@ -98,8 +98,9 @@ typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1, SRJ_TOL_UPDATE_INF = 
 
 typedef struct {
     int32_t ndim;          /* 1, 2 or 3 */
-    int64_t n[3];          /* interior sizes, >= 1; n[d] == 1 for d >= ndim */
-    double cconst[3];      /* coupling on axis d when face[d] == NULL */
+    int64_t n[3];          /* interior sizes, >= 1; n[d] == 1 for d >= ndim; n[1], n[2]
+                              <= 65535 (srj_setup); n[0] n[1] n[2] <= 2^38 */
+    double cconst[3];      /* coupling on axis d when face[d] == NULL, finite, >= 0 */
     const double *face[3]; /* optional device array: coupling between p and p + e_d */
     double dconst;         /* diagonal when diag == NULL; must be > 0 */
     const double *diag;    /* optional device array: diagonal D (> 0) */

@@ -68,11 +68,12 @@ srj_status validate_problem(const srj_problem *p)
     for (int d = 0; d < 3; ++d) {
         if (p->n[d] < 1) return fail(SRJ_ERR_INVALID, "every n[d] must be >= 1");
         if (d >= p->ndim && p->n[d] != 1) return fail(SRJ_ERR_INVALID, "n[d] must be 1 for d >= ndim");
-        if (d < p->ndim && !p->face[d] && !(p->cconst[d] >= 0.0) )
+        if (d < p->ndim && !p->face[d] && !(p->cconst[d] >= 0.0 && isfinite(p->cconst[d])))
             return fail(SRJ_ERR_INVALID, "cconst[d] must be finite and >= 0");
     }
     if (p->n[1] > 65535 || p->n[2] > 65535)
         return fail(SRJ_ERR_INVALID, "n[1] and n[2] must be <= 65535");
+    if (!points_fit(p->n)) return fail(SRJ_ERR_INVALID, "n[0] n[1] n[2] must be <= 2^38");
     if (!p->b) return fail(SRJ_ERR_INVALID, "b is NULL");
     if (!p->diag && !(p->dconst > 0.0) ) return fail(SRJ_ERR_INVALID, "dconst must be > 0");
     if (!p->diag && !isfinite(p->dconst)) return fail(SRJ_ERR_INVALID, "dconst must be finite");

@@ -848,6 +848,7 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
     if (!out) return fail(SRJ_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (count < 1 || !probs) return fail(SRJ_ERR_INVALID, "count must be >= 1 and probs non-NULL");
+    int64_t total = 0;
     for (int i = 0; i < count; ++i) {
         const srj_problem &p = probs[i];
         if (p.ndim < 1 || p.ndim > 3) return fail(SRJ_ERR_INVALID, "ndim must be 1, 2 or 3");
@@ -856,9 +857,12 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
             if (d >= p.ndim && p.n[d] != 1) return fail(SRJ_ERR_INVALID, "n[d] must be 1 for d >= ndim");
             if (d < p.ndim && p.face[d])
                 return fail(SRJ_ERR_UNSUPPORTED, "batched solves take constant couplings only");
-            if (d < p.ndim && !(p.cconst[d] >= 0.0) )
+            if (d < p.ndim && !(p.cconst[d] >= 0.0 && isfinite(p.cconst[d])))
                 return fail(SRJ_ERR_INVALID, "cconst[d] must be finite and >= 0");
         }
+        if (!points_fit(p.n)) return fail(SRJ_ERR_INVALID, "n[0] n[1] n[2] must be <= 2^38");
+        total += p.n[0] * p.n[1] * p.n[2];
+        if (total > kMaxPoints) return fail(SRJ_ERR_INVALID, "the instances hold more than 2^38 points");
         if (p.diag) return fail(SRJ_ERR_UNSUPPORTED, "batched solves take a constant diagonal only");
         if (!(p.dconst > 0.0) || !isfinite(p.dconst)) return fail(SRJ_ERR_INVALID, "dconst must be > 0");
         if (!p.b) return fail(SRJ_ERR_INVALID, "b is NULL");

@@ -25,6 +25,16 @@ srj_status fail(srj_status st, const std::string &msg);
 // message naming `what`.
 srj_status check_device_array(const void *p, size_t bytes, int dev, const char *what);
 
+// Largest number of points of one grid (and of all instances of a batch):
+// 2^38 binary64 values are 2 TiB, far beyond one device, so every byte count
+// and launch dimension derived from it fits its type.
+constexpr int64_t kMaxPoints = int64_t(1) << 38;
+// n[0] n[1] n[2] <= kMaxPoints without overflow (each n[d] >= 1).
+inline bool points_fit(const int64_t n[3])
+{
+    return n[1] <= kMaxPoints && n[2] <= kMaxPoints / n[1] && n[0] <= kMaxPoints / (n[1] * n[2]);
+}
+
 #define SRJ_HIP_CHECK(expr)                                                              \
     do {                                                                                 \
         hipError_t _e = (expr);                                                          \

@@ -65,7 +65,7 @@ def _prob(**kw):
     n = kw.get("n", (8, 1, 1))
     for d in range(3):
         p.n[d] = n[d]
-        p.cconst[d] = 1.0
+        p.cconst[d] = kw.get("c", 1.0) if d == 0 else 1.0
         p.face[d] = None
     p.dconst = kw.get("dconst", 2.0)
     p.diag = None
@@ -76,6 +76,9 @@ def _prob(**kw):
 @pytest.mark.parametrize("kw", [
     dict(ndim=0), dict(ndim=4), dict(n=(0, 1, 1)), dict(ndim=1, n=(8, 2, 1)),
     dict(dconst=0.0), dict(dconst=-1.0), dict(dconst=float("nan")), dict(b=None),
+    dict(c=float("inf")), dict(c=float("nan")), dict(c=-1.0),
+    dict(ndim=2, n=(8, 65536, 1)), dict(n=(2 ** 38 + 1, 1, 1)), dict(n=(2 ** 62, 1, 1)),
+    dict(ndim=3, n=(2 ** 7, 65535, 65535)),
 ])
 def test_setup_rejects_invalid_problem(kw):
     lib = abi.load()
@@ -84,6 +87,28 @@ def test_setup_rejects_invalid_problem(kw):
     assert st == abi.SRJ_ERR_INVALID
     assert not h.value
     assert abi.last_error()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(ndim=0), dict(n=(0, 1, 1)), dict(dconst=0.0), dict(b=None), dict(c=float("inf")),
+    dict(n=(2 ** 38 + 1, 1, 1)), dict(n=(2 ** 62, 1, 1)), dict(ndim=3, n=(2 ** 40, 2 ** 40, 2 ** 40)),
+])
+def test_batch_setup_rejects_invalid_problem(kw):
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    probs = (abi.SrjProblem * 2)(_prob(), _prob(**kw))
+    st = lib.srj_batch_setup(2, probs, None, ctypes.byref(h))
+    assert st == abi.SRJ_ERR_INVALID
+    assert not h.value
+    assert abi.last_error()
+
+
+def test_batch_setup_rejects_too_many_points_in_total():
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    probs = (abi.SrjProblem * 3)(*[_prob(n=(2 ** 37, 1, 1)) for _ in range(3)])
+    assert lib.srj_batch_setup(3, probs, None, ctypes.byref(h)) == abi.SRJ_ERR_INVALID
+    assert "2^38" in abi.last_error()
 
 
 def test_null_context_calls_are_invalid():
