@@ -228,7 +228,10 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * sweeps_per_launch sweeps per launch with the halo paid once per block;
  * kind 8: the same with two adjacent columns per lane (128-column blocks);
  * kind 10: the blocks of kind 7 for 2D grids with both per-face coupling
- * arrays and a per-point diagonal, one column per lane.
+ * arrays and a per-point diagonal, one column per lane; kind 11: 3D with
+ * constant couplings and diagonal, two sweeps per launch (sweeps_per_launch
+ * 1 or 2) in plane tiles of 60 written columns x tile_rows rows streamed
+ * over waves_per_simd planes (that field is the chunk length, as for kind 6).
  * Otherwise waves_per_simd is the register budget the kernel was compiled
  * for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan.  Defaults at
  * setup, binary64: 2D constant-coefficient grids of at least 64 x 64 take
@@ -236,10 +239,11 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * 108 x 44 written points, else kind 7 (8 rows, 8 sweeps, 8 waves); 2D
  * per-face grids of at least 64 x 64 take kind 10, (8 rows, 8 sweeps, 8
  * waves) when they hold at least 1024 blocks of 48 x 48 written points, else
- * (4 rows, 12 sweeps, 16 waves); 3D takes kind 6 (4 rows, 8-plane chunks)
- * where its coefficient layout fits, else kind 3; anything else kind 0.
- * Inner sweeps: the same with kind 7 in place of kind 8 and kind 10 always
- * (8 rows, 8 sweeps, 8 waves). */
+ * (4 rows, 12 sweeps, 16 waves); 3D with constant coefficients takes kind
+ * 11 (4 rows, 2 sweeps, 8-plane chunks), 3D with all faces and a diagonal
+ * array kind 6 (4 rows, 8-plane chunks), other 3D layouts kind 3; anything
+ * else kind 0.  Inner sweeps: the same with kind 7 in place of kind 8, kind
+ * 10 always (8 rows, 8 sweeps, 8 waves) and kind 11 with 8 rows. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);
 srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,

@@ -107,7 +107,12 @@ SweepPlan default_inner_plan(const DevProblem &P)
 {
     SweepPlan pl;
     if (P.ndim == 3) {
-        if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
+        if (!P.face[0] && !P.face[1] && !P.face[2] && !P.diag) {
+            pl.kind = 11;  // two-sweep plane tiles: 8 rows, 8 planes per chunk
+            pl.by = 8;
+            pl.T = 2;
+            pl.occ = 8;
+        } else if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
             pl.kind = 6;  // plane tiles: 4 rows, 8 planes per chunk
             pl.by = 4;
             pl.occ = 8;
@@ -138,7 +143,12 @@ SweepPlan default_plan(const DevProblem &P)
     pl.kind = 0;
     pl.T = 1;
     if (P.ndim == 3) {
-        if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
+        if (!P.face[0] && !P.face[1] && !P.face[2] && !P.diag) {
+            pl.kind = 11;  // two-sweep plane tiles: 4 rows, 8 planes per chunk
+            pl.by = 4;
+            pl.T = 2;
+            pl.occ = 8;
+        } else if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
             pl.kind = 6;
             pl.by = 4;
             pl.occ = 8;

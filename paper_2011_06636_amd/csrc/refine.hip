@@ -28,6 +28,7 @@
 #include "stream3d.h"
 #include "wave2d.h"
 #include "plane3d.h"
+#include "plane3d_fused.h"
 #include "block2d.h"
 #include "block2d_face.h"
 
@@ -186,6 +187,19 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
 #undef SRJ_GOF
         return hipErrorInvalidValue;
     }
+    if (plan.kind == 11) {
+        const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
+                                {nullptr, nullptr, nullptr}, Q.dconst, Q.dinvconst, nullptr,
+                                nullptr};
+        // the last launch of an odd-length cycle does one sweep
+        if (T == 1) return launch_plane3d<St, 4, 8>(S, dd, oo, rr, w_dev, s);
+        if (T != 2) return hipErrorInvalidValue;
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d2<St, HH, ZZ>(S, dd, oo, rr, w_dev, s);
+        SRJ_INNER_PLANE2_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 6) {
         const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
                                 {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
@@ -282,6 +296,15 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 #undef SRJ_CHK
         return false;
     }
+    if (plan.kind == 11) {
+        if (!(P.ndim == 3 && !P.face[0] && !P.face[1] && !P.face[2] && !P.diag) || plan.T < 1 ||
+            plan.T > 2)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_INNER_PLANE2_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 6) {
         if (!plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag) || plan.T != 1)
             return false;
@@ -345,6 +368,16 @@ int inner_plan_variants(int32_t *out, int cap)
     ++n;
     SRJ_PLANE_VARIANTS(SRJ_LIST6)
 #undef SRJ_LIST6
+#define SRJ_LIST11(HH, ZZ)             \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 11;           \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 2;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_INNER_PLANE2_VARIANTS(SRJ_LIST11)
+#undef SRJ_LIST11
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \

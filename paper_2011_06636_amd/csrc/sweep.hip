@@ -13,6 +13,7 @@
 #include "stream3d.h"
 #include "wave2d.h"
 #include "plane3d.h"
+#include "plane3d_fused.h"
 #include "block2d.h"
 #include "block2d_face.h"
 
@@ -237,6 +238,16 @@ int plan_variants(int32_t *out, int cap)
     ++n;
     SRJ_PLANE_VARIANTS(SRJ_LIST6)
 #undef SRJ_LIST6
+#define SRJ_LIST11(HH, ZZ)             \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 11;           \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 2;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_PLANE2_VARIANTS(SRJ_LIST11)
+#undef SRJ_LIST11
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \
@@ -284,6 +295,15 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
         if (!(P.ndim == 2 && P.face[0] && P.face[1] && P.diag && P.dinv) || plan.T < 1) return false;
 #define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
         SRJ_BLOCKF_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
+    if (plan.kind == 11) {
+        if (!(P.ndim == 3 && !P.face[0] && !P.face[1] && !P.face[2] && !P.diag) || plan.T < 1 ||
+            plan.T > 2)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_PLANE2_VARIANTS(SRJ_CHK)
 #undef SRJ_CHK
         return false;
     }
@@ -345,6 +365,19 @@ hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const 
                                                   P.diag, P.dinv, w_dev, T, s, reverse);
         SRJ_BLOCKF_VARIANTS(SRJ_GOF)
 #undef SRJ_GOF
+        return hipErrorInvalidValue;
+    }
+    if (plan.kind == 11) {
+        const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
+                                 {nullptr, nullptr, nullptr}, P.dconst, P.dinvconst, nullptr,
+                                 nullptr};
+        // the last launch of an odd-length cycle does one sweep
+        if (T == 1) return launch_plane3d<StF64, 4, 8>(S, x, xo, P.b, w_dev, s);
+        if (T != 2) return hipErrorInvalidValue;
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d2<StF64, HH, ZZ>(S, x, xo, P.b, w_dev, s);
+        SRJ_PLANE2_VARIANTS(SRJ_GO)
+#undef SRJ_GO
         return hipErrorInvalidValue;
     }
     if (plan.kind == 6) {

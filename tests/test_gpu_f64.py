@@ -230,6 +230,47 @@ def test_3d_plans_bit_identical(torch_cuda, orc, case):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["poisson_70x9x37", "poisson_61x64x33", "aniso", "small_3x2x5"])
+def test_3d_two_sweep_plans_bit_identical(torch_cuda, orc, case):
+    # the two-sweep plane kernels (plan kind 11, every tile shape, odd and even
+    # cycle lengths) give the bits of the one-sweep kernel on ragged boxes with
+    # constant couplings, and the oracle agrees; per-face boxes refuse them
+    from paper_2011_06636_amd import abi
+    rng = np.random.default_rng(9)
+    if case == "aniso":
+        prob = workloads.c5_instance(3, lo=20, hi=45)
+    else:
+        n = [int(v) for v in case.split("_")[1].split("x")]
+        prob = workloads.poisson(n, b=rng.uniform(-1, 1, n[::-1]))
+    s = _solver(prob)
+    x0 = rng.uniform(-1, 1, prob.shape)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] == 11]
+    assert len(plans) > 1
+    results = {}
+    levels = (0, 1, 2, 5, 9)
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in levels:
+            s.run_cycle(x, level)
+        results[plan] = x.cpu().numpy()
+    base = results[(0, 0, 1, 1)]
+    for plan, v in results.items():
+        assert np.array_equal(v, base), plan
+    x_ref = x0.copy()
+    for level in levels:
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    assert _close(base, x_ref)
+    s.close()
+    s = _solver(workloads.variable_coefficient(12, seed=1))
+    for v in abi.srj_plan_variants():
+        if v[0] == 11:
+            assert s.set_plan(*v) != 0
+            assert s.set_plan(v[0], v[1], 3, v[3]) != 0
+    s.close()
+
+
 def test_resume_is_bit_identical(torch_cuda, orc):
     prob = workloads.c2(n=160)
     s = _solver(prob)
@@ -291,6 +332,18 @@ def test_default_2d_plan_follows_grid_size(torch_cuda):
         assert tuple(s.get_plan(0)) == want, (n0, n1, s.get_plan(0))
         assert tuple(s.get_plan(1)) == ((10, 8, 8, 8) if want[0] else (0, 0, 1, 1))
         s.close()
+
+
+def test_default_3d_plans(torch_cuda):
+    # constant coefficients: two sweeps per launch (kind 11), 4 rows binary64,
+    # 8 rows inner; per-face boxes: one-sweep plane tiles (kind 6)
+    from paper_2011_06636_amd.solver import Solver
+    s = Solver(workloads.poisson([40, 30, 20]))
+    assert tuple(s.get_plan(0)) == (11, 4, 2, 8) and tuple(s.get_plan(1)) == (11, 8, 2, 8)
+    s.close()
+    s = Solver(workloads.variable_coefficient(16, seed=0))
+    assert tuple(s.get_plan(0)) == (6, 4, 1, 8) and tuple(s.get_plan(1)) == (6, 4, 1, 8)
+    s.close()
 
 
 def test_c2_full_size_first_cycles(torch_cuda, orc):
