@@ -286,7 +286,7 @@ def extra_batch(which):
         if which == "c4":
             rec |= {"plan": list(bs.get_plan()), "autotune_us_per_sweep": round(tune_us, 3)}
         else:
-            rec |= {"plane_tile": list(bs.get_plan3d()), "autotune_us_per_step": round(tune_us, 3)}
+            rec |= {"plane_plan_rows_planes_sweeps": list(bs.get_plan3d()), "autotune_us_per_step": round(tune_us, 3)}
         batched.append(rec)
         xs_by_prec[prec] = [x.clone() for x in out["xs"]]
         if best is None or dt_b < best[0]:

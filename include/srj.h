@@ -391,12 +391,17 @@ srj_status srj_fit_rule(const srj_cluster *clusters, int32_t count, double *t_lo
                         int32_t *agree, int32_t *decided);
 
 /* 3D plane tile of a batch: 3D instances are swept by waves that each own
- * 62 written columns x tile_rows rows and walk `planes` planes along axis 2
- * (tile_rows, planes) in {(2, 16), (4, 8), (4, 16), (8, 8), (8, 16)}; default
- * (4, 8).  SRJ_ERR_UNSUPPORTED for any other shape.  Iterates do not depend
- * on the tile. */
-srj_status srj_batch_set_plan3d(srj_batch *batch, int32_t tile_rows, int32_t planes);
-srj_status srj_batch_get_plan3d(srj_batch *batch, int32_t *tile_rows, int32_t *planes);
+ * tile_rows rows of 62 written columns (sweeps = 1) or 60 (sweeps = 2) and
+ * walk `planes` planes along axis 2; with sweeps = 2 each step applies the
+ * next two sweeps of an instance's cycle in one pass (one when a single
+ * sweep is left).  (tile_rows, planes) in {(2, 16), (4, 8), (4, 16), (8, 8),
+ * (8, 16)}; default (4, 8) with 2 sweeps.  SRJ_ERR_UNSUPPORTED for any other
+ * shape, SRJ_ERR_INVALID for sweeps other than 1 or 2.  Iterates do not
+ * depend on the plan. */
+srj_status srj_batch_set_plan3d(srj_batch *batch, int32_t tile_rows, int32_t planes,
+                                int32_t sweeps);
+srj_status srj_batch_get_plan3d(srj_batch *batch, int32_t *tile_rows, int32_t *planes,
+                                int32_t *sweeps);
 
 /* Batch autotuner: for `precision`, times every tile or block plan of the
  * batch's 2D/1D instances (when it has any; `sweeps` sweeps of them) and then

@@ -127,8 +127,8 @@ def load() -> ctypes.CDLL:
         "srj_batch_setup": (i32, [i32, P(SrjProblem), vp, P(vp)]),
         "srj_batch_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
         "srj_batch_get_plan": (i32, [vp, P(i32), P(i32), P(i32), P(i32), P(i32)]),
-        "srj_batch_set_plan3d": (i32, [vp, i32, i32]),
-        "srj_batch_get_plan3d": (i32, [vp, P(i32), P(i32)]),
+        "srj_batch_set_plan3d": (i32, [vp, i32, i32, i32]),
+        "srj_batch_get_plan3d": (i32, [vp, P(i32), P(i32), P(i32)]),
         "srj_batch_autotune": (i32, [vp, i32, i32, P(f64)]),
         "srj_batch_solve": (i32, [vp, P(vp), P(SrjSolveOpts), P(SrjSolveResult), P(i32)]),
         "srj_batch_destroy": (i32, [vp]),
@@ -280,12 +280,12 @@ def srj_batch_get_plan(batch):
     return tuple(a.value for a in v)
 
 
-def srj_batch_set_plan3d(batch, tile_rows: int, planes: int) -> None:
-    check(load().srj_batch_set_plan3d(batch, tile_rows, planes), "srj_batch_set_plan3d")
+def srj_batch_set_plan3d(batch, tile_rows: int, planes: int, sweeps: int = 2) -> None:
+    check(load().srj_batch_set_plan3d(batch, tile_rows, planes, sweeps), "srj_batch_set_plan3d")
 
 
 def srj_batch_get_plan3d(batch):
-    v = [ctypes.c_int32() for _ in range(2)]
+    v = [ctypes.c_int32() for _ in range(3)]
     check(load().srj_batch_get_plan3d(batch, *[ctypes.byref(a) for a in v]), "srj_batch_get_plan3d")
     return tuple(a.value for a in v)
 

@@ -31,6 +31,7 @@
 #include "stream3d.h"
 #include "tile2d.h"
 #include "plane3d.h"
+#include "plane3d_fused.h"
 #include "block2d.h"
 
 #pragma clang fp contract(off)
@@ -63,7 +64,7 @@ struct BState {
 struct BParams {
     int32_t rule, fixed_level, max_level, max_cycles;
     int64_t max_sweeps;
-    int32_t tol_mode, T2;
+    int32_t tol_mode, T2, T3, pad3_;
     double tol, tgt_rms, r0_given;
     const int32_t *levelM;
     const int32_t *offsets;
@@ -97,9 +98,9 @@ struct Sel<float> {
 __device__ __forceinline__ int sweeps_this_step(const BDesc &d, const BState &s, const BParams &p)
 {
     const int M = p.levelM[s.level];
-    if (d.ndim == 3) return 1;
     const int left = M - s.pos;
-    return left < p.T2 ? left : p.T2;
+    const int T = d.ndim == 3 ? p.T3 : p.T2;
+    return left < T ? left : T;
 }
 
 __device__ __forceinline__ double pow2_scale_dev(double norm, double sqrtN, double tgt)
@@ -171,8 +172,10 @@ __global__ __launch_bounds__(64 * NW) void k_bsweep2d_blk(const BDesc *__restric
 }
 
 // 1'. sweeps, 3D instances: one wave per (instance, plane tile) item; a
-// tile is 62 written columns x PH rows x ZC planes
-template <class V, int PH, int ZC>
+// tile is 62 written columns x PH rows x ZC planes, or with TWO (two sweeps
+// per step) 60 written columns, and an instance with two sweeps left in its
+// cycle takes both in one pass
+template <class V, int PH, int ZC, bool TWO>
 __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc,
                                                   const BState *__restrict__ st,
                                                   const int2 *__restrict__ items, int nitems,
@@ -187,11 +190,16 @@ __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc
         if (s.done) continue;
         const BDesc &d = desc[it.x];
         const int tx = it.y % d.gx3, ty = (it.y / d.gx3) % d.gy3, tz = it.y / (d.gx3 * d.gy3);
-        const A w = Sel<A>::omega(prm)[prm.offsets[s.level] + s.pos];
+        const A *w = Sel<A>::omega(prm) + prm.offsets[s.level] + s.pos;
         const typename V::T *uin = (s.pu ? ub : ua) + d.off;
         typename V::T *uout = (s.pu ? ua : ub) + d.off;
-        plane3d_run<V, PH, ZC, false, false>(Sel<A>::sten(d), uin, uout, rhs + d.off, w, tx, ty,
-                                             tz, threadIdx.x & 63);
+        if (TWO && sweeps_this_step(d, s, prm) == 2)
+            plane3d2_run<V, PH, ZC>(Sel<A>::sten(d), uin, uout, rhs + d.off, w[0], w[1], tx, ty, tz,
+                                    threadIdx.x & 63);
+        else
+            plane3d_run<V, PH, ZC, false, false, TWO ? 60 : 62>(Sel<A>::sten(d), uin, uout,
+                                                                rhs + d.off, w[0], tx, ty, tz,
+                                                                threadIdx.x & 63);
     }
 }
 
@@ -467,6 +475,7 @@ struct srj_batch {
     int tile_rows = 24, halo = 4, T2 = 4, waves = 1, steps_per_graph = 16;
     bool use_graph = true;
     int ph3 = 4, zc3 = 8;  // 3D plane tile: rows, planes per work item
+    int t3 = 2;            // most sweeps per step of a 3D instance (1 or 2)
     int device = 0;        // current device at setup; caller arrays must live there
 };
 
@@ -569,10 +578,16 @@ srj_status enqueue_step(srj_batch *B, const BParams &prm)
         bool launched = false;
 #define SRJ_GO3(PH, ZC)                                                                           \
         if (!launched && B->ph3 == PH && B->zc3 == ZC) {                                          \
-            hipLaunchKernelGGL((k_bsweep3d<V, PH, ZC>), dim3(grid), dim3(256), 0, B->stream,     \
-                               B->desc, B->state, B->items3, (int)B->hitems3.size(),            \
-                               (typename V::T *)ua, (typename V::T *)ub,                         \
-                               (const typename V::T *)rhs, prm);                                 \
+            if (B->t3 == 2)                                                                        \
+                hipLaunchKernelGGL((k_bsweep3d<V, PH, ZC, true>), dim3(grid), dim3(256), 0,       \
+                                   B->stream, B->desc, B->state, B->items3,                        \
+                                   (int)B->hitems3.size(), (typename V::T *)ua,                    \
+                                   (typename V::T *)ub, (const typename V::T *)rhs, prm);          \
+            else                                                                                   \
+                hipLaunchKernelGGL((k_bsweep3d<V, PH, ZC, false>), dim3(grid), dim3(256), 0,      \
+                                   B->stream, B->desc, B->state, B->items3,                        \
+                                   (int)B->hitems3.size(), (typename V::T *)ua,                    \
+                                   (typename V::T *)ub, (const typename V::T *)rhs, prm);          \
             launched = true;                                                                       \
         }
         SRJ_BATCH_PLANE(SRJ_GO3)
@@ -601,6 +616,7 @@ BParams make_params(const srj_batch *B, const srj_solve_opts *o)
     prm.max_sweeps = o->max_sweeps;
     prm.tol_mode = o->tol_mode;
     prm.T2 = B->T2;
+    prm.T3 = B->t3;
     prm.tol = o->tol;
     prm.tgt_rms = o->scale_target > 0.0 ? o->scale_target
                   : (o->precision == SRJ_PREC_F16_REFINE ? ldexp(1.0, -8) : 1.0);
@@ -999,7 +1015,8 @@ srj_status srj_batch_set_plan(srj_batch *B, int32_t tile_rows, int32_t sweeps_pe
     for (int i = 0; i < B->count; ++i) {
         BDesc &d = B->hdesc[i];
         if (d.ndim == 3) {
-            d.gx3 = (int)((d.n0 + 61) / 62);
+            const int W = B->t3 == 2 ? 60 : 62;  // written columns per plane tile
+            d.gx3 = (int)((d.n0 + W - 1) / W);
             d.gy3 = (int)((d.n1 + B->ph3 - 1) / B->ph3);
             const int gz = (int)((d.n2 + B->zc3 - 1) / B->zc3);
             for (int k = 0; k < d.gx3 * d.gy3 * gz; ++k) B->hitems3.push_back({i, k});
@@ -1077,9 +1094,10 @@ srj_status srj_batch_get_plan(srj_batch *B, int32_t *tile_rows, int32_t *sweeps_
     return SRJ_OK;
 }
 
-srj_status srj_batch_set_plan3d(srj_batch *B, int32_t tile_rows, int32_t planes)
+srj_status srj_batch_set_plan3d(srj_batch *B, int32_t tile_rows, int32_t planes, int32_t sweeps)
 {
     if (!B) return fail(SRJ_ERR_INVALID, "batch is NULL");
+    if (sweeps != 1 && sweeps != 2) return fail(SRJ_ERR_INVALID, "sweeps must be 1 or 2");
     bool ok = false;
 #define SRJ_OK3(PH, ZC) ok = ok || (tile_rows == PH && planes == ZC);
     SRJ_BATCH_PLANE(SRJ_OK3)
@@ -1087,16 +1105,19 @@ srj_status srj_batch_set_plan3d(srj_batch *B, int32_t tile_rows, int32_t planes)
     if (!ok) return fail(SRJ_ERR_UNSUPPORTED, "3D plane tile not available");
     B->ph3 = tile_rows;
     B->zc3 = planes;
+    B->t3 = sweeps;
     // rebuild the work items with the current 2D plan
     return srj_batch_set_plan(B, B->tile_rows, B->T2, B->waves, B->steps_per_graph,
                               B->use_graph ? 1 : 0);
 }
 
-srj_status srj_batch_get_plan3d(srj_batch *B, int32_t *tile_rows, int32_t *planes)
+srj_status srj_batch_get_plan3d(srj_batch *B, int32_t *tile_rows, int32_t *planes,
+                                int32_t *sweeps)
 {
-    if (!B || !tile_rows || !planes) return fail(SRJ_ERR_INVALID, "NULL argument");
+    if (!B || !tile_rows || !planes || !sweeps) return fail(SRJ_ERR_INVALID, "NULL argument");
     *tile_rows = B->ph3;
     *planes = B->zc3;
+    *sweeps = B->t3;
     return SRJ_OK;
 }
 
@@ -1143,7 +1164,8 @@ srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
         for (const Cand &cd : cands) {
             srj_status st = srj_batch_set_plan(B, cd.rows, cd.T, cd.waves, steps_per_graph, use_graph);
             if (st != SRJ_OK) return st;
-            // every step moves 2D instances by T sweeps and 3D instances by one
+            // every step moves 2D instances by up to T sweeps (3D instances by
+            // their own plan's count)
             const int steps = std::max(1, (sweeps + cd.T - 1) / cd.T);
             float ms = 0.f;
             st = time_steps(steps, &ms);
@@ -1160,31 +1182,33 @@ srj_status srj_batch_autotune(srj_batch *B, int32_t precision, int32_t sweeps,
                                            use_graph ? 1 : 0);
         if (st != SRJ_OK) return st;
     }
-    // 3D instances: plane tile, timed per step (one sweep of every 3D instance)
+    // 3D instances: plane tile and sweeps per step, timed per sweep
     if (!B->hitems3.empty()) {
-        int best_ph = B->ph3, best_zc = B->zc3;
+        int best_ph = B->ph3, best_zc = B->zc3, best_t3 = B->t3;
         double best3 = INFINITY;
         struct Tile {
-            int ph, zc;
+            int ph, zc, t3;
         };
         std::vector<Tile> tiles;
-#define SRJ_C3(PH, ZC) tiles.push_back({PH, ZC});
+#define SRJ_C3(PH, ZC) tiles.push_back({PH, ZC, 1}); tiles.push_back({PH, ZC, 2});
         SRJ_BATCH_PLANE(SRJ_C3)
 #undef SRJ_C3
         for (const Tile &t : tiles) {
-            srj_status st = srj_batch_set_plan3d(B, t.ph, t.zc);
+            srj_status st = srj_batch_set_plan3d(B, t.ph, t.zc, t.t3);
             if (st != SRJ_OK) return st;
+            const int steps = std::max(1, (sweeps + t.t3 - 1) / t.t3);
             float ms = 0.f;
-            st = time_steps(sweeps, &ms);
+            st = time_steps(steps, &ms);
             if (st != SRJ_OK) return st;
-            const double us = 1e3 * ms / sweeps;
+            const double us = 1e3 * ms / (steps * t.t3);
             if (us < best3) {
                 best3 = us;
                 best_ph = t.ph;
                 best_zc = t.zc;
+                best_t3 = t.t3;
             }
         }
-        srj_status st = srj_batch_set_plan3d(B, best_ph, best_zc);
+        srj_status st = srj_batch_set_plan3d(B, best_ph, best_zc, best_t3);
         if (st != SRJ_OK) return st;
         best = best3;
     }

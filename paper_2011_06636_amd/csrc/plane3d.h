@@ -27,7 +27,9 @@
 
 namespace srj {
 
-template <class V, int H, int ZC, bool FACE, bool DIAG>
+// W: written columns per tile, 62 (one halo lane on each side) or 60 (two,
+// the tiling of the two-sweep kernel, which batches mixing both use)
+template <class V, int H, int ZC, bool FACE, bool DIAG, int W = 62>
 __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
                                             const typename V::T *__restrict__ x,
                                             typename V::T *__restrict__ xo,
@@ -38,7 +40,9 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
     constexpr bool kRecipInPlace = sizeof(A) == sizeof(double);
     const int64_t n0 = S.n0, n1 = S.n1, n2 = S.n2;
     const int64_t s1 = n0, s2 = n0 * n1;
-    const int64_t gx = (int64_t)tx * 62 - 1 + lane;
+    static_assert(W == 62 || W == 60, "tile width");
+    constexpr int kLo = (64 - W) / 2;  // first written lane
+    const int64_t gx = (int64_t)tx * W - kLo + lane;
     const int64_t gy0 = (int64_t)ty * H;
     const int64_t z0 = (int64_t)tz * ZC;
     const int64_t z1 = z0 + ZC < n2 ? z0 + ZC : n2;
@@ -130,7 +134,7 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
             const A rr = bz[r] - s;
             const A t = di[r] * rr;
             const int64_t gy = gy0 + r;
-            if (lane >= 1 && lane < 63 && row_ok(gy))
+            if (lane >= kLo && lane < kLo + W && row_ok(gy))
                 xo[colp + gy * s1 + z * s2] = V::store(xc + w * t);
         }
 #pragma unroll

@@ -280,9 +280,10 @@ class BatchSolver:
         """(tile_rows, sweeps per step, waves per block, steps per graph, use_graph)."""
         return abi.srj_batch_get_plan(self.handle)
 
-    def set_plan3d(self, tile_rows: int, planes: int) -> None:
-        """Plane tile of the 3D instances: rows per tile, planes per work item."""
-        abi.srj_batch_set_plan3d(self.handle, tile_rows, planes)
+    def set_plan3d(self, tile_rows: int, planes: int, sweeps: int = 2) -> None:
+        """Plane tile of the 3D instances: rows per tile, planes per work item,
+        most sweeps per step (1 or 2)."""
+        abi.srj_batch_set_plan3d(self.handle, tile_rows, planes, sweeps)
 
     def get_plan3d(self):
         return abi.srj_batch_get_plan3d(self.handle)

@@ -83,21 +83,23 @@ def test_batch_plans_identical(torch_cuda, orc):
 
 
 TILES3D = [(4, 8), (2, 16), (4, 16), (8, 8), (8, 16)]
+PLANS3D = [t + (s,) for s in (2, 1) for t in TILES3D]
 
 
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("bf16", 1e-8)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("bf16", 1e-8), ("f32", 1e-10)])
 def test_batch_3d_tiles_identical(torch_cuda, orc, precision, tol):
-    # every plane tile of the 3D instances gives the same bits: boxes wider
-    # than one 62-column tile, ragged in rows and planes
+    # every plane tile of the 3D instances, with one or two sweeps per step,
+    # gives the same bits: boxes wider than one 60-column tile, ragged in rows
+    # and planes, cycles of odd and even length
     from paper_2011_06636_amd import abi
     from paper_2011_06636_amd.solver import BatchSolver
     probs = [workloads.c5_instance(i, lo=20, hi=70) for i in range(5)]
     assert max(p.n[0] for p in probs) > 62
     bs = BatchSolver(probs)
-    assert bs.get_plan3d() == (4, 8)
+    assert bs.get_plan3d() == (4, 8, 2)
     kw = dict(tol=tol, precision=precision, max_cycles=200)
     base = None
-    for tile in TILES3D:
+    for tile in PLANS3D:
         bs.set_plan3d(*tile)
         assert bs.get_plan3d() == tile
         out = bs.solve(**kw)
@@ -112,6 +114,10 @@ def test_batch_3d_tiles_identical(torch_cuda, orc, precision, tol):
         with pytest.raises(abi.SrjError) as e:
             bs.set_plan3d(*bad)
         assert e.value.status == abi.SRJ_ERR_UNSUPPORTED
+    for sweeps in (0, 3):
+        with pytest.raises(abi.SrjError) as e:
+            bs.set_plan3d(4, 8, sweeps)
+        assert e.value.status == abi.SRJ_ERR_INVALID
     bs.close()
 
 
@@ -141,7 +147,7 @@ def test_batch_autotune_keeps_results(torch_cuda, orc):
     assert us > 0
     rows, T, waves, _, _ = bs.get_plan()
     assert (rows, waves) in ((16, 1), (24, 1), (32, 1), (48, 1), (8, 8), (12, 8), (16, 4)) and T >= 1
-    assert bs.get_plan3d() in TILES3D
+    assert bs.get_plan3d() in PLANS3D
     out = bs.solve(**kw)
     for a, b in zip(out["xs"], ref_x):
         assert np.array_equal(a.cpu().numpy(), b)
