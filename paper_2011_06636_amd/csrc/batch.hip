@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_bsweep2d(const BDesc *__restrict__ desc
     using A = typename V::A;
     const int lane = threadIdx.x & 63;
     const int nwaves = gridDim.x * 4;
-    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < nitems; item += nwaves) {
+    for (int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems; item += nwaves) {
         const int2 it = items[item];
         const BState s = st[it.x];
         if (s.done) continue;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_bsweep3d(const BDesc *__restrict__ desc
 {
     using A = typename V::A;
     const int nwaves = gridDim.x * 4;
-    for (int item = blockIdx.x * 4 + (threadIdx.x >> 6); item < nitems; item += nwaves) {
+    for (int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); item < nitems; item += nwaves) {
         const int2 it = items[item];
         const BState s = st[it.x];
         if (s.done) continue;

@@ -47,14 +47,47 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
     const int64_t z0 = (int64_t)tz * ZC;
     const int64_t z1 = z0 + ZC < n2 ? z0 + ZC : n2;
     const bool col_in = gx >= 0 && gx < n0;
-    const int64_t colp = gx;  // column part of the flat index
     auto row_ok = [&](int64_t gy) { return col_in && gy >= 0 && gy < n1; };
+    // 16-bit storage: addresses are a wave-uniform row offset (rows clamped
+    // into the grid, formed once per tile) plus a plane offset (clamped) plus
+    // a 32-bit lane offset (lanes outside the grid read column 0), so every
+    // load is unconditional, and values outside the grid are then replaced by
+    // zero through per-lane selects (a wave-uniform condition would let the
+    // compiler branch around each load and wait for it on its own).  Measured
+    // 1.8-1.9x faster for 16-bit storage; binary32 and binary64 keep per-lane
+    // addresses and predicated loads, which measured faster for them.
+    constexpr bool kLean = sizeof(typename V::T) == 2;
+    const int64_t colp = gx;  // column part of the flat index
+    const uint32_t off = col_in ? (uint32_t)gx : 0u;
+    int64_t yoff[H + 2];  // rows gy0 - 1 .. gy0 + H
+    uint32_t rows_in = 0;
+#pragma unroll
+    for (int i = 0; i < H + 2; ++i) {
+        const int64_t gy = gy0 - 1 + i;
+        yoff[i] = (gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy)) * s1;
+        if (gy >= 0 && gy < n1) rows_in |= 1u << i;
+    }
+    auto zoff = [&](int64_t z) { return (z < 0 ? 0 : (z >= n2 ? n2 - 1 : z)) * s2; };
+    auto lane_rows = [&](int64_t z) -> uint32_t {
+        return (col_in && z >= 0 && z < n2) ? rows_in : 0u;
+    };
     auto ldu = [&](int64_t z, int64_t gy) -> A {
-        return (z >= 0 && z < n2 && row_ok(gy)) ? V::load(x[colp + gy * s1 + z * s2]) : A(0);
+        if constexpr (!kLean)
+            return (z >= 0 && z < n2 && row_ok(gy)) ? V::load(x[colp + gy * s1 + z * s2]) : A(0);
+        const int i = (int)(gy - gy0) + 1;
+        const A v = V::load(x[zoff(z) + yoff[i] + off]);
+        return ((lane_rows(z) >> i) & 1) ? v : A(0);
     };
     auto ldc = [&](const A *arr, A cst, int64_t z, int64_t gy) -> A {  // coupling / D / 1/D
-        if (!(z >= 0 && z < n2 && row_ok(gy))) return A(0);
-        return arr ? arr[colp + gy * s1 + z * s2] : cst;
+        if constexpr (!kLean) {
+            if (!(z >= 0 && z < n2 && row_ok(gy))) return A(0);
+            return arr ? arr[colp + gy * s1 + z * s2] : cst;
+        }
+        const int i = (int)(gy - gy0) + 1;
+        const bool in = (lane_rows(z) >> i) & 1;
+        if (!arr) return in ? cst : A(0);
+        const A v = arr[zoff(z) + yoff[i] + off];
+        return in ? v : A(0);
     };
     // Products are formed once and moved or kept, not recomputed: c0lo u_{-e0}
     // is lane p-1's (c0 u) shifted one lane; with constant couplings, c1 u of
@@ -80,7 +113,12 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
         for (int r = 0; r < H; ++r) {
             const int64_t gy = gy0 + r;
             up[r] = ldu(z + 1, gy);
-            bz[r] = row_ok(gy) ? V::load(b[colp + gy * s1 + z * s2]) : A(0);
+            if constexpr (kLean) {
+                const A v = V::load(b[zoff(z) + yoff[r + 1] + off]);
+                bz[r] = row_ok(gy) ? v : A(0);
+            } else {
+                bz[r] = row_ok(gy) ? V::load(b[colp + gy * s1 + z * s2]) : A(0);
+            }
             f0[r] = FACE ? ldc(S.face[0], S.c[0], z, gy) : S.c[0];
             f1[r] = FACE ? ldc(S.face[1], S.c[1], z, gy) : S.c[1];
             f2c[r] = FACE ? ldc(S.face[2], S.c[2], z, gy) : S.c[2];
@@ -135,7 +173,7 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
             const A t = di[r] * rr;
             const int64_t gy = gy0 + r;
             if (lane >= kLo && lane < kLo + W && row_ok(gy))
-                xo[colp + gy * s1 + z * s2] = V::store(xc + w * t);
+                xo[zoff(z) + yoff[r + 1] + off] = V::store(xc + w * t);
         }
 #pragma unroll
         for (int r = 0; r < H; ++r) {
@@ -158,7 +196,7 @@ __global__ __launch_bounds__(256) void k_plane3d(Stencil3<typename V::A> S,
                                                  const typename V::A *__restrict__ wp, int tiles_x,
                                                  int tiles_y, int tiles_z)
 {
-    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
     const int tx = item % tiles_x, ty = (item / tiles_x) % tiles_y, tz = item / (tiles_x * tiles_y);
     plane3d_run<V, H, ZC, FACE, DIAG>(S, x, xo, b, wp[0], tx, ty, tz, threadIdx.x & 63);
