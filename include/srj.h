@@ -231,7 +231,8 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * arrays and a per-point diagonal, one column per lane; kind 11: 3D with
  * constant couplings and diagonal, two sweeps per launch (sweeps_per_launch
  * 1 or 2) in plane tiles of 60 written columns x tile_rows rows streamed
- * over waves_per_simd planes (that field is the chunk length, as for kind 6).
+ * over waves_per_simd planes (that field is the chunk length, as for kind 6);
+ * kind 12: the same for 3D with all faces and a diagonal array.
  * Otherwise waves_per_simd is the register budget the kernel was compiled
  * for.  SRJ_ERR_UNSUPPORTED if the problem cannot use the plan.  Defaults at
  * setup, binary64: 2D constant-coefficient grids of at least 64 x 64 take
@@ -241,9 +242,11 @@ srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_so
  * waves) when they hold at least 1024 blocks of 48 x 48 written points, else
  * (4 rows, 12 sweeps, 16 waves); 3D with constant coefficients takes kind
  * 11 (4 rows, 2 sweeps, 8-plane chunks), 3D with all faces and a diagonal
- * array kind 6 (4 rows, 8-plane chunks), other 3D layouts kind 3; anything
- * else kind 0.  Inner sweeps: the same with kind 7 in place of kind 8, kind
- * 10 always (8 rows, 8 sweeps, 8 waves) and kind 11 with 8 rows. */
+ * array kind 12 (4 rows, 2 sweeps, 16-plane chunks where that still gives
+ * 4096 tiles of 60 columns x 4 rows x 16 planes, else 8), other 3D layouts kind
+ * 3; anything else kind 0.  Inner sweeps: the same with kind 7 in place of
+ * kind 8, kind 10 always (8 rows, 8 sweeps, 8 waves) and kind 11 with 8
+ * rows. */
 srj_status srj_set_plan(srj_ctx *ctx, int32_t which, int32_t kind, int32_t tile_rows,
                         int32_t sweeps_per_launch, int32_t waves_per_simd);
 srj_status srj_get_plan(srj_ctx *ctx, int32_t which, int32_t *kind, int32_t *tile_rows,

@@ -103,6 +103,15 @@ srj_status validate_opts(const srj_solve_opts *o)
     return SRJ_OK;
 }
 
+// Plane chunk of the per-face two-sweep tiles (4 rows, 60 columns): 16 when
+// the grid still gives at least 4096 waves with it (measured 7 % faster than
+// 8 at 256^3), else 8 (1.6x faster at 96^3, where 16 leaves too few waves).
+int per_face_chunk(const DevProblem &P)
+{
+    const int64_t waves = ((P.n0 + 59) / 60) * ((P.n1 + 3) / 4) * ((P.n2 + 15) / 16);
+    return waves >= 4096 ? 16 : 8;
+}
+
 SweepPlan default_inner_plan(const DevProblem &P)
 {
     SweepPlan pl;
@@ -113,9 +122,12 @@ SweepPlan default_inner_plan(const DevProblem &P)
             pl.T = 2;
             pl.occ = 8;
         } else if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
-            pl.kind = 6;  // plane tiles: 4 rows, 8 planes per chunk
+            // per-face two-sweep plane tiles of 4 rows: chunks of 16 planes
+            // where they still give at least 4096 waves, else 8
+            pl.kind = 12;
             pl.by = 4;
-            pl.occ = 8;
+            pl.T = 2;
+            pl.occ = per_face_chunk(P);
         } else {
             pl.kind = 3;
             pl.by = 16;
@@ -149,9 +161,12 @@ SweepPlan default_plan(const DevProblem &P)
             pl.T = 2;
             pl.occ = 8;
         } else if (plane3d_fits(P.ndim, P.face[0], P.face[1], P.face[2], P.diag)) {
-            pl.kind = 6;
+            // per-face two-sweep plane tiles of 4 rows: chunks of 16 planes
+            // where they still give at least 4096 waves, else 8
+            pl.kind = 12;
             pl.by = 4;
-            pl.occ = 8;
+            pl.T = 2;
+            pl.occ = per_face_chunk(P);
         } else {
             pl.kind = 3;
             pl.by = 16;

@@ -187,6 +187,19 @@ hipError_t launch_inner_fused(const SweepPlan &plan, const DevProblem32 &Q, cons
 #undef SRJ_GOF
         return hipErrorInvalidValue;
     }
+    if (plan.kind == 12) {
+        const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
+                                {Q.face[0], Q.face[1], Q.face[2]}, Q.dconst, Q.dinvconst,
+                                Q.diag, Q.dinv};
+        // the last launch of an odd-length cycle does one sweep
+        if (T == 1) return launch_plane3d<St, 4, 8>(S, dd, oo, rr, w_dev, s);
+        if (T != 2) return hipErrorInvalidValue;
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d2f<St, HH, ZZ>(S, dd, oo, rr, w_dev, s);
+        SRJ_INNER_PLANE2F_VARIANTS(SRJ_GO)
+#undef SRJ_GO
+        return hipErrorInvalidValue;
+    }
     if (plan.kind == 11) {
         const Stencil3<float> S{Q.n0, Q.n1, Q.n2, {Q.c[0], Q.c[1], Q.c[2]},
                                 {nullptr, nullptr, nullptr}, Q.dconst, Q.dinvconst, nullptr,
@@ -296,6 +309,15 @@ bool inner_fused_supported(const DevProblem &P, const SweepPlan &plan)
 #undef SRJ_CHK
         return false;
     }
+    if (plan.kind == 12) {
+        if (!(P.ndim == 3 && P.face[0] && P.face[1] && P.face[2] && P.diag) || plan.T < 1 ||
+            plan.T > 2)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_INNER_PLANE2F_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
     if (plan.kind == 11) {
         if (!(P.ndim == 3 && !P.face[0] && !P.face[1] && !P.face[2] && !P.diag) || plan.T < 1 ||
             plan.T > 2)
@@ -378,6 +400,16 @@ int inner_plan_variants(int32_t *out, int cap)
     ++n;
     SRJ_INNER_PLANE2_VARIANTS(SRJ_LIST11)
 #undef SRJ_LIST11
+#define SRJ_LIST12(HH, ZZ)             \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 12;           \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 2;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_INNER_PLANE2F_VARIANTS(SRJ_LIST12)
+#undef SRJ_LIST12
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \

@@ -248,6 +248,16 @@ int plan_variants(int32_t *out, int cap)
     ++n;
     SRJ_PLANE2_VARIANTS(SRJ_LIST11)
 #undef SRJ_LIST11
+#define SRJ_LIST12(HH, ZZ)             \
+    if (n < cap) {                     \
+        out[4 * n + 0] = 12;           \
+        out[4 * n + 1] = HH;           \
+        out[4 * n + 2] = 2;            \
+        out[4 * n + 3] = ZZ;           \
+    }                                  \
+    ++n;
+    SRJ_PLANE2F_VARIANTS(SRJ_LIST12)
+#undef SRJ_LIST12
 #define SRJ_LIST5(OH, TM)              \
     if (n < cap) {                     \
         out[4 * n + 0] = 5;            \
@@ -295,6 +305,15 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan)
         if (!(P.ndim == 2 && P.face[0] && P.face[1] && P.diag && P.dinv) || plan.T < 1) return false;
 #define SRJ_CHK(HW, HL, NW) if (plan.by == HW && plan.occ == NW && plan.T <= HL) return true;
         SRJ_BLOCKF_VARIANTS(SRJ_CHK)
+#undef SRJ_CHK
+        return false;
+    }
+    if (plan.kind == 12) {
+        if (!(P.ndim == 3 && P.face[0] && P.face[1] && P.face[2] && P.diag) || plan.T < 1 ||
+            plan.T > 2)
+            return false;
+#define SRJ_CHK(HH, ZZ) if (plan.by == HH && plan.occ == ZZ) return true;
+        SRJ_PLANE2F_VARIANTS(SRJ_CHK)
 #undef SRJ_CHK
         return false;
     }
@@ -365,6 +384,19 @@ hipError_t launch_sweep_fused(const DevProblem &P, const SweepPlan &plan, const 
                                                   P.diag, P.dinv, w_dev, T, s, reverse);
         SRJ_BLOCKF_VARIANTS(SRJ_GOF)
 #undef SRJ_GOF
+        return hipErrorInvalidValue;
+    }
+    if (plan.kind == 12) {
+        const Stencil3<double> S{P.n0, P.n1, P.n2, {P.c[0], P.c[1], P.c[2]},
+                                 {P.face[0], P.face[1], P.face[2]}, P.dconst, P.dinvconst,
+                                 P.diag, P.dinv};
+        // the last launch of an odd-length cycle does one sweep
+        if (T == 1) return launch_plane3d<StF64, 4, 8>(S, x, xo, P.b, w_dev, s);
+        if (T != 2) return hipErrorInvalidValue;
+#define SRJ_GO(HH, ZZ) \
+    if (plan.by == HH && plan.occ == ZZ) return launch_plane3d2f<StF64, HH, ZZ>(S, x, xo, P.b, w_dev, s);
+        SRJ_PLANE2F_VARIANTS(SRJ_GO)
+#undef SRJ_GO
         return hipErrorInvalidValue;
     }
     if (plan.kind == 11) {

@@ -271,6 +271,42 @@ def test_3d_two_sweep_plans_bit_identical(torch_cuda, orc, case):
     s.close()
 
 
+@pytest.mark.parametrize("n", [27, 65, 5])
+def test_3d_two_sweep_face_plans_bit_identical(torch_cuda, orc, n):
+    # the per-face two-sweep plane kernels (plan kind 12, every tile shape,
+    # odd and even cycle lengths) give the bits of the one-sweep kernel on
+    # variable-coefficient boxes (65: wider than one 60-column tile), and the
+    # oracle agrees; constant-coefficient boxes refuse them
+    from paper_2011_06636_amd import abi
+    prob = workloads.variable_coefficient(n, seed=n, corr_len=3.0)
+    s = _solver(prob)
+    x0 = np.random.default_rng(10).uniform(-1, 1, prob.shape)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] == 12]
+    assert len(plans) > 1
+    results = {}
+    levels = (0, 1, 2, 5, 9)
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in levels:
+            s.run_cycle(x, level)
+        results[plan] = x.cpu().numpy()
+    base = results[(0, 0, 1, 1)]
+    for plan, v in results.items():
+        assert np.array_equal(v, base), plan
+    x_ref = x0.copy()
+    for level in levels:
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    assert _close(base, x_ref)
+    s.close()
+    s = _solver(workloads.poisson([20, 10, 12]))
+    for v in abi.srj_plan_variants():
+        if v[0] == 12:
+            assert s.set_plan(*v) != 0
+    s.close()
+
+
 def test_resume_is_bit_identical(torch_cuda, orc):
     prob = workloads.c2(n=160)
     s = _solver(prob)
@@ -336,13 +372,14 @@ def test_default_2d_plan_follows_grid_size(torch_cuda):
 
 def test_default_3d_plans(torch_cuda):
     # constant coefficients: two sweeps per launch (kind 11), 4 rows binary64,
-    # 8 rows inner; per-face boxes: one-sweep plane tiles (kind 6)
+    # 8 rows inner; per-face boxes: two sweeps per launch too (kind 12)
     from paper_2011_06636_amd.solver import Solver
     s = Solver(workloads.poisson([40, 30, 20]))
     assert tuple(s.get_plan(0)) == (11, 4, 2, 8) and tuple(s.get_plan(1)) == (11, 8, 2, 8)
     s.close()
     s = Solver(workloads.variable_coefficient(16, seed=0))
-    assert tuple(s.get_plan(0)) == (6, 4, 1, 8) and tuple(s.get_plan(1)) == (6, 4, 1, 8)
+    # (8-plane chunks: 16^3 gives fewer than 4096 tiles of 16 planes)
+    assert tuple(s.get_plan(0)) == (12, 4, 2, 8) and tuple(s.get_plan(1)) == (12, 4, 2, 8)
     s.close()
 
 

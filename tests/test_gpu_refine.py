@@ -163,6 +163,32 @@ def test_inner_3d_two_sweep_plans_bit_identical(torch_cuda, orc, precision):
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
+def test_inner_3d_two_sweep_face_plans_bit_identical(torch_cuda, orc, precision):
+    # the per-face two-sweep plane kernels (kind 12) in the inner sweeps:
+    # the bits of one sweep per launch on a variable-coefficient box, and the
+    # oracle agrees
+    from paper_2011_06636_amd import abi
+    prob = workloads.variable_coefficient(23, seed=6, corr_len=3.0)
+    s = _solver(prob)
+    kw = dict(tol=1e-300, precision=precision, max_cycles=9)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] == 12]
+    assert len(plans) > 1
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan, which=1) == 0, plan
+        out = s.solve(**kw)
+        results[plan] = (out["levels"].copy(), out["x"].cpu().numpy())
+    base_lv, base_x = results[(0, 0, 1, 1)]
+    for plan, (lv, xv) in results.items():
+        assert np.array_equal(lv, base_lv), plan
+        assert np.array_equal(xv, base_x), plan
+    ref = orc.solve(prob, **kw)
+    np.testing.assert_array_equal(ref["levels"], base_lv)
+    assert np.max(np.abs(base_x - ref["x"])) <= 1e-12 * np.max(np.abs(ref["x"]))
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16", "f16"])
 def test_inner_3d_plans_bit_identical(torch_cuda, orc, precision):
     from paper_2011_06636_amd import abi
     prob = workloads.variable_coefficient(23, seed=4, corr_len=3.0)
