@@ -1,5 +1,5 @@
-"""A grid of more than 2^31 points (65536 x 32769, the largest axis-1 extent
-is 65535): every index on the path must be 64-bit.
+"""Grids of more than 2^31 points (2D: 65536 x 32769; 3D: 2048 x 1024 x
+1025, swept two sweeps per launch): every index on the path must be 64-bit.
 
 From x0 = 0 with b = 1 and unit couplings, after one level-1 cycle (two
 sweeps) a point's value depends only on its distance to each boundary, up to
@@ -84,6 +84,58 @@ def test_more_than_2_31_points(torch_cuda, orc):
         got = np.stack([_row(x.data_ptr(), j)[cols] for j in rows])
         want = np.array([[xs[_map(j, N1), _map(i, N0)] for i in cols] for j in rows])
         assert np.array_equal(got, want)
+        assert nrm == pytest.approx(want_norm, rel=1e-10)
+    finally:
+        abi.srj_destroy(ctx)
+    del x, b
+    torch.cuda.empty_cache()
+
+
+M0, M1, M2 = 2048, 1024, 1025
+
+
+def test_3d_more_than_2_31_points(torch_cuda, orc):
+    # the same construction in 3D: a level-1 cycle (two sweeps, one launch of
+    # the two-sweep plane kernel) on a 2048 x 1024 x 1025 box, checked against
+    # a 9 x 9 x 9 reference box on sampled rows, and the norm as a weighted sum
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import make_problem
+    torch = torch_cuda
+    npts = M0 * M1 * M2
+    assert npts > 2 ** 31
+    small = workloads.anisotropic([9, 9, 9], (1.0, 1.0, 1.0), np.ones((9, 9, 9)))
+    xs = np.zeros(small.shape)
+    for w in orc.scheme(1):
+        xs = orc.sweep(small, xs, float(w))
+    rs = (small.b - orc.apply(small, xs)).reshape(9, 9, 9)
+    xs = xs.reshape(9, 9, 9)
+    wt = np.array([1.0] * 4 + [0.0] + [1.0] * 4)
+    w0, w1, w2 = wt.copy(), wt.copy(), wt.copy()
+    w0[4], w1[4], w2[4] = M0 - 8, M1 - 8, M2 - 8
+    want_norm = math.sqrt(float(np.sum(w2[:, None, None] * w1[None, :, None] * w0[None, None, :]
+                                       * rs * rs)))
+    b = torch.ones(npts, dtype=torch.float64, device="cuda")
+    x = torch.zeros(npts, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    p = make_problem(3, [M0, M1, M2], [1.0, 1.0, 1.0], 6.0, b)
+    ctx = abi.srj_setup(p, torch.cuda.current_stream().cuda_stream)
+    try:
+        assert abi.srj_get_plan(ctx, 0)[0] == 11
+        nrm = abi.srj_run_cycle(ctx, x.data_ptr(), 1)
+        torch.cuda.synchronize()
+        planes = [0, 1, 3, 4, M2 // 2, (2 ** 31) // (M0 * M1), M2 - 4, M2 - 2, M2 - 1]
+        rows = [0, 2, 4, M1 // 2, M1 - 3, M1 - 1]
+        cols = [0, 1, 3, 4, M0 // 2, M0 - 4, M0 - 1]
+        hip = _hip()
+        for k in planes:
+            for j in rows:
+                assert 0 <= k < M2 and 0 <= j < M1, (k, j)
+                out = np.empty(M0, dtype=np.float64)
+                ofs = 8 * (k * M1 * M0 + j * M0)
+                assert ofs + 8 * M0 <= 8 * npts
+                assert hip.hipMemcpy(out.ctypes.data, x.data_ptr() + ofs, 8 * M0, 2) == 0
+                want = np.array([xs[_map(k, M2), _map(j, M1), _map(i, M0)] for i in cols])
+                assert np.array_equal(out[cols], want), (k, j)
         assert nrm == pytest.approx(want_norm, rel=1e-10)
     finally:
         abi.srj_destroy(ctx)
