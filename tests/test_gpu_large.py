@@ -94,10 +94,13 @@ def test_more_than_2_31_points(torch_cuda, orc):
 M0, M1, M2 = 2048, 1024, 1025
 
 
-def test_3d_more_than_2_31_points(torch_cuda, orc):
+@pytest.mark.parametrize("faces", [False, True])
+def test_3d_more_than_2_31_points(torch_cuda, orc, faces):
     # the same construction in 3D: a level-1 cycle (two sweeps, one launch of
-    # the two-sweep plane kernel) on a 2048 x 1024 x 1025 box, checked against
-    # a 9 x 9 x 9 reference box on sampled rows, and the norm as a weighted sum
+    # the two-sweep plane kernel: constant coefficients, or unit face arrays
+    # and a diagonal array of 6, about 140 GB in all) on a 2048 x 1024 x 1025
+    # box, checked against a 9 x 9 x 9 reference box on sampled rows, and the
+    # norm as a weighted sum
     from paper_2011_06636_amd import abi
     from paper_2011_06636_amd.solver import make_problem
     torch = torch_cuda
@@ -117,10 +120,18 @@ def test_3d_more_than_2_31_points(torch_cuda, orc):
     b = torch.ones(npts, dtype=torch.float64, device="cuda")
     x = torch.zeros(npts, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    p = make_problem(3, [M0, M1, M2], [1.0, 1.0, 1.0], 6.0, b)
+    arrays = []
+    if faces:
+        arrays = [torch.ones(npts, dtype=torch.float64, device="cuda") for _ in range(3)]
+        arrays.append(torch.full((npts,), 6.0, dtype=torch.float64, device="cuda"))
+        p = make_problem(3, [M0, M1, M2], [0.0, 0.0, 0.0], 1.0, b, faces=arrays[:3],
+                         diag=arrays[3])
+    else:
+        p = make_problem(3, [M0, M1, M2], [1.0, 1.0, 1.0], 6.0, b)
+    torch.cuda.synchronize()
     ctx = abi.srj_setup(p, torch.cuda.current_stream().cuda_stream)
     try:
-        assert abi.srj_get_plan(ctx, 0)[0] == 11
+        assert abi.srj_get_plan(ctx, 0)[0] == (12 if faces else 11)
         nrm = abi.srj_run_cycle(ctx, x.data_ptr(), 1)
         torch.cuda.synchronize()
         planes = [0, 1, 3, 4, M2 // 2, (2 ** 31) // (M0 * M1), M2 - 4, M2 - 2, M2 - 1]
@@ -139,5 +150,5 @@ def test_3d_more_than_2_31_points(torch_cuda, orc):
         assert nrm == pytest.approx(want_norm, rel=1e-10)
     finally:
         abi.srj_destroy(ctx)
-    del x, b
+    del x, b, arrays
     torch.cuda.empty_cache()
