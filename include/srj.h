@@ -89,8 +89,11 @@ typedef enum {
  * UPDATE_INF: after every sweep, max_p |x'_p - x_p| < tol, the update norm
  * of the 2D Laplace test with Neumann boundaries (section 4.2.2, Eq. (25));
  * the selector still runs on cycle-end residual ratios.  UPDATE_INF needs
- * precision SRJ_PREC_F64 and runs one sweep per launch, the update's maximum
- * reduced in the sweep kernel; the solve stops at the exact sweep. */
+ * precision SRJ_PREC_F64; the update's maximum is reduced in the sweep
+ * kernels (one sweep per launch, or the fused per-face blocks of plan kind
+ * 10, where the stop sweep's iterate is formed again from its launch's
+ * input); the solve stops at the exact sweep, with the same iterate for
+ * every plan. */
 typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1, SRJ_TOL_UPDATE_INF = 2 } srj_tol_mode;
 
 #define SRJ_NUM_LEVELS 25

@@ -315,6 +315,7 @@ srj_status srj_destroy(srj_ctx *c)
     else (void)hipDeviceSynchronize();
     refine_free(c);
     (void)hipFree(c->upd);
+    (void)hipFree(c->updf);
     for (void *q : {(void *)c->csr_diag, (void *)c->csr_b, (void *)c->csr_val, (void *)c->csr_len,
                     (void *)c->csr_col})
         (void)hipFree(q);
@@ -688,9 +689,126 @@ srj_status srj_residual_norm(srj_ctx *c, const double *x, double *norm_out)
 // After each cycle the host reads the test state: a launch inside the cycle
 // may have found that an earlier sweep met the test (later launches then did
 // nothing), or the cycle's last sweep met it.
+// The update test with fused sweeps (plan kind 10): each launch of T sweeps
+// records the largest |x' - x| of each of its sweeps, a check after it finds
+// the first sweep below tol, and later launches do nothing.  A launch reads
+// one buffer and writes the other, and the launches after the stop write
+// nothing, so the input of the launch that held the stop is intact: the
+// iterate of the stop sweep is formed again from it (the same sweeps, so the
+// same bits) unless the stop is that launch's last sweep.
+static srj_status solve_update_inf_fused(srj_ctx *c, double *x, const srj_solve_opts *o,
+                                         srj_solve_result *res, int32_t *levels_out,
+                                         double *norms_out)
+{
+    if (!c->updf && hipMalloc(&c->updf, sizeof(UpdFState)) != hipSuccess) {
+        c->updf = nullptr;
+        return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the update test state");
+    }
+    SRJ_HIP_CHECK(hipMemsetAsync(c->updf, 0, sizeof(UpdFState), c->stream));
+    SRJ_HIP_CHECK(launch_upd_check(c->updf, 1, 0, 0, o->tol, c->stream));  // clears ring 0
+    double norm0 = 0.0;
+    srj_status st = residual_norm(c, x, &norm0);
+    if (st != SRJ_OK) return st;
+    res->r0 = o->r0 > 0.0 ? o->r0 : norm0;
+    res->r_final = norm0;
+    if (norms_out) norms_out[0] = norm0;
+    if (!isfinite(norm0)) return fail(SRJ_ERR_NONFINITE, "initial residual norm is not finite");
+    if (norm0 == 0.0) {
+        res->converged = 1;  // x solves the system: every update is zero
+        return SRJ_OK;
+    }
+    struct Launch {
+        int64_t g0;
+        int T, done;
+        double *in, *out;
+    };
+    std::vector<Launch> launches;
+    srj_status status = SRJ_ERR_NOT_CONVERGED;
+    int level = o->start_level;
+    double prev = norm0;
+    double *cur = x, *nxt = c->ws;
+    double *result = x;  // the iterate of the last sweep that counts
+    int64_t g = 0;       // sweeps enqueued
+    int64_t nl = 0;      // launches enqueued
+    for (int cycle = 0; cycle < o->max_cycles; ++cycle) {
+        const int lv = o->rule == SRJ_RULE_FIXED ? o->fixed_level : level;
+        const int M = static_cast<int>(c->factors[lv].size());
+        if (g + M > o->max_sweeps) break;
+        const double *wdev = c->omega_dev + c->offsets[lv];
+        launches.clear();
+        for (int done = 0; done < M; ++nl) {
+            const int T = std::min(c->plan.T, M - done);
+            const int ring = (int)(nl & 1);
+            SRJ_HIP_CHECK(launch_sweep_fused_upd(c->P, c->plan, cur, nxt, wdev + done, T, c->updf,
+                                                 ring, c->stream, c->reverse));
+            SRJ_HIP_CHECK(launch_upd_check(c->updf, ring, T, g, o->tol, c->stream));
+            c->reverse = !c->reverse;
+            launches.push_back({g, T, done, cur, nxt});
+            std::swap(cur, nxt);
+            g += T;
+            done += T;
+        }
+        double norm = 0.0;
+        st = residual_norm(c, cur, &norm);  // synchronises the stream
+        if (st != SRJ_OK) return st;
+        int32_t flag = 0;
+        int64_t stop = -1;
+        SRJ_HIP_CHECK(hipMemcpy(&flag, &c->updf->flag, sizeof(flag), hipMemcpyDeviceToHost));
+        if (flag) SRJ_HIP_CHECK(hipMemcpy(&stop, &c->updf->stop, sizeof(stop), hipMemcpyDeviceToHost));
+        res->cycles = cycle + 1;
+        res->final_level = lv;
+        if (levels_out) levels_out[cycle] = lv;
+        if (flag) {
+            const Launch *hit = nullptr;
+            for (const Launch &L : launches)
+                if (stop >= L.g0 && stop < L.g0 + L.T) hit = &L;
+            if (!hit) return fail(SRJ_ERR_HIP, "update test stop outside the cycle's launches");
+            result = hit->out;
+            const int Tstop = (int)(stop - hit->g0) + 1;
+            if (Tstop != hit->T || hit != &launches.back()) {
+                if (Tstop != hit->T)  // the stop sweep's iterate, formed again
+                    SRJ_HIP_CHECK(launch_sweep_fused(c->P, c->plan, hit->in, hit->out,
+                                                     wdev + hit->done, Tstop, c->stream,
+                                                     c->reverse));
+                st = residual_norm(c, result, &norm);
+                if (st != SRJ_OK) return st;
+            }
+            res->sweeps = stop + 1;
+            res->r_final = norm;
+            if (norms_out) norms_out[cycle + 1] = norm;
+            res->converged = 1;
+            status = SRJ_OK;
+            break;
+        }
+        result = cur;
+        res->sweeps = g;
+        res->r_final = norm;
+        if (norms_out) norms_out[cycle + 1] = norm;
+        if (!isfinite(norm)) {
+            status = fail(SRJ_ERR_NONFINITE, "residual norm is not finite");
+            break;
+        }
+        const double ratio = norm / prev;
+        prev = norm;
+        if (o->rule == SRJ_RULE_HEURISTIC) {
+            const double m = std::min(fabs(ratio - 0.2), fabs(ratio - 0.4));
+            res->min_margin = std::min(res->min_margin, m);
+        }
+        level = next_level(o->rule, level, ratio, o->max_level);
+    }
+    if (status == SRJ_ERR_NOT_CONVERGED) set_error("cycle or sweep cap reached");
+    if (result != x)
+        SRJ_HIP_CHECK(hipMemcpyAsync(x, result, sizeof(double) * (size_t)c->npoints,
+                                     hipMemcpyDeviceToDevice, c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return status;
+}
+
 static srj_status solve_update_inf(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
                                    int32_t *levels_out, double *norms_out)
 {
+    if (c->plan.kind != 0 && fused_upd_supported(c->P, c->plan))
+        return solve_update_inf_fused(c, x, o, res, levels_out, norms_out);
     if (!c->upd && hipMalloc(&c->upd, sizeof(UpdState)) != hipSuccess) {
         c->upd = nullptr;
         return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the update test state");

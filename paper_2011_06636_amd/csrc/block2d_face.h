@@ -34,7 +34,10 @@
 
 namespace srj {
 
-template <class V, int HW, int NW, bool MASK>
+// With UPD (binary64 only), each sweep also finds the largest |x' - x| over
+// the block's written points and merges it into slot [ring][k] of st (see
+// UpdFState): out_lane and [rlo, rhi) select the written lanes and rows.
+template <class V, int HW, int NW, bool MASK, bool UPD>
 __device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
                                               const typename V::A (&br)[HW],
                                               const typename V::A (&fe)[HW],
@@ -43,15 +46,28 @@ __device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
                                               const typename V::A (&di)[HW], bool col_in,
                                               uint32_t rowbits,
                                               const typename V::A *__restrict__ wlist, int T,
-                                              typename V::A *edge, int wave, int lane)
+                                              typename V::A *edge, int wave, int lane,
+                                              bool out_lane, int rlo, int rhi, UpdFState *st,
+                                              int ring, unsigned long long *red)
 {
     using A = typename V::A;
+    // red: [2][NW] per-wave maxima of the previous sweeps; thread 0 merges
+    // sweep k - 1 after sweep k's barrier (the last one after a final barrier)
+    const int stripe = (int)(blockIdx.x % kUpdFStripes);
+    auto merge = [&](int k) {
+        unsigned long long m = red[(k & 1) * NW];
+#pragma unroll
+        for (int w2 = 1; w2 < NW; ++w2) m = red[(k & 1) * NW + w2] > m ? red[(k & 1) * NW + w2] : m;
+        atomicMax(&st->maxbits[ring][k][stripe * kUpdStride], m);
+    };
     for (int k = 0; k < T; ++k) {
         // edge: [2 buffers][0: first row's x, 1: last row's f1 x][NW][64]
         A *e = edge + (k & 1) * (2 * NW * 64);
         e[wave * 64 + lane] = xr[0];
         e[(NW + wave) * 64 + lane] = fn[HW - 1] * xr[HW - 1];
         __syncthreads();
+        if (UPD && k > 0 && threadIdx.x == 0) merge(k - 1);
+        unsigned long long dmax = 0ull;
         // rows outside the block read zero (they only feed halo rows)
         A pdown = wave > 0 ? e[(NW + wave - 1) * 64 + lane] : A(0);
         const A xup = wave + 1 < NW ? e[(wave + 1) * 64 + lane] : A(0);
@@ -72,17 +88,35 @@ __device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
             const A t = di[r] * rr;
             const A nx = V::round(xc + w * t);
             pdown = pn;
+            if (UPD && r >= rlo && r < rhi) {
+                const bool wr = out_lane && (!MASK || (col_in && ((rowbits >> r) & 1)));
+                const unsigned long long d =
+                    wr ? (unsigned long long)__double_as_longlong(fabs(nx - xc)) : 0ull;
+                dmax = d > dmax ? d : dmax;
+            }
             if (MASK)
                 xr[r] = (col_in && ((rowbits >> r) & 1)) ? nx : A(0);
             else
                 xr[r] = nx;
         }
+        if (UPD) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(dmax, off);
+                dmax = o > dmax ? o : dmax;
+            }
+            if (lane == 0) red[(k & 1) * NW + wave] = dmax;
+        }
+    }
+    if (UPD) {
+        __syncthreads();
+        if (threadIdx.x == 0) merge(T - 1);
     }
 }
 
 // One wave's part of one block (see block2d_run for the addressing and the
 // treatment of blocks that cross the grid's edge).
-template <class V, int HW, int HALO, int NW, bool EDGE>
+template <class V, int HW, int HALO, int NW, bool EDGE, bool UPD>
 __device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1,
                                            const typename V::T *__restrict__ x,
                                            typename V::T *__restrict__ xo,
@@ -93,7 +127,8 @@ __device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1,
                                            const typename V::A *__restrict__ dgi,
                                            const typename V::A *__restrict__ wlist, int T,
                                            int64_t bx0, int64_t by0, int wv, int lane,
-                                           typename V::A *edge)
+                                           typename V::A *edge, UpdFState *st, int ring,
+                                           unsigned long long *red)
 {
     using A = typename V::A;
     using S = BlockShape<HW, HALO, NW, 1>;
@@ -128,16 +163,17 @@ __device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1,
         dd[r] = in ? vd : A(0);
         di[r] = in ? vi : A(0);
     }
-    blockf_sweeps<V, HW, NW, EDGE>(xr, br, fe, fn, dd, di, col_in, rowbits, wlist, T, edge, wv,
-                                   lane);
-    if (!(lane >= HALO && lane < S::BW - HALO) || !col_in) return;
+    const bool out_lane = lane >= HALO && lane < S::BW - HALO;
     const int rlo = HALO - wv * HW, rhi = S::BH - HALO - wv * HW;
+    blockf_sweeps<V, HW, NW, EDGE, UPD>(xr, br, fe, fn, dd, di, col_in, rowbits, wlist, T, edge, wv,
+                                        lane, out_lane, rlo, rhi, st, ring, red);
+    if (!out_lane || !col_in) return;
 #pragma unroll
     for (int r = 0; r < HW; ++r)
         if (r >= rlo && r < rhi && ((rowbits >> r) & 1)) xo[row_of(r) * n0 + off] = V::store(xr[r]);
 }
 
-template <class V, int HW, int HALO, int NW>
+template <class V, int HW, int HALO, int NW, bool UPD>
 __global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
                                                       const typename V::T *__restrict__ x,
                                                       typename V::T *__restrict__ xo,
@@ -148,9 +184,11 @@ __global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
                                                       const typename V::A *__restrict__ dgi,
                                                       const typename V::A *__restrict__ wlist,
                                                       int T, int blocks_x, int nblocks,
-                                                      int reverse)
+                                                      int reverse, UpdFState *st, int ring)
 {
     __shared__ typename V::A edge[2 * 2 * NW * 64];
+    __shared__ unsigned long long red[UPD ? 2 * NW : 1];
+    if (UPD && st->flag) return;  // an earlier sweep met the update test
     // XCD-aware order, each XCD's range walked backwards on alternate launches
     // (as in block2d.h)
     const int per_xcd = (nblocks + 7) / 8;
@@ -163,20 +201,23 @@ __global__ __launch_bounds__(64 * NW) void k_blockf2d(int64_t n0, int64_t n1,
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (bx0 >= 0 && bx0 + S::BW <= n0 && by0 >= 0 && by0 + S::BH <= n1)
-        blockf_run<V, HW, HALO, NW, false>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0,
-                                           wv, lane, edge);
+        blockf_run<V, HW, HALO, NW, false, UPD>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0,
+                                                by0, wv, lane, edge, st, ring, red);
     else
-        blockf_run<V, HW, HALO, NW, true>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0, by0,
-                                          wv, lane, edge);
+        blockf_run<V, HW, HALO, NW, true, UPD>(n0, n1, x, xo, b, f0, f1, dg, dgi, wlist, T, bx0,
+                                               by0, wv, lane, edge, st, ring, red);
 }
 
-template <class V, int HW, int HALO, int NW>
+// UPD: the update-test form (binary64; st and ring as for blockf_sweeps).
+template <class V, int HW, int HALO, int NW, bool UPD = false>
 hipError_t launch_blockf2d(int64_t n0, int64_t n1, const typename V::T *x, typename V::T *xo,
                            const typename V::T *b, const typename V::A *f0,
                            const typename V::A *f1, const typename V::A *dg,
                            const typename V::A *dgi, const typename V::A *w_dev, int T,
-                           hipStream_t s, bool reverse)
+                           hipStream_t s, bool reverse, UpdFState *st = nullptr, int ring = 0)
 {
+    static_assert(!UPD || sizeof(typename V::A) == sizeof(double), "the update test is binary64");
+    if (UPD && (!st || T > kUpdFMaxT || ring < 0 || ring > 1)) return hipErrorInvalidValue;
     using S = BlockShape<HW, HALO, NW, 1>;
     if (T < 1 || T > HALO) return hipErrorInvalidValue;
     if (n0 > INT32_MAX) return hipErrorInvalidValue;  // column offsets are 32-bit
@@ -185,8 +226,9 @@ hipError_t launch_blockf2d(int64_t n0, int64_t n1, const typename V::T *x, typen
     const int64_t nblocks = bxn * byn;
     if (nblocks > (int64_t)1 << 28) return hipErrorInvalidValue;
     const int grid = (int)((nblocks + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_blockf2d<V, HW, HALO, NW>), dim3(grid), dim3(64 * NW), 0, s, n0, n1, x,
-                       xo, b, f0, f1, dg, dgi, w_dev, T, (int)bxn, (int)nblocks, reverse ? 1 : 0);
+    hipLaunchKernelGGL((k_blockf2d<V, HW, HALO, NW, UPD>), dim3(grid), dim3(64 * NW), 0, s, n0, n1,
+                       x, xo, b, f0, f1, dg, dgi, w_dev, T, (int)bxn, (int)nblocks,
+                       reverse ? 1 : 0, st, ring);
     return hipGetLastError();
 }
 

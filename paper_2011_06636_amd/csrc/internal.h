@@ -122,6 +122,27 @@ struct UpdState {
 // once an earlier sweep met the test.
 hipError_t launch_sweep_upd(const DevProblem &P, const double *x, double *xo, double w, double tol,
                             UpdState *st, int64_t g, hipStream_t s);
+// The update test with fused sweeps (plan kind 10): a launch of T <= kUpdFMaxT
+// sweeps accumulates the largest |x' - x| of its k-th sweep in slot [ring][k]
+// (kUpdFStripes stripes one 128-byte line apart); a one-workgroup check after
+// each launch folds that launch's slots in sweep order, and the first sweep
+// below tol sets flag and stop (its global index); launches that find flag
+// set do nothing.  The check also clears the slots of the other ring.
+constexpr int kUpdFStripes = 16, kUpdFMaxT = 16;
+struct UpdFState {
+    unsigned long long maxbits[2][kUpdFMaxT][kUpdFStripes * kUpdStride];
+    int32_t flag, pad_;
+    int64_t stop;
+};
+// T fused sweeps with the test (kind 10 plans); ring: slot set of this launch.
+hipError_t launch_sweep_fused_upd(const DevProblem &P, const SweepPlan &plan, const double *x,
+                                  double *xo, const double *w_dev, int T, UpdFState *st, int ring,
+                                  hipStream_t s, bool reverse);
+bool fused_upd_supported(const DevProblem &P, const SweepPlan &plan);
+// Folds the T sweeps of the launch that used `ring` (first global index g0),
+// sets flag/stop on the first below tol, and clears the other ring.  T = 0
+// only clears.
+hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, hipStream_t s);
 // Fused sweeps: applies w[0..T-1] (device pointer into the scheme table).
 // reverse alternates the block order of the block kernels (callers flip it
 // every launch); results do not depend on it.
@@ -173,6 +194,7 @@ struct srj_ctx {
     srj::SweepPlan plan_inner;  // inner sweeps of the refinement modes
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     srj::UpdState *upd = nullptr;          // per-sweep update test (lazily allocated)
+    srj::UpdFState *updf = nullptr;        // the same for fused sweeps (lazily allocated)
     // library copies of a general sparse matrix (srj_setup_csr)
     double *csr_diag = nullptr, *csr_b = nullptr, *csr_val = nullptr;
     int32_t *csr_len = nullptr, *csr_col = nullptr;

@@ -207,6 +207,61 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
     return hipGetLastError();
 }
 
+// One workgroup of 64 threads: lane k folds the stripes of sweep k of the
+// launch that used `ring`; the first sweep below tol (in sweep order) sets
+// flag and stop.  Then the slots of the other ring are cleared for the next
+// launch.  Does nothing but the clearing once flag is set.
+__global__ __launch_bounds__(64) void k_upd_check(UpdFState *st, int ring, int T, int64_t g0,
+                                                  double tol)
+{
+    const int lane = threadIdx.x;
+    if (!st->flag && T > 0) {
+        bool below = false;
+        if (lane < T) {
+            unsigned long long m = 0ull;
+            for (int j = 0; j < kUpdFStripes; ++j) {
+                const unsigned long long v = st->maxbits[ring][lane][j * kUpdStride];
+                m = v > m ? v : m;
+            }
+            below = __longlong_as_double((long long)m) < tol;
+        }
+        const unsigned long long mask = __ballot(below);
+        if (mask && lane == 0) {
+            st->flag = 1;
+            st->stop = g0 + (__builtin_ctzll(mask));
+        }
+    }
+    for (int i = lane; i < kUpdFMaxT * kUpdFStripes; i += 64)
+        st->maxbits[ring ^ 1][i / kUpdFStripes][(i % kUpdFStripes) * kUpdStride] = 0ull;
+}
+
+hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, hipStream_t s)
+{
+    if (!st || ring < 0 || ring > 1 || T < 0 || T > kUpdFMaxT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_upd_check, dim3(1), dim3(64), 0, s, st, ring, T, g0, tol);
+    return hipGetLastError();
+}
+
+bool fused_upd_supported(const DevProblem &P, const SweepPlan &plan)
+{
+    return plan.kind == 10 && plan.T <= kUpdFMaxT && fused_supported(P, plan);
+}
+
+hipError_t launch_sweep_fused_upd(const DevProblem &P, const SweepPlan &plan, const double *x,
+                                  double *xo, const double *w_dev, int T, UpdFState *st, int ring,
+                                  hipStream_t s, bool reverse)
+{
+    if (plan.kind != 10) return hipErrorInvalidValue;
+#define SRJ_GOF(HW, HL, NW)                                                                        \
+    if (plan.by == HW && plan.occ == NW && plan.T <= HL)                                           \
+        return launch_blockf2d<StF64, HW, HL, NW, true>(P.n0, P.n1, x, xo, P.b, P.face[0],         \
+                                                        P.face[1], P.diag, P.dinv, w_dev, T, s,     \
+                                                        reverse, st, ring);
+    SRJ_BLOCKF_VARIANTS(SRJ_GOF)
+#undef SRJ_GOF
+    return hipErrorInvalidValue;
+}
+
 int plan_variants(int32_t *out, int cap)
 {
     int n = 0;

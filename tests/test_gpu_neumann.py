@@ -1,10 +1,11 @@
 """GPU parity of the update stopping test on the Neumann Laplace problem
 (section 4.2.2, Eq. (25)).
 
-srj_solve with SRJ_TOL_UPDATE_INF runs one sweep per launch and reduces the
-largest |x' - x| inside the sweep kernel; it must stop at the same sweep as
-the CPU reference, after the same levels, with the same iterate (the
-per-point expression is the reference's, so bit for bit).  Grids are ragged
+srj_solve with SRJ_TOL_UPDATE_INF reduces the largest |x' - x| of every sweep
+inside the sweep kernels (one sweep per launch, or the fused per-face blocks,
+whose stop sweep's iterate is formed again from the launch's input); it must
+stop at the same sweep as the CPU reference, after the same levels, with the
+same iterate (the per-point expression is the reference's, so bit for bit).  Grids are ragged
 against the 256-point launch rows; one case stops inside a cycle, the full
 256 x 256 case of the paper runs both rules.
 """
@@ -55,6 +56,41 @@ def test_update_stop_matches_reference(torch_cuda, orc, n, rule, seed):
     assert got["sweeps"] <= sum(len(orc.scheme(int(lv))) for lv in got["levels"])
 
 
+@pytest.mark.parametrize("n,seed", [(96, 11), (131, 12)])
+def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed):
+    # one sweep per launch and every fused per-face block plan (several sweep
+    # counts, so the stop falls at different places inside launches) stop at
+    # the same sweep with the same iterate
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.neumann_laplace(n)
+    x0 = workloads.random_start(prob, seed)
+    s = Solver(prob)
+    assert s.get_plan(0)[0] == 10
+    plans = [(0, 0, 1, 1)]
+    for kind, rows, halo, occ in abi.srj_plan_variants():
+        if kind == 10:
+            plans += [(kind, rows, t, occ) for t in sorted({1, 3, halo // 2 + 1, halo})]
+    results = {}
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        out = s.solve(x, rule="heuristic", tol=TOL, tol_mode="update_inf", max_cycles=100000)
+        results[plan] = (out["status"], out["sweeps"], out["cycles"], out["levels"].copy(),
+                         out["r_final"], x.cpu().numpy())
+    s.close()
+    base = results[(0, 0, 1, 1)]
+    assert base[0] == "ok"
+    for plan, r in results.items():
+        assert r[:3] == base[:3], plan
+        assert np.array_equal(r[3], base[3]), plan
+        assert r[4] == base[4], plan
+        assert np.array_equal(r[5], base[5]), plan
+    ref = orc.solve(prob, x0, rule="heuristic", tol=TOL, tol_mode="update_inf", max_cycles=100000)
+    assert base[1] == ref["sweeps"]
+    assert np.array_equal(base[5].reshape(-1), ref["x"].reshape(-1))
+
+
 def test_paper_grid_256(torch_cuda, orc):
     for rule in ("heuristic", "increasing"):
         got, gx, ref = _both(orc, 256, rule, 7, max_cycles=100000)
@@ -63,8 +99,10 @@ def test_paper_grid_256(torch_cuda, orc):
         assert np.array_equal(gx.reshape(-1), ref["x"].reshape(-1))
 
 
-def test_sweep_cap(torch_cuda, orc):
-    got, gx, ref = _both(orc, 40, "heuristic", 9, max_sweeps=60)
+@pytest.mark.parametrize("n", [40, 80])
+def test_sweep_cap(torch_cuda, orc, n):
+    # 80: the fused per-face blocks
+    got, gx, ref = _both(orc, n, "heuristic", 9, max_sweeps=60)
     assert got["status"] == ref["status"] == "not_converged"
     assert got["sweeps"] == ref["sweeps"]
     assert np.array_equal(gx.reshape(-1), ref["x"].reshape(-1))
