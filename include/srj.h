@@ -29,7 +29,8 @@
  * fused multiply-add, in the fixed per-point order
  *   s = D_p x_p;  for d = 0..ndim-1: s -= c_lo * x[p - e_d]; s -= c_hi * x[p + e_d];
  *   x'_p = x_p + w * ((1 / D_p) * (b_p - s))
- * (ghost neighbours contribute nothing), so iterates do not depend on tiling
+ * (ghost neighbours contribute nothing, whatever face[d] holds on the last
+ * layer along axis d), so iterates do not depend on tiling
  * or on the number of sweeps fused into one kernel.  The refinement modes
  * run the inner cycles on the correction equation in binary32 arithmetic.
  *

@@ -119,9 +119,17 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
             } else {
                 bz[r] = row_ok(gy) ? V::load(b[colp + gy * s1 + z * s2]) : A(0);
             }
+            // couplings stored towards a point outside the grid (last column,
+            // row or plane) are never used: taken as zero, as the ghost term
+            // they would multiply is left out by the one-sweep kernel
             f0[r] = FACE ? ldc(S.face[0], S.c[0], z, gy) : S.c[0];
             f1[r] = FACE ? ldc(S.face[1], S.c[1], z, gy) : S.c[1];
             f2c[r] = FACE ? ldc(S.face[2], S.c[2], z, gy) : S.c[2];
+            if (FACE) {  // per-lane selects (col_in is per lane)
+                f0[r] = (col_in && gx == n0 - 1) ? A(0) : f0[r];
+                f1[r] = (col_in && gy == n1 - 1) ? A(0) : f1[r];
+                f2c[r] = (col_in && z == n2 - 1) ? A(0) : f2c[r];
+            }
             dd[r] = DIAG ? ldc(S.diag, S.dconst, z, gy) : S.dconst;
             // binary64: 1/D is formed here (a correctly rounded division, as
             // the stored array holds) instead of being read, 8 bytes less per

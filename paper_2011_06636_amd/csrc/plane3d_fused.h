@@ -249,6 +249,15 @@ __device__ __forceinline__ void plane3d2f_run(const Stencil3<typename V::A> &S,
     A bc[R1], f0c[R1], f1c[R1 + 1], f2c[R1], dc[R1], ic[R1];
     A bp[R1], f0p[R1], f1p[R1 + 1], dp[R1], ip[R1];
     A f2m[R1], f2mm[R1];
+    // couplings stored towards a point outside the grid (last column, row or
+    // plane) are never used by the one-sweep kernel: taken as zero through
+    // the per-lane row masks (rows of f1 without the last grid row, no rows
+    // of f0 in the last column, no rows of f2 in the last plane)
+    const uint32_t not_last_col = (col_in && gx == n0 - 1) ? 0u : ~0u;
+    uint32_t not_last_row = ~0u;
+#pragma unroll
+    for (int i = 0; i < R0; ++i)
+        if (gy0 - 2 + i == n1 - 1) not_last_row &= ~(1u << i);
     {
         const int64_t zm = zoff(z0 - 2), zc = zoff(z0 - 1);
         const uint32_t okm = lane_rows(z0 - 2), okc = lane_rows(z0 - 1);
@@ -258,7 +267,7 @@ __device__ __forceinline__ void plane3d2f_run(const Stencil3<typename V::A> &S,
             u0c[i] = ldv(x, zc, okc, i);
         }
 #pragma unroll
-        for (int j = 0; j < R1; ++j) f2m[j] = ldc(F2, zm, okm, j + 1);
+        for (int j = 0; j < R1; ++j) f2m[j] = ldc(F2, zm, okm, j + 1);  // plane z0 - 2 < n2 - 1
     }
 #pragma unroll
     for (int j = 0; j < R1; ++j) {
@@ -274,8 +283,8 @@ __device__ __forceinline__ void plane3d2f_run(const Stencil3<typename V::A> &S,
 #pragma unroll
         for (int j = 0; j < R1; ++j) {
             bc[j] = ldv(b, zc, okc, j + 1);
-            f0c[j] = ldc(F0, zc, okc, j + 1);
-            f2c[j] = ldc(F2, zc, okc, j + 1);
+            f0c[j] = ldc(F0, zc, okc & not_last_col, j + 1);
+            f2c[j] = ldc(F2, zc, okc & (z == n2 - 1 ? 0u : ~0u), j + 1);
             dc[j] = ldc(DG, zc, okc, j + 1);
             if constexpr (kRecipInPlace)
                 ic[j] = ((okc >> (j + 1)) & 1) ? A(1) / dc[j] : A(0);
@@ -283,7 +292,7 @@ __device__ __forceinline__ void plane3d2f_run(const Stencil3<typename V::A> &S,
                 ic[j] = ldc(DI, zc, okc, j + 1);
         }
 #pragma unroll
-        for (int i = 0; i <= R1; ++i) f1c[i] = ldc(F1, zc, okc, i);
+        for (int i = 0; i <= R1; ++i) f1c[i] = ldc(F1, zc, okc & not_last_row, i);
         // first sweep, plane z
 #pragma unroll
         for (int j = 0; j < R1; ++j) {

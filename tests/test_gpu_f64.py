@@ -307,6 +307,63 @@ def test_3d_two_sweep_face_plans_bit_identical(torch_cuda, orc, n):
     s.close()
 
 
+def _boundary_faces(prob, value):
+    """A copy of prob with the couplings stored towards points outside the
+    grid (face d on the last layer along axis d) set to value."""
+    import copy
+    q = copy.copy(prob)
+    q.faces = [None if f is None else f.copy() for f in prob.faces]
+    for d, f in enumerate(q.faces):
+        if f is None:
+            continue
+        idx = [slice(None)] * 3
+        idx[2 - d] = -1  # arrays are (n2, n1, n0)
+        f[tuple(idx)] = value
+    return q
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_unused_boundary_couplings_are_ignored(torch_cuda, case):
+    # every plan leaves out the couplings towards points outside the grid,
+    # as the one-sweep kernel does: NaN there changes no bit (binary64 sweeps
+    # and binary32 inner sweeps)
+    from paper_2011_06636_amd import abi
+    if case == "2d":
+        prob = workloads.variable_coefficient_2d(131, 70, seed=4, corr_len=4.0)
+    else:
+        prob = workloads.variable_coefficient(29, seed=4, corr_len=3.0)
+    bad, good = _boundary_faces(prob, np.nan), _boundary_faces(prob, 0.0)
+    x0 = np.random.default_rng(12).uniform(-1, 1, prob.shape)
+    levels = (0, 1, 2, 5, 9)
+
+    def run(p, plan):
+        s = _solver(p)
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in levels:
+            s.run_cycle(x, level)
+        out = x.cpu().numpy()
+        s.close()
+        return out
+
+    def run_inner(p, plan):
+        s = _solver(p)
+        assert s.set_plan(*plan, which=1) == 0, plan
+        out = s.solve(tol=1e-300, precision="f32", max_cycles=6)["x"].cpu().numpy()
+        s.close()
+        return out
+
+    ref = run(good, (0, 0, 1, 1))
+    assert np.all(np.isfinite(ref))
+    kinds = (10,) if case == "2d" else (3, 6, 12)
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] in kinds]
+    for plan in plans:
+        assert np.array_equal(run(bad, plan), ref), plan
+    ref_in = run_inner(good, (0, 0, 1, 1))
+    for plan in [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] in kinds]:
+        assert np.array_equal(run_inner(bad, plan), ref_in), plan
+
+
 def test_resume_is_bit_identical(torch_cuda, orc):
     prob = workloads.c2(n=160)
     s = _solver(prob)
