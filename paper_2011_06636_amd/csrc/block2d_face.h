@@ -155,7 +155,15 @@ __device__ __forceinline__ void blockf_run(int64_t n0, int64_t n1,
         const bool in = !EDGE || (((rowbits >> r) & 1) && col_in);
         const bool row_last = EDGE && gy0 + r == n1 - 1;
         const A vx = V::load(x[base]), vb = V::load(b[base]), v0 = f0[base], v1 = f1[base],
-                vd = dg[base], vi = dgi[base];
+                vd = dg[base];
+        // binary64: 1/D formed here (a correctly rounded division, the value
+        // the stored array holds), 8 bytes less per point; below binary64 the
+        // stored reciprocal (rounded from binary64) is read
+        A vi;
+        if constexpr (sizeof(A) == sizeof(double))
+            vi = A(1) / vd;
+        else
+            vi = dgi[base];
         xr[r] = in ? vx : A(0);
         br[r] = in ? vb : A(0);
         fe[r] = in && !col_last ? v0 : A(0);
