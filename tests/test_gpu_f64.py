@@ -307,6 +307,44 @@ def test_3d_two_sweep_face_plans_bit_identical(torch_cuda, orc, n):
     s.close()
 
 
+@pytest.mark.parametrize("n", [(61, 5, 3), (130, 1, 17), (7, 33, 1), (64, 9, 40), (1, 1, 23),
+                               (200, 3), (3, 90)])
+def test_per_face_plans_on_ragged_boxes(torch_cuda, orc, n):
+    # every per-face plan (2D: kind 10; 3D: kinds 3, 6, 12) on boxes with one
+    # tile or less along some axes, single rows, columns and planes, random
+    # face couplings: the bits of one sweep per launch, binary64 and binary32
+    # inner sweeps, and the oracle agrees
+    from paper_2011_06636_amd import abi
+    prob = workloads.random_faces(list(n), seed=sum(n))
+    kinds = (10,) if len(n) == 2 else (3, 6, 12)
+    s = _solver(prob)
+    x0 = np.random.default_rng(13).uniform(-1, 1, prob.shape)
+    levels = (0, 1, 2, 5)
+    results = {}
+    plans = [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants() if v[0] in kinds]
+    for plan in plans:
+        assert s.set_plan(*plan) == 0, plan
+        x = s.to_device(x0)
+        for level in levels:
+            s.run_cycle(x, level)
+        results[plan] = x.cpu().numpy()
+    base = results[(0, 0, 1, 1)]
+    for plan, v in results.items():
+        assert np.array_equal(v, base), plan
+    x_ref = x0.copy()
+    for level in levels:
+        for w in orc.scheme(level):
+            x_ref = orc.sweep(prob, x_ref, w)
+    assert _close(base, x_ref)
+    inner = {}
+    for plan in [(0, 0, 1, 1)] + [v for v in abi.srj_plan_variants(which=1) if v[0] in kinds]:
+        assert s.set_plan(*plan, which=1) == 0, plan
+        inner[plan] = s.solve(tol=1e-300, precision="f32", max_cycles=5)["x"].cpu().numpy()
+    for plan, v in inner.items():
+        assert np.array_equal(v, inner[(0, 0, 1, 1)]), plan
+    s.close()
+
+
 def _boundary_faces(prob, value):
     """A copy of prob with the couplings stored towards points outside the
     grid (face d on the last layer along axis d) set to value."""

@@ -35,10 +35,12 @@ def small_problems():
     vc2 = workloads.variable_coefficient_2d(5, 4, seed=5, corr_len=1.5)
     vc2.b = rng.uniform(-1, 1, vc2.shape)
     out.append(vc2)
+    out.append(workloads.random_faces([4, 3, 2], seed=6))
+    out.append(workloads.random_faces([3, 5], seed=7))
     return out
 
 
-@pytest.mark.parametrize("k", range(7))
+@pytest.mark.parametrize("k", range(9))
 def test_apply_matches_dense(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)
@@ -48,7 +50,7 @@ def test_apply_matches_dense(orc, k):
     np.testing.assert_allclose(y, A @ x.ravel(), rtol=1e-13, atol=1e-13 * np.abs(A).max())
 
 
-@pytest.mark.parametrize("k", range(7))
+@pytest.mark.parametrize("k", range(9))
 def test_sweep_is_weighted_jacobi_eq3(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)
@@ -65,7 +67,7 @@ def test_sweep_is_weighted_jacobi_eq3(orc, k):
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14 * scale)
 
 
-@pytest.mark.parametrize("k", range(7))
+@pytest.mark.parametrize("k", range(9))
 def test_residual_norm_matches_dense(orc, k):
     prob = small_problems()[k]
     A = dense_matrix(prob)

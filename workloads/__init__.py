@@ -274,6 +274,37 @@ def variable_coefficient_2d(n0: int, n1: int, seed: int, corr_len: float = 8.0,
                    name=name or f"varcoef2d_{n0}x{n1}")
 
 
+def random_faces(n: Sequence[int], seed: int, name: str = "") -> Problem:
+    """A symmetric stencil with per-face couplings on any box (2D or 3D):
+    every stored coupling (the ones towards the outside included) U(0.5, 1.5),
+    a coupling to the ghost below the first layer U(0.5, 1.5) per axis, D_p
+    the sum of the 2 ndim couplings of p (strictly diagonally dominant only
+    through the ghost couplings, as a Dirichlet problem), b ~ U(-1, 1).  Drawn
+    in that order: faces, then the low ghost couplings, then b."""
+    ndim, n3 = _dims(n)
+    shape = (n3[2], n3[1], n3[0])
+    rng = np.random.default_rng(seed)
+    faces = [rng.uniform(0.5, 1.5, shape) for _ in range(ndim)]
+    diag = np.zeros(shape)
+    for d in range(ndim):
+        ax = 2 - d  # axis d is numpy axis 2 - d
+        lo = np.empty(shape)
+        idx_first = [slice(None)] * 3
+        idx_first[ax] = slice(0, 1)
+        idx_rest = [slice(None)] * 3
+        idx_rest[ax] = slice(1, None)
+        idx_prev = [slice(None)] * 3
+        idx_prev[ax] = slice(0, -1)
+        lo[tuple(idx_rest)] = faces[d][tuple(idx_prev)]
+        ghost_shape = list(shape)
+        ghost_shape[ax] = 1
+        lo[tuple(idx_first)] = rng.uniform(0.5, 1.5, ghost_shape)
+        diag += faces[d] + lo
+    b = rng.uniform(-1, 1, shape)
+    return Problem(ndim, n3, (0.0, 0.0, 0.0), 0.0, b, faces=faces + [None] * (3 - ndim),
+                   diag=diag, name=name or f"randfaces{ndim}d")
+
+
 def c3(seed: int = 0, n: int = 256) -> Problem:
     return variable_coefficient(n, seed, name=f"c3_varcoef3d_{n}")
 
