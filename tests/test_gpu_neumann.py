@@ -56,11 +56,13 @@ def test_update_stop_matches_reference(torch_cuda, orc, n, rule, seed):
     assert got["sweeps"] <= sum(len(orc.scheme(int(lv))) for lv in got["levels"])
 
 
-@pytest.mark.parametrize("n,seed", [(96, 11), (131, 12)])
-def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed):
+@pytest.mark.parametrize("n,seed,tol", [(96, 11, TOL), (131, 12, TOL), (96, 13, 1e-2),
+                                        (131, 14, 1e-5), (96, 15, 0.5)])
+def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed, tol):
     # one sweep per launch and every fused per-face block plan (several sweep
-    # counts, so the stop falls at different places inside launches) stop at
-    # the same sweep with the same iterate
+    # counts, so the stop falls at different places inside launches; loose
+    # tolerances stop in the first short cycles) stop at the same sweep with
+    # the same iterate
     from paper_2011_06636_amd import abi
     from paper_2011_06636_amd.solver import Solver
     prob = workloads.neumann_laplace(n)
@@ -75,7 +77,7 @@ def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed):
     for plan in plans:
         assert s.set_plan(*plan) == 0, plan
         x = s.to_device(x0)
-        out = s.solve(x, rule="heuristic", tol=TOL, tol_mode="update_inf", max_cycles=100000)
+        out = s.solve(x, rule="heuristic", tol=tol, tol_mode="update_inf", max_cycles=100000)
         results[plan] = (out["status"], out["sweeps"], out["cycles"], out["levels"].copy(),
                          out["r_final"], x.cpu().numpy())
     s.close()
@@ -86,7 +88,7 @@ def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed):
         assert np.array_equal(r[3], base[3]), plan
         assert r[4] == base[4], plan
         assert np.array_equal(r[5], base[5]), plan
-    ref = orc.solve(prob, x0, rule="heuristic", tol=TOL, tol_mode="update_inf", max_cycles=100000)
+    ref = orc.solve(prob, x0, rule="heuristic", tol=tol, tol_mode="update_inf", max_cycles=100000)
     assert base[1] == ref["sweeps"]
     assert np.array_equal(base[5].reshape(-1), ref["x"].reshape(-1))
 
