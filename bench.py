@@ -48,6 +48,13 @@ MEASURED_TRAFFIC_UNFUSED = 104.4e6
 # HBM bytes per launch, taken the same way
 ONE_SWEEP_PLAN = (5, 16, 1, 1)
 MEASURED_TRAFFIC_ONE_SWEEP = 107.0e6
+# VALU issue bound of the default block kernel (plan (8, 8, 10, 8)): its
+# interior sweep loop issues 228 vector instructions for a wave's 16 point
+# updates (read from the kernel's gfx950 assembly), each wave64 instruction
+# occupies a SIMD for 4 cycles, 256 CUs x 4 SIMDs at 2.4 GHz; a block of
+# 128 x 64 points writes 108 x 44 of them, so 1.724 updates per useful one
+VALU_CEILING = {(8, 8, 10, 8): {"instr_per_update": 228 / 16,
+                                "updates_per_written": (128 * 64) / (108 * 44)}}
 
 
 def parse():
@@ -119,6 +126,21 @@ KERNEL_NAMES = {
     7: "k_block2d<StF64, C=1> (cooperative wave blocks, fused sweeps)",
     8: "k_block2d<StF64, C=2> (cooperative wave blocks, two columns per lane)",
 }
+
+
+def valu_issue(plan, npoints, sweeps, launches, avg_launch_s):
+    """The block kernel's useful point updates per second (kernel time only)
+    against its VALU issue ceiling (VALU_CEILING); None for other plans."""
+    c = VALU_CEILING.get(tuple(plan))
+    if c is None or launches == 0:
+        return None
+    raw = 256 * 4 * 64 / (c["instr_per_update"] * 4) * 2.4e9  # updates per second
+    ceiling = raw / c["updates_per_written"]
+    achieved = npoints * sweeps / launches / avg_launch_s
+    return {"ceiling_GLUPS": round(ceiling / 1e9, 1), "achieved_GLUPS": round(achieved / 1e9, 1),
+            "frac": round(achieved / ceiling, 4),
+            "basis": "228 VALU instructions per 16 updates of a wave in the interior sweep loop, "
+                     "4 cycles each, 256 CUs x 4 SIMDs at 2.4 GHz, 1.724 updates per written point"}
 
 
 def one_sweep_rate(s, x, prob, plan, traffic, level=12):
@@ -651,7 +673,9 @@ def main():
                      "copy_ceiling_GBps": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4),
                      "unfused_one_sweep": unfused,
-                     "single_sweep_best": single},
+                     "single_sweep_best": single,
+                     "valu_issue": valu_issue(plan, prob.npoints, prof_sweeps, launches,
+                                              avg_launch_s)},
     }
     s.close()
     del x
