@@ -44,6 +44,9 @@ __device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
 {
     using A = typename V::A;
     for (int k = 0; k < T; ++k) {
+        // the sweep's factor is requested before the barrier, so its load
+        // completes while the wave waits there
+        const A w = wlist[k];
         A *e = edge + ((kbase + k) & 1) * (2 * NW * C * 64);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -58,7 +61,6 @@ __device__ __forceinline__ void block_sweeps(typename V::A (&xr)[HW][C],
             upv[c] = wave > 0 ? e[((NW + wave - 1) * C + c) * 64 + lane] : A(0);
             dnv[c] = wave + 1 < NW ? e[((wave + 1) * C + c) * 64 + lane] : A(0);
         }
-        const A w = wlist[k];
         // products are formed once and moved: c0 u of a column serves the
         // columns on both sides (in the lane, or one lane over by a shift),
         // and c1 u of a row serves the rows on both sides

@@ -61,6 +61,7 @@ __device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
         atomicMax(&st->maxbits[ring][k][stripe * kUpdStride], m);
     };
     for (int k = 0; k < T; ++k) {
+        const A w = wlist[k];  // requested before the barrier (as in block2d.h)
         // edge: [2 buffers][0: first row's x, 1: last row's f1 x][NW][64]
         A *e = edge + (k & 1) * (2 * NW * 64);
         e[wave * 64 + lane] = xr[0];
@@ -71,7 +72,6 @@ __device__ __forceinline__ void blockf_sweeps(typename V::A (&xr)[HW],
         // rows outside the block read zero (they only feed halo rows)
         A pdown = wave > 0 ? e[(NW + wave - 1) * 64 + lane] : A(0);
         const A xup = wave + 1 < NW ? e[(wave + 1) * 64 + lane] : A(0);
-        const A w = wlist[k];
 #pragma unroll
         for (int r = 0; r < HW; ++r) {
             const A xc = xr[r];
