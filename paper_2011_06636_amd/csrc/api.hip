@@ -316,6 +316,9 @@ srj_status srj_destroy(srj_ctx *c)
     refine_free(c);
     (void)hipFree(c->upd);
     (void)hipFree(c->updf);
+    (void)hipFree(c->rs_fixed);
+    (void)hipFree(c->rs_levels);
+    (void)hipFree(c->rs_norms);
     for (void *q : {(void *)c->csr_diag, (void *)c->csr_b, (void *)c->csr_val, (void *)c->csr_len,
                     (void *)c->csr_col})
         (void)hipFree(q);
@@ -930,6 +933,8 @@ srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_r
     if (o->tol_mode == SRJ_TOL_UPDATE_INF) {
         if (o->precision != SRJ_PREC_F64)
             return fail(SRJ_ERR_UNSUPPORTED, "the update test needs precision F64");
+        if (c->resident && resident_fits(c->P))
+            return resident_solve(c, x, o, res, levels_out, norms_out);
         return solve_update_inf(c, x, o, res, levels_out, norms_out);
     }
     if (o->precision != SRJ_PREC_F64) return refine_solve(c, x, o, res, levels_out, norms_out);

@@ -195,6 +195,12 @@ struct srj_ctx {
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     srj::UpdState *upd = nullptr;          // per-sweep update test (lazily allocated)
     srj::UpdFState *updf = nullptr;        // the same for fused sweeps (lazily allocated)
+    // one-workgroup solves: result record and level/offset tables (fixed
+    // size), level and norm histories (grown to the largest max_cycles seen)
+    void *rs_fixed = nullptr;
+    int32_t *rs_levels = nullptr;
+    double *rs_norms = nullptr;
+    int64_t rs_cap = 0;
     // library copies of a general sparse matrix (srj_setup_csr)
     double *csr_diag = nullptr, *csr_b = nullptr, *csr_val = nullptr;
     int32_t *csr_len = nullptr, *csr_col = nullptr;

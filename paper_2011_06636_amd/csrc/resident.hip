@@ -40,6 +40,32 @@ struct ResidentArgs {
     double tol, r0_given;
 };
 
+// Largest of the threads' values (bit patterns of non-negative doubles, which
+// order like the values; a NaN orders above everything), broadcast.
+__device__ unsigned long long group_max_bits(unsigned long long v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = __longlong_as_double((long long)v);
+    __syncthreads();
+    const int nw = blockDim.x / 64;
+    if (threadIdx.x == 0) {
+        unsigned long long t = (unsigned long long)__double_as_longlong(red[0]);
+        for (int i = 1; i < nw; ++i) {
+            const unsigned long long u = (unsigned long long)__double_as_longlong(red[i]);
+            t = u > t ? u : t;
+        }
+        red[kThreads / 64] = __longlong_as_double((long long)t);
+    }
+    __syncthreads();
+    return (unsigned long long)__double_as_longlong(red[kThreads / 64]);
+}
+
 // Fixed-order sum over the workgroup, broadcast to every thread.
 __device__ double group_sum(double v, double *red)
 {
@@ -98,13 +124,16 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
     const double norm0 = norm_of(cur);
     const double r0 = a.r0_given > 0.0 ? a.r0_given : norm0;
     const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
+    // the update test (section 4.2.2, Eq. (25)): stop at the first sweep whose
+    // largest |x' - x| is below tol; the selector still runs on cycle-end norms
+    const bool upd = a.tol_mode == SRJ_TOL_UPDATE_INF;
     if (threadIdx.x == 0) norms_hist[0] = norm0;
     int status = SRJ_ERR_NOT_CONVERGED, cycles = 0, level = a.start_level, last_level = a.start_level;
     int64_t sweeps = 0;
     double prev = norm0, last = norm0, margin = INFINITY;
     if (!isfinite(norm0)) {
         status = SRJ_ERR_NONFINITE;
-    } else if (norm0 == 0.0 || norm0 < target) {
+    } else if (norm0 == 0.0 || (!upd && norm0 < target)) {
         status = SRJ_OK;
     } else {
         for (int cycle = 0; cycle < a.max_cycles; ++cycle) {
@@ -113,23 +142,37 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
             if (sweeps + M > a.max_sweeps) break;
             const double *w = omega + offsets[lv];
             double wnext = w[0];
+            int done = M;          // sweeps of this cycle that count
+            bool stopped = false;  // the update test held after sweep done - 1
             for (int j = 0; j < M; ++j) {
                 const double wj = wnext;
                 if (j + 1 < M) wnext = w[j + 1];  // in flight during this sweep
+                unsigned long long dmax = 0ull;
 #pragma unroll
                 for (int k = 0; k < kPPT; ++k) {
                     if (pi[k] < 0) continue;
                     const double s = row_s(P, cur, pi[k], c0[k], c1[k], c2[k]);
                     const double r = bv[k] - s;
                     const double t = dinv[k] * r;
-                    nxt[pi[k]] = cur[pi[k]] + wj * t;
+                    const double xn = cur[pi[k]] + wj * t;
+                    nxt[pi[k]] = xn;
+                    if (upd) {
+                        const unsigned long long d =
+                            (unsigned long long)__double_as_longlong(fabs(xn - cur[pi[k]]));
+                        dmax = d > dmax ? d : dmax;
+                    }
                 }
                 __syncthreads();
                 double *tmp = cur;
                 cur = nxt;
                 nxt = tmp;
+                if (upd && __longlong_as_double((long long)group_max_bits(dmax, red)) < a.tol) {
+                    done = j + 1;  // every thread takes the same decision
+                    stopped = true;
+                    break;
+                }
             }
-            sweeps += M;
+            sweeps += done;
             const double norm = norm_of(cur);
             cycles = cycle + 1;
             last = norm;
@@ -142,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
                 status = SRJ_ERR_NONFINITE;
                 break;
             }
-            if (norm < target) {
+            if (upd ? stopped : norm < target) {
                 status = SRJ_OK;
                 break;
             }
@@ -194,21 +237,42 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
     a.tol = o->tol;
     a.r0_given = o->r0;
     const int64_t N = c->npoints;
-    int32_t *lh = nullptr;
-    double *nh = nullptr;
-    ResidentOut *dout = nullptr;
-    int32_t *lm = nullptr;
     std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
     for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
+    // device buffers kept by the context from one solve to the next: the
+    // result record, the level sizes and offsets (fixed size), the histories
+    constexpr size_t kOutBytes = 256, kLmBytes = 128, kOffsBytes = 128;
+    static_assert(sizeof(ResidentOut) <= kOutBytes, "result record");
+    static_assert(sizeof(int32_t) * SRJ_NUM_LEVELS <= kLmBytes, "level sizes");
+    static_assert(sizeof(int32_t) * (SRJ_NUM_LEVELS + 1) <= kOffsBytes, "level offsets");
+    if (c->offsets.size() > (size_t)SRJ_NUM_LEVELS + 1)
+        return fail(SRJ_ERR_INVALID, "scheme family larger than the level table");
+    if (!c->rs_fixed && hipMalloc(&c->rs_fixed, kOutBytes + kLmBytes + kOffsBytes) != hipSuccess) {
+        c->rs_fixed = nullptr;
+        return fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
+    }
+    if (c->rs_cap < o->max_cycles) {
+        (void)hipFree(c->rs_levels);
+        (void)hipFree(c->rs_norms);
+        c->rs_levels = nullptr;
+        c->rs_norms = nullptr;
+        c->rs_cap = 0;
+        if (hipMalloc(&c->rs_levels, sizeof(int32_t) * (size_t)o->max_cycles) != hipSuccess ||
+            hipMalloc(&c->rs_norms, sizeof(double) * ((size_t)o->max_cycles + 1)) != hipSuccess) {
+            (void)hipFree(c->rs_levels);
+            c->rs_levels = nullptr;
+            c->rs_norms = nullptr;
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
+        }
+        c->rs_cap = o->max_cycles;
+    }
+    int32_t *lh = c->rs_levels;
+    double *nh = c->rs_norms;
+    char *fixed = static_cast<char *>(c->rs_fixed);
+    ResidentOut *dout = reinterpret_cast<ResidentOut *>(fixed);
+    int32_t *lm = reinterpret_cast<int32_t *>(fixed + kOutBytes);
+    int32_t *offs = reinterpret_cast<int32_t *>(fixed + kOutBytes + kLmBytes);
     srj_status st = SRJ_OK;
-    if (hipMalloc(&lh, sizeof(int32_t) * (size_t)o->max_cycles) != hipSuccess ||
-        hipMalloc(&nh, sizeof(double) * ((size_t)o->max_cycles + 1)) != hipSuccess ||
-        hipMalloc(&dout, sizeof(ResidentOut)) != hipSuccess ||
-        hipMalloc(&lm, sizeof(int32_t) * SRJ_NUM_LEVELS) != hipSuccess)
-        st = fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
-    int32_t *offs = nullptr;
-    if (st == SRJ_OK && hipMalloc(&offs, sizeof(int32_t) * c->offsets.size()) != hipSuccess)
-        st = fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
     ResidentOut h{};
     if (st == SRJ_OK) {
         hipError_t e = hipMemcpyAsync(lm, lmh.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
@@ -245,11 +309,6 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
         }
         if (e != hipSuccess) st = fail(SRJ_ERR_HIP, std::string("resident solve: ") + hipGetErrorString(e));
     }
-    (void)hipFree(lh);
-    (void)hipFree(nh);
-    (void)hipFree(dout);
-    (void)hipFree(lm);
-    (void)hipFree(offs);
     if (st != SRJ_OK) return st;
     res->converged = h.converged;
     res->cycles = h.cycles;

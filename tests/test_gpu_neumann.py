@@ -93,6 +93,35 @@ def test_update_stop_same_for_every_plan(torch_cuda, orc, n, seed, tol):
     assert np.array_equal(base[5].reshape(-1), ref["x"].reshape(-1))
 
 
+@pytest.mark.parametrize("n,rule,tol", [(17, "heuristic", TOL), (40, "increasing", TOL),
+                                        (63, "heuristic", TOL), (63, "heuristic", 1e-3),
+                                        (30, "heuristic", 0.5)])
+def test_resident_update_stop_matches_multi_kernel(torch_cuda, orc, n, rule, tol):
+    # grids of at most 4000 points run the update test inside the one-workgroup
+    # solve: the same stop sweep, levels and iterate as the multi-kernel path
+    # and the CPU reference (norms differ only in summation order)
+    from paper_2011_06636_amd.solver import Solver
+    prob = workloads.neumann_laplace(n)
+    x0 = workloads.random_start(prob, n)
+    s = Solver(prob)
+    runs = {}
+    for resident in (True, False):
+        assert s.set_resident(resident) == 0
+        x = s.to_device(x0)
+        out = s.solve(x, rule=rule, tol=tol, tol_mode="update_inf", max_cycles=100000)
+        runs[resident] = (out, x.cpu().numpy())
+    s.close()
+    (a, xa), (b, xb) = runs[True], runs[False]
+    assert a["status"] == b["status"] == "ok"
+    assert a["sweeps"] == b["sweeps"] and a["cycles"] == b["cycles"]
+    assert np.array_equal(a["levels"], b["levels"])
+    assert np.array_equal(xa, xb)
+    assert a["r_final"] == pytest.approx(b["r_final"], rel=1e-12)
+    ref = orc.solve(prob, x0, rule=rule, tol=tol, tol_mode="update_inf", max_cycles=100000)
+    assert a["sweeps"] == ref["sweeps"]
+    assert np.array_equal(xa.reshape(-1), ref["x"].reshape(-1))
+
+
 def test_paper_grid_256(torch_cuda, orc):
     for rule in ("heuristic", "increasing"):
         got, gx, ref = _both(orc, 256, rule, 7, max_cycles=100000)
