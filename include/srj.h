@@ -91,10 +91,10 @@ typedef enum {
  * of the 2D Laplace test with Neumann boundaries (section 4.2.2, Eq. (25));
  * the selector still runs on cycle-end residual ratios.  UPDATE_INF needs
  * precision SRJ_PREC_F64; the update's maximum is reduced in the sweep
- * kernels (one sweep per launch, or the fused per-face blocks of plan kind
- * 10, where the stop sweep's iterate is formed again from its launch's
- * input); the solve stops at the exact sweep, with the same iterate for
- * every plan. */
+ * kernels (one sweep per launch, the fused per-face blocks of plan kind 10,
+ * where the stop sweep's iterate is formed again from its launch's input, or
+ * the one-workgroup solve of grids of at most 4000 points); the solve stops
+ * at the exact sweep, with the same iterate for every plan. */
 typedef enum { SRJ_TOL_RELATIVE = 0, SRJ_TOL_ABSOLUTE = 1, SRJ_TOL_UPDATE_INF = 2 } srj_tol_mode;
 
 #define SRJ_NUM_LEVELS 25
