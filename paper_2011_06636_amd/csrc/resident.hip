@@ -84,6 +84,9 @@ __device__ double group_sum(double v, double *red)
     return red[kThreads / 64];
 }
 
+// UPD: the update stopping test (a.tol_mode == SRJ_TOL_UPDATE_INF); a
+// template argument so that the residual-test kernel carries none of it.
+template <bool UPD>
 __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__restrict__ x,
                                                        const double *__restrict__ omega,
                                                        const int32_t *__restrict__ offsets,
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
     const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
     // the update test (section 4.2.2, Eq. (25)): stop at the first sweep whose
     // largest |x' - x| is below tol; the selector still runs on cycle-end norms
-    const bool upd = a.tol_mode == SRJ_TOL_UPDATE_INF;
+    constexpr bool upd = UPD;
     if (threadIdx.x == 0) norms_hist[0] = norm0;
     int status = SRJ_ERR_NOT_CONVERGED, cycles = 0, level = a.start_level, last_level = a.start_level;
     int64_t sweeps = 0;
@@ -286,8 +289,12 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
             // one point per thread up to 1024 points (latency hiding across
             // waves), then up to kPPT points per thread
             const int threads = (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
-            hipLaunchKernelGGL(k_resident, dim3(1), dim3(threads), shmem, c->stream, c->P, x,
-                               c->omega_dev, offs, lm, a, lh, nh, dout);
+            if (a.tol_mode == SRJ_TOL_UPDATE_INF)
+                hipLaunchKernelGGL(k_resident<true>, dim3(1), dim3(threads), shmem, c->stream, c->P,
+                                   x, c->omega_dev, offs, lm, a, lh, nh, dout);
+            else
+                hipLaunchKernelGGL(k_resident<false>, dim3(1), dim3(threads), shmem, c->stream,
+                                   c->P, x, c->omega_dev, offs, lm, a, lh, nh, dout);
             e = hipGetLastError();
         }
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
