@@ -201,6 +201,24 @@ srj_status srj_run_cycle(srj_ctx *ctx, double *x, int32_t level, double *resnorm
 /* L2 norm of b - A x for the device array x (host result, blocking). */
 srj_status srj_residual_norm(srj_ctx *ctx, const double *x, double *norm_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the L2 norm
+ * of b - A x, as srj_residual_norm computes it, without a context and
+ * without any allocation.  *p is a stencil problem as for srj_setup (its
+ * device arrays are only read during the call's kernels); x (n0*n1*n2
+ * binary64) and norm_out (one binary64) are DEVICE pointers of the current
+ * device.  The norm is written to *norm_out on the device by work enqueued on
+ * hip_stream (a hipStream_t, NULL: null stream); the call does not
+ * synchronise, so *norm_out is valid once that stream has reached it.
+ * Partial sums go to a fixed 2 MiB device array that each GPU holds from the
+ * first call until the process ends: grids needing more than 2^18 residual
+ * blocks (ceil(n0 / 256) * n1 * n2) return SRJ_ERR_UNSUPPORTED.  Every call
+ * on one GPU shares that array, so calls whose work overlaps on one GPU (two
+ * streams, two threads) race: order them on one stream.  Validation as
+ * srj_setup, plus x and norm_out (SRJ_ERR_INVALID). */
+srj_status srj_residual_norm_noalloc(const srj_problem *p, const double *x, void *hip_stream,
+                                     double *norm_out);
+
 /* Solve A x = b from the initial guess in x (device, in/out) with cycles
  * whose schemes the rule picks (Algorithm 1 by default), until the stopping
  * test of opts->tol_mode holds (see srj_tol_mode) or a cap is reached; with

@@ -31,7 +31,7 @@ MAX_M = 2362
 # Public entry points of include/srj.h (checked by the tests).
 EXPORTS = [
     "srj_default_opts", "srj_scheme", "srj_setup", "srj_setup_csr", "srj_run_cycle",
-    "srj_residual_norm",
+    "srj_residual_norm", "srj_residual_norm_noalloc",
     "srj_solve", "srj_destroy", "srj_set_plan", "srj_get_plan", "srj_plan_variants",
     "srj_autotune", "srj_set_resident",
     "srj_set_profiling",
@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
         "srj_setup": (i32, [P(SrjProblem), vp, P(vp)]),
         "srj_run_cycle": (i32, [vp, vp, i32, P(f64)]),
         "srj_residual_norm": (i32, [vp, vp, P(f64)]),
+        "srj_residual_norm_noalloc": (i32, [P(SrjProblem), vp, vp, vp]),
         "srj_solve": (i32, [vp, vp, P(SrjSolveOpts), P(SrjSolveResult), P(i32), P(f64)]),
         "srj_destroy": (i32, [vp]),
         "srj_set_plan": (i32, [vp, i32, i32, i32, i32, i32]),
@@ -205,6 +206,13 @@ def srj_residual_norm(ctx, x_ptr: int) -> float:
     check(load().srj_residual_norm(ctx, ctypes.c_void_p(x_ptr), ctypes.byref(nrm)),
           "srj_residual_norm")
     return nrm.value
+
+
+def srj_residual_norm_noalloc(prob: SrjProblem, x_ptr: int, stream: int, norm_ptr: int) -> None:
+    """Enqueues ||b - A x|| into the device double at norm_ptr (no allocation, no sync)."""
+    check(load().srj_residual_norm_noalloc(ctypes.byref(prob), ctypes.c_void_p(x_ptr),
+                                           ctypes.c_void_p(stream), ctypes.c_void_p(norm_ptr)),
+          "srj_residual_norm_noalloc")
 
 
 def srj_solve(ctx, x_ptr: int, opts: SrjSolveOpts, levels=None, norms=None):

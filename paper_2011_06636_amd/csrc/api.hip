@@ -57,9 +57,7 @@ srj_status check_device_array(const void *p, size_t bytes, int dev, const char *
 
 }  // namespace srj
 
-using namespace srj;
-
-namespace {
+namespace srj {
 
 srj_status validate_problem(const srj_problem *p)
 {
@@ -79,6 +77,39 @@ srj_status validate_problem(const srj_problem *p)
     if (!p->diag && !isfinite(p->dconst)) return fail(SRJ_ERR_INVALID, "dconst must be finite");
     return SRJ_OK;
 }
+
+srj_status check_problem_arrays(const srj_problem *p, int dev)
+{
+    const size_t nb = sizeof(double) * (size_t)(p->n[0] * p->n[1] * p->n[2]);
+    srj_status st = check_device_array(p->b, nb, dev, "b");
+    if (st == SRJ_OK && p->diag) st = check_device_array(p->diag, nb, dev, "diag");
+    for (int d = 0; st == SRJ_OK && d < p->ndim; ++d)
+        if (p->face[d]) st = check_device_array(p->face[d], nb, dev, "face[d]");
+    return st;
+}
+
+void fill_dev_problem(const srj_problem *p, DevProblem &P)
+{
+    P = DevProblem{};
+    P.ndim = p->ndim;
+    P.n0 = p->n[0];
+    P.n1 = p->n[1];
+    P.n2 = p->n[2];
+    for (int d = 0; d < 3; ++d) {
+        P.c[d] = d < p->ndim ? p->cconst[d] : 0.0;
+        P.face[d] = d < p->ndim ? p->face[d] : nullptr;
+    }
+    P.dconst = p->diag ? 0.0 : p->dconst;
+    P.dinvconst = p->diag ? 0.0 : 1.0 / p->dconst;
+    P.diag = p->diag;
+    P.b = p->b;
+}
+
+}  // namespace srj
+
+using namespace srj;
+
+namespace {
 
 srj_status validate_opts(const srj_solve_opts *o)
 {
@@ -386,31 +417,13 @@ srj_status srj_setup(const srj_problem *p, void *hip_stream, srj_ctx **out)
     if (st != SRJ_OK) return st;
     int dev = 0;
     SRJ_HIP_CHECK(hipGetDevice(&dev));
-    {
-        const size_t nb = sizeof(double) * (size_t)(p->n[0] * p->n[1] * p->n[2]);
-        if ((st = check_device_array(p->b, nb, dev, "b")) != SRJ_OK) return st;
-        if (p->diag && (st = check_device_array(p->diag, nb, dev, "diag")) != SRJ_OK) return st;
-        for (int d = 0; d < p->ndim; ++d)
-            if (p->face[d] && (st = check_device_array(p->face[d], nb, dev, "face[d]")) != SRJ_OK)
-                return st;
-    }
+    if ((st = check_problem_arrays(p, dev)) != SRJ_OK) return st;
 
     srj_ctx *c = new srj_ctx();
     c->device = dev;
     c->stream = static_cast<hipStream_t>(hip_stream);
     DevProblem &P = c->P;
-    P.ndim = p->ndim;
-    P.n0 = p->n[0];
-    P.n1 = p->n[1];
-    P.n2 = p->n[2];
-    for (int d = 0; d < 3; ++d) {
-        P.c[d] = d < p->ndim ? p->cconst[d] : 0.0;
-        P.face[d] = d < p->ndim ? p->face[d] : nullptr;
-    }
-    P.dconst = p->diag ? 0.0 : p->dconst;
-    P.dinvconst = p->diag ? 0.0 : 1.0 / p->dconst;
-    P.diag = p->diag;
-    P.b = p->b;
+    fill_dev_problem(p, P);
     c->npoints = P.n0 * P.n1 * P.n2;
     const size_t bytes = sizeof(double) * (size_t)c->npoints;
 

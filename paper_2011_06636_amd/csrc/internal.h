@@ -153,10 +153,21 @@ bool fused_supported(const DevProblem &P, const SweepPlan &plan);
 // Lists the fused variants as (kind, rows, halo, occ); returns how many exist.
 int plan_variants(int32_t *out, int cap);
 
+// srj_problem checks (api.hip): the description (SRJ_ERR_INVALID with a
+// message), its device arrays on device dev, and its device view (dinv unset).
+srj_status validate_problem(const srj_problem *p);
+srj_status check_problem_arrays(const srj_problem *p, int dev);
+void fill_dev_problem(const srj_problem *p, DevProblem &P);
+
 // Sum of (b - A x)^2 into scratch.sum (device); blocks needed for scratch sizing.
 int64_t residual_blocks(const DevProblem &P);
 hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
                                  hipStream_t s);
+// The same residual with its L2 norm (square root of the fixed-order sum)
+// written to norm_out (device); partials holds at least residual_blocks(P)
+// values.  Stencil problems only.
+hipError_t launch_residual_norm_into(const DevProblem &P, const double *x, double *partials,
+                                     int64_t capacity, double *norm_out, hipStream_t s);
 // Folds rs.partials[0..nblocks) into rs.sum in a fixed order.
 hipError_t launch_fold(ReduceScratch &rs, int64_t nblocks, hipStream_t s);
 // Block-level fixed-order sums used by every reduction kernel.

@@ -91,7 +91,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_ell(DevProblem P, const dou
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// One block: thread i sums partials i, i + 1024, ... in order, then a fixed tree.
+// One block: thread i sums partials i, i + 1024, ... in order, then a fixed
+// tree; ROOT writes the square root of the sum instead of the sum.
+template <bool ROOT>
 __global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ partials, int64_t n,
                                                  double *__restrict__ out)
 {
@@ -99,7 +101,19 @@ __global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ part
     double v = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += kFinal) v += partials[i];
     const double t = block_sum<kFinal / 64>(v, lds);
-    if (threadIdx.x == 0) *out = t;
+    if (threadIdx.x == 0) *out = ROOT ? sqrt(t) : t;
+}
+
+template <int ND>
+void launch_stencil_residual(const DevProblem &P, const double *x, double *partials, dim3 grid,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual_sumsq<ND>, grid, dim3(kBlock), 0, s, P, x, partials);
+}
+
+dim3 residual_grid(const DevProblem &P)
+{
+    return dim3((unsigned)((P.n0 + kBlock - 1) / kBlock), (unsigned)P.n1, (unsigned)P.n2);
 }
 
 }  // namespace
@@ -107,7 +121,7 @@ __global__ __launch_bounds__(kFinal) void k_fold(const double *__restrict__ part
 hipError_t launch_fold(ReduceScratch &rs, int64_t nblocks, hipStream_t s)
 {
     if (nblocks > rs.capacity) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFinal), 0, s, rs.partials, nblocks, rs.sum);
+    hipLaunchKernelGGL(k_fold<false>, dim3(1), dim3(kFinal), 0, s, rs.partials, nblocks, rs.sum);
     return hipGetLastError();
 }
 
@@ -119,21 +133,38 @@ int64_t residual_blocks(const DevProblem &P)
 hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
                                  hipStream_t s)
 {
-    const dim3 grid((unsigned)((P.n0 + kBlock - 1) / kBlock), (unsigned)P.n1, (unsigned)P.n2);
+    const dim3 grid = residual_grid(P);
     const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
     if (nb > rs.capacity) return hipErrorInvalidValue;
     if (P.ell_len) {
         hipLaunchKernelGGL(k_residual_ell, grid, dim3(kBlock), 0, s, P, x, rs.partials);
     } else {
     switch (P.ndim) {
-    case 1: hipLaunchKernelGGL(k_residual_sumsq<1>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
-    case 2: hipLaunchKernelGGL(k_residual_sumsq<2>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
-    default: hipLaunchKernelGGL(k_residual_sumsq<3>, grid, dim3(kBlock), 0, s, P, x, rs.partials); break;
+    case 1: launch_stencil_residual<1>(P, x, rs.partials, grid, s); break;
+    case 2: launch_stencil_residual<2>(P, x, rs.partials, grid, s); break;
+    default: launch_stencil_residual<3>(P, x, rs.partials, grid, s); break;
     }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFinal), 0, s, rs.partials, nb, rs.sum);
+    hipLaunchKernelGGL(k_fold<false>, dim3(1), dim3(kFinal), 0, s, rs.partials, nb, rs.sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_norm_into(const DevProblem &P, const double *x, double *partials,
+                                     int64_t capacity, double *norm_out, hipStream_t s)
+{
+    const dim3 grid = residual_grid(P);
+    const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
+    if (nb > capacity || P.ell_len) return hipErrorInvalidValue;
+    switch (P.ndim) {
+    case 1: launch_stencil_residual<1>(P, x, partials, grid, s); break;
+    case 2: launch_stencil_residual<2>(P, x, partials, grid, s); break;
+    default: launch_stencil_residual<3>(P, x, partials, grid, s); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fold<true>, dim3(1), dim3(kFinal), 0, s, partials, nb, norm_out);
     return hipGetLastError();
 }
 
