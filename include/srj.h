@@ -440,6 +440,18 @@ srj_status srj_batch_autotune(srj_batch *batch, int32_t precision, int32_t sweep
 
 srj_status srj_batch_destroy(srj_batch *batch);
 
+/* Measurement aid, not a step of the method: one launch of a streaming
+ * kernel of known traffic on hip_stream (no synchronisation), the ceiling
+ * that sweep kernels' byte rates are quoted against and the reference
+ * dispatch for hardware byte counters.  kind 0: out[i] = a[i] (8 B read and
+ * 8 B written per value); kind 1: out[i] = a[i] + b[i] (16 B read, 8 B
+ * written: the mix of a one-sweep launch; b unused for kind 0).  a, b, out:
+ * DEVICE arrays of n binary64 values, 16-byte aligned, of the current device.
+ * SRJ_ERR_INVALID for another kind, n odd, n < 2 or n > 2^36, or an array
+ * that is not device memory. */
+srj_status srj_stream_probe(int32_t kind, const double *a, const double *b, double *out, int64_t n,
+                            void *hip_stream);
+
 const char *srj_last_error(void);
 
 #ifdef __cplusplus

@@ -94,6 +94,8 @@ def load() -> ctypes.CDLL:
         lib.srjo_round_bf16.restype = ctypes.c_float
         lib.srjo_round_bf16.argtypes = [ctypes.c_float]
         lib.srjo_num_threads.restype = ctypes.c_int32
+        lib.srjo_set_num_threads.argtypes = [ctypes.c_int32]
+        lib.srjo_set_num_threads.restype = None
         lib.srjo_collect.argtypes = [P(_Problem), ctypes.c_int32, ctypes.c_int32,
                                      P(ctypes.c_double), ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_void_p, P(ctypes.c_int32)]
@@ -230,6 +232,11 @@ def round_bf16(v: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(load().srjo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not depend on it)."""
+    load().srjo_set_num_threads(int(n))
 
 
 # Record layout of srjo_sample (section 3 tuples, one per branch).

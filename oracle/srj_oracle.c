@@ -60,6 +60,17 @@ int32_t srjo_num_threads(void)
 #endif
 }
 
+/* Thread count of later parallel loops (timing only: the sums that the
+ * results depend on are sequential, so results do not depend on it). */
+void srjo_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
+
 /* Eq. (17): omega_j = (l* + 1) / (2 (l* - x_j)), j = 0..M-1, where
  * x_j = cos((2j+1) pi / (2M)) are the roots of the Chebyshev polynomial T_M
  * and l* is the real root > 1 of T_M(l*) = 3, i.e. cosh(arccosh(3) / M)

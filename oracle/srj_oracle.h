@@ -124,6 +124,7 @@ void srjo_collect(const srjo_problem *p, int32_t trials, int32_t max_steps, cons
 float srjo_round_f16(float v);
 float srjo_round_bf16(float v);
 int32_t srjo_num_threads(void);
+void srjo_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,7 @@ EXPORTS = [
     "srj_batch_set_plan3d", "srj_batch_get_plan3d",
     "srj_batch_autotune",
     "srj_batch_solve", "srj_batch_destroy", "srj_collect", "srj_cluster_samples",
-    "srj_fit_rule", "srj_set_scheme_family", "srj_last_error",
+    "srj_fit_rule", "srj_set_scheme_family", "srj_last_error", "srj_stream_probe",
 ]
 
 SRJ_ACTION_NONE = 2
@@ -139,6 +139,7 @@ def load() -> ctypes.CDLL:
         "srj_cluster_samples": (i32, [vp, ctypes.c_int64, i32, f64, vp, i32, P(i32)]),
         "srj_fit_rule": (i32, [vp, i32, P(f64), P(f64), P(i32), P(i32)]),
         "srj_last_error": (ctypes.c_char_p, []),
+        "srj_stream_probe": (i32, [i32, vp, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -213,6 +214,13 @@ def srj_residual_norm_noalloc(prob: SrjProblem, x_ptr: int, stream: int, norm_pt
     check(load().srj_residual_norm_noalloc(ctypes.byref(prob), ctypes.c_void_p(x_ptr),
                                            ctypes.c_void_p(stream), ctypes.c_void_p(norm_ptr)),
           "srj_residual_norm_noalloc")
+
+
+def srj_stream_probe(kind: int, a_ptr: int, b_ptr, out_ptr: int, n: int, stream: int) -> None:
+    """One streaming launch (0: copy, 1: a + b) of n binary64 values on `stream`."""
+    check(load().srj_stream_probe(kind, ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr),
+                                  ctypes.c_void_p(out_ptr), n, ctypes.c_void_p(stream)),
+          "srj_stream_probe")
 
 
 def srj_solve(ctx, x_ptr: int, opts: SrjSolveOpts, levels=None, norms=None):
