@@ -23,7 +23,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "srj_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SRJ_ORACLE_LIB selects another build of the same source (the sanitizer
+# build); by default the in-tree liboracle.so
+_LIB = os.environ.get("SRJ_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 RULES = {"heuristic": 0, "increasing": 1, "fixed": 2, "jacobi": 3}
 TOL_MODES = {"relative": 0, "absolute": 1, "update_inf": 2}

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsrj.so")
+# SRJ_LIB_PATH selects another build of the same library (the host-sanitizer
+# build of sanitize_build.py); by default the in-tree libsrj.so
+LIB_PATH = os.environ.get("SRJ_LIB_PATH") or os.path.join(HERE, "libsrj.so")
 
 SRJ_OK = 0
 SRJ_ERR_INVALID = 1

@@ -1,11 +1,11 @@
 """GPU parity of the binary64 path against the CPU oracle (through the C ABI).
 
-Bar: the scheme chosen at every cycle is identical, iterates agree within a
-relative 1e-12 (the kernels evaluate the oracle's per-point expression in the
-same order with no fused multiply-add, so they are expected to be bit
-identical; the tests also record that), and every kernel plan (one sweep per
+Bar: the scheme chosen at every cycle is identical and iterates are bit
+identical to the oracle's (the kernels evaluate the oracle's per-point
+expression in the same order with no fused multiply-add; this is stricter
+than the stated 1e-12 relative bar), and every kernel plan (one sweep per
 launch, or T fused sweeps in register tiles of several shapes) gives the same
-bits.  Sizes span several tiles with ragged tails; the full 2048 x 2048
+bits.  Residual norms are sums in a different order and agree to 1e-13.  Sizes span several tiles with ragged tails; the full 2048 x 2048
 benchmark grid is checked on its first cycles against the oracle and on its
 level sequence against the closed-form spectral model.
 """
@@ -33,10 +33,10 @@ def _solver(prob):
 
 
 def _close(got, ref):
+    """Bit identity (which implies the 1e-12 relative bar RTOL)."""
     got = np.asarray(got).reshape(-1)
     ref = np.asarray(ref).reshape(-1)
-    scale = np.max(np.abs(ref)) if ref.size else 1.0
-    return np.max(np.abs(got - ref)) <= RTOL * max(scale, 1e-300)
+    return got.shape == ref.shape and np.array_equal(got, ref)
 
 
 CYCLE_CASES = [
