@@ -23,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "srj_oracle.c")
+_SRC_MG = os.path.join(_HERE, "srj_mg.c")
 # SRJ_ORACLE_LIB selects another build of the same source (the sanitizer
 # build); by default the in-tree liboracle.so
 _LIB = os.environ.get("SRJ_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
@@ -38,7 +39,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, _SRC_MG, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
         os.replace(tmp, _LIB)
     return _LIB
@@ -98,6 +99,13 @@ def load() -> ctypes.CDLL:
         lib.srjo_num_threads.restype = ctypes.c_int32
         lib.srjo_set_num_threads.argtypes = [ctypes.c_int32]
         lib.srjo_set_num_threads.restype = None
+        lib.srjo_mg_hierarchy.restype = ctypes.c_int32
+        lib.srjo_mg_hierarchy.argtypes = [P(_Problem), ctypes.c_int32, P(ctypes.c_int64)]
+        lib.srjo_restrict_residual.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double)]
+        lib.srjo_prolong_add.argtypes = [P(_Problem), P(ctypes.c_double), P(ctypes.c_double)]
+        lib.srjo_mg_solve.restype = ctypes.c_int32
+        lib.srjo_mg_solve.argtypes = [P(_Problem), P(ctypes.c_double), P(_MgOpts), P(_MgResult),
+                                      P(ctypes.c_int32), P(ctypes.c_double)]
         lib.srjo_collect.argtypes = [P(_Problem), ctypes.c_int32, ctypes.c_int32,
                                      P(ctypes.c_double), ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_void_p, P(ctypes.c_int32)]
@@ -218,6 +226,77 @@ def solve(prob, x0: Optional[np.ndarray] = None, *, rule: str = "heuristic",
         "r0": float(r.r0), "r_final": float(r.r_final), "min_margin": float(r.min_margin),
         "levels": levels[:r.cycles].copy(), "norms": norms[:r.cycles + 1].copy(),
     }
+
+
+class _MgOpts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("start_level", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("pre", ctypes.c_int32), ("post", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("coarse_tol", ctypes.c_double),
+                ("coarse_max_cycles", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int32)]
+
+
+class _MgResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("vcycles", ctypes.c_int32), ("final_level", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("sweeps", ctypes.c_int64),
+                ("coarse_sweeps", ctypes.c_int64), ("work", ctypes.c_double),
+                ("r0", ctypes.c_double), ("r_final", ctypes.c_double)]
+
+
+def mg_hierarchy(prob, max_levels: int = 32) -> list:
+    """Grid sizes of the multigrid levels (finest first)."""
+    cp, keep = _cproblem(prob)
+    dims = np.zeros(3 * 32, dtype=np.int64)
+    L = load().srjo_mg_hierarchy(ctypes.byref(cp), min(max_levels, 32),
+                                 dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(L)]
+
+
+def coarse_shape(prob) -> tuple:
+    """NumPy shape (n2, n1, n0) of the next coarser grid."""
+    m = [(int(prob.n[d]) - 1) // 2 if d < prob.ndim else 1 for d in range(3)]
+    return (m[2], m[1], m[0])
+
+
+def restrict_residual(prob, x: np.ndarray) -> np.ndarray:
+    """R (b - A x) on the next coarser grid (full weighting)."""
+    cp, keep = _cproblem(prob)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(prob.shape)
+    out = np.zeros(coarse_shape(prob))
+    load().srjo_restrict_residual(ctypes.byref(cp), _dptr(x), _dptr(out))
+    return out
+
+
+def prolong_add(prob, ec: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """x + P ec (multilinear interpolation from the next coarser grid)."""
+    cp, keep = _cproblem(prob)
+    ec = np.ascontiguousarray(ec, dtype=np.float64).reshape(coarse_shape(prob))
+    out = np.array(x, dtype=np.float64).reshape(prob.shape).copy()
+    load().srjo_prolong_add(ctypes.byref(cp), _dptr(ec), _dptr(out))
+    return out
+
+
+def mg_solve(prob, x0: Optional[np.ndarray] = None, *, rule: str = "fixed",
+             start_level: int = 1, max_level: int = 24, pre: int = 1, post: int = 1,
+             max_levels: int = 32, coarse_tol: float = 1e-8, coarse_max_cycles: int = 1000,
+             tol: float = 1e-10, tol_mode: str = "relative", max_vcycles: int = 200) -> Dict:
+    """V-cycles with SRJ smoothing to tolerance; per-V-cycle levels and norms."""
+    cp, keep = _cproblem(prob)
+    x = (np.zeros(prob.shape) if x0 is None else np.array(x0, dtype=np.float64)
+         .reshape(prob.shape)).copy()
+    o = _MgOpts(RULES[rule], start_level, max_level, pre, post, max_levels, coarse_tol,
+                coarse_max_cycles, TOL_MODES[tol_mode], tol, max_vcycles)
+    r = _MgResult()
+    levels = np.full(max_vcycles, -2, dtype=np.int32)
+    norms = np.full(max_vcycles + 1, np.nan, dtype=np.float64)
+    st = load().srjo_mg_solve(ctypes.byref(cp), _dptr(x), ctypes.byref(o), ctypes.byref(r),
+                              levels.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(norms))
+    return {"status": STATUS.get(int(st), str(st)), "x": x, "converged": bool(r.converged),
+            "vcycles": int(r.vcycles), "final_level": int(r.final_level), "levels_grid": int(r.levels),
+            "sweeps": int(r.sweeps), "coarse_sweeps": int(r.coarse_sweeps), "work": float(r.work),
+            "r0": float(r.r0), "r_final": float(r.r_final),
+            "levels": levels[:r.vcycles].copy(), "norms": norms[:r.vcycles + 1].copy()}
 
 
 def round_f16(v: np.ndarray) -> np.ndarray:

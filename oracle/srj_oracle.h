@@ -120,6 +120,42 @@ typedef struct {
 void srjo_collect(const srjo_problem *p, int32_t trials, int32_t max_steps, const double *u,
                   double tol, int32_t max_level, srjo_sample *out, int32_t *steps);
 
+/* SRJ as the smoother of a geometric multigrid V-cycle (srj_mg.c; section 5
+ * names the use, the design is this library's reading).  Constant-coefficient
+ * stencils only; every active axis of the fine grid is halved, n' = (n-1)/2,
+ * while all active sizes are odd and >= 3 (at least two levels needed). */
+typedef struct {
+    int32_t rule;              /* SRJO_RULE_HEURISTIC or SRJO_RULE_FIXED: smoothing scheme */
+    int32_t start_level;       /* smoothing scheme of the first V-cycle */
+    int32_t max_level;         /* highest smoothing level the selector may choose */
+    int32_t pre, post;         /* SRJ cycles before and after the coarse-grid correction */
+    int32_t max_levels;        /* grid levels at most (>= 2) */
+    double coarse_tol;         /* coarsest grid: SRJ with the selector from 0 to this relative tol */
+    int32_t coarse_max_cycles;
+    int32_t tol_mode;          /* SRJO_TOL_RELATIVE or SRJO_TOL_ABSOLUTE, after each V-cycle */
+    double tol;
+    int32_t max_vcycles;
+} srjo_mg_opts;
+
+typedef struct {
+    int32_t status, converged, vcycles, final_level, levels;
+    int64_t sweeps;          /* fine-grid smoothing sweeps */
+    int64_t coarse_sweeps;   /* coarsest-grid SRJ sweeps */
+    double work;             /* all sweeps in fine-sweep equivalents (points / fine points) */
+    double r0, r_final;
+} srjo_mg_result;
+
+int32_t srjo_mg_hierarchy(const srjo_problem *p, int32_t max_levels, int64_t *dims_out);
+/* bc = R (b - A x), full weighting, coarse grid of the hierarchy's next level */
+void srjo_restrict_residual(const srjo_problem *p, const double *x, double *bc);
+/* x += P ec, multilinear interpolation from the next level's grid */
+void srjo_prolong_add(const srjo_problem *p, const double *ec, double *x);
+/* V-cycles until the residual test holds; levels_out[max_vcycles] receives
+ * the smoothing level of each V-cycle, norms_out[max_vcycles + 1] the
+ * initial norm and each V-cycle's. */
+int32_t srjo_mg_solve(const srjo_problem *p, double *x, const srjo_mg_opts *o,
+                      srjo_mg_result *res, int32_t *levels_out, double *norms_out);
+
 /* Storage roundings used by the 16-bit refinement modes. */
 float srjo_round_f16(float v);
 float srjo_round_bf16(float v);

@@ -55,11 +55,11 @@ def build_library() -> str:
 
 def build_oracle() -> str:
     os.makedirs(ORACLE_DIR, exist_ok=True)
-    src = os.path.join(ROOT, "oracle", "srj_oracle.c")
+    srcs = [os.path.join(ROOT, "oracle", "srj_oracle.c"), os.path.join(ROOT, "oracle", "srj_mg.c")]
     lib = os.path.join(ORACLE_DIR, "liboracle.so")
     cmd = ["gcc", "-O1", "-g", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
-           "-fno-omit-frame-pointer", "-o", lib, src, "-lm"]
+           "-fno-omit-frame-pointer", "-o", lib] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     return lib
 
