@@ -106,8 +106,8 @@ def parse():
                     help="target length of each CPU oracle sample (0 = skip)")
     ap.add_argument("--ooc-n", type=int, default=8192,
                     help="side of the out-of-cache 2D grid (0 = skip)")
-    ap.add_argument("--only", choices=["c1", "ooc", "c3", "c4", "c5", "c2vc", "training", "neumann",
-                                       "general"],
+    ap.add_argument("--only", choices=["c1", "ooc", "mg", "c3", "c4", "c5", "c2vc", "training",
+                                       "neumann", "general"],
                     default="", help="run one leg alone and print its record")
     ap.add_argument("--c3-cycles", type=int, default=200,
                     help="cycle cap of each 3D variable-coefficient solve")
@@ -694,6 +694,89 @@ def leg_out_of_cache(n=8192, level=12):
     return rec
 
 
+def leg_multigrid(runs=5):
+    """SRJ as the smoother of a multigrid V-cycle (section 5 names the use):
+    2D Poisson 2047^2 (the C2 recipe on an odd grid, seed 0) and 3D Poisson
+    255^3 (b ~ U(-1, 1), seed 0), V-cycles with Algorithm 1 choosing the
+    smoothing scheme, to relative 1e-10, against plain binary64 SRJ on the
+    same problem (2D to the tolerance both reach, 2e-9; 3D to 1e-10).  The
+    CPU oracle's multigrid on 255^2 sits beside it with its time and the GPU's
+    agreement on that grid."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads
+    from paper_2011_06636_amd.solver import MgSolver, Solver
+
+    def med(fn):
+        fn()
+        ts, out = [], None
+        for _ in range(runs):
+            out, dt = _timed(fn)
+            ts.append(dt)
+        return out, statistics.median(ts)
+
+    recs = {}
+    rng = np.random.default_rng(0)
+    cases = [("2d_2047", workloads.c2(n=2047), 2e-9),
+             ("3d_255", workloads.poisson([255, 255, 255], b=rng.uniform(-1, 1, (255, 255, 255))), 1e-10)]
+    for name, prob, srj_tol in cases:
+        m = MgSolver(prob)
+        x = m.zeros()
+
+        def mg_run(tol):
+            x.zero_()
+            return m.solve(x, tol=tol)
+        out, t_mg = med(lambda: mg_run(1e-10))
+        outc, t_mgc = med(lambda: mg_run(srj_tol))
+        m.close()
+        del x
+        s = Solver(prob)
+        y = s.zeros()
+
+        def srj_run():
+            y.zero_()
+            return s.solve(y, tol=srj_tol, max_cycles=300)
+        ref, t_srj = med(srj_run)
+        s.close()
+        del y
+        torch.cuda.empty_cache()
+        recs[name] = {
+            "grid": list(prob.n[:prob.ndim]), "grid_levels": out["levels_grid"],
+            "mg_to_1e-10": {"converged": out["converged"], "vcycles": out["vcycles"],
+                            "smoothing_levels": [int(v) for v in out["levels"]],
+                            "fine_sweeps": out["sweeps"], "coarse_sweeps": out["coarse_sweeps"],
+                            "work_fine_sweep_equivalents": round(out["work"], 2),
+                            "time_ms": round(t_mg * 1e3, 3),
+                            "final_rel_residual": float(out["r_final"] / out["r0"])},
+            "common_tol": srj_tol,
+            "mg_to_common_tol": {"vcycles": outc["vcycles"], "time_ms": round(t_mgc * 1e3, 3),
+                                 "work_fine_sweep_equivalents": round(outc["work"], 2)},
+            "srj_f64_to_common_tol": {"converged": ref["converged"], "cycles": ref["cycles"],
+                                      "sweeps": ref["sweeps"], "time_ms": round(t_srj * 1e3, 3)},
+            "mg_speedup_at_common_tol": round(t_srj / t_mgc, 2)}
+        print(f"# multigrid {name}: {t_mgc * 1e3:.2f} ms vs SRJ {t_srj * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    # the oracle's multigrid on a smaller grid, and the GPU's agreement there
+    small = workloads.c2(n=255)
+    t0 = time.perf_counter()
+    ro = oracle.mg_solve(small, rule="heuristic", start_level=0, tol=1e-10)
+    t_or = time.perf_counter() - t0
+    m = MgSolver(small)
+    go = m.solve(tol=1e-10)
+    xg = go["x"].cpu().numpy()
+    m.close()
+    recs["cpu_reference_sample"] = {
+        "grid": [255, 255], "vcycles": ro["vcycles"], "time_ms": round(t_or * 1e3, 1),
+        "threads": oracle.num_threads(),
+        "gpu_same_levels": bool(np.array_equal(go["levels"], ro["levels"])),
+        "gpu_bit_identical": bool(np.array_equal(xg, ro["x"]))}
+    return {"workload": "multigrid V-cycles with SRJ smoothing: full weighting, multilinear "
+                        "interpolation, coarse couplings / 4, one pre- and one post-cycle, "
+                        "coarsest grid by SRJ to 1e-8", "cases": recs}
+
+
 def run_leg(s, x, kw, steps, warmup, label):
     """warmup + timed solves; returns per-step times, results and the sweep profile."""
     import torch
@@ -762,7 +845,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.only:
-        legs = {"c1": leg_c1, "ooc": lambda: leg_out_of_cache(args.ooc_n),
+        legs = {"c1": leg_c1, "ooc": lambda: leg_out_of_cache(args.ooc_n), "mg": leg_multigrid,
                 "c3": lambda: extra_c3(args.c3_cycles), "c4": lambda: extra_batch("c4"),
                 "c5": lambda: extra_batch("c5"), "c2vc": extra_c2_varcoef,
                 "training": extra_training,
@@ -877,7 +960,8 @@ def main():
                          "c5_batch_3d": extra_batch("c5"), "c2_2d_varcoef": extra_c2_varcoef(),
                          "selector_training": extra_training(),
                          "neumann_update_test": extra_neumann(),
-                         "general_matrices": extra_general()}
+                         "general_matrices": extra_general(),
+                         "multigrid_srj_smoother": leg_multigrid()}
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, last["levels"], last["norms"])
     print(json.dumps(rec), flush=True)

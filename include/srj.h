@@ -440,6 +440,70 @@ srj_status srj_batch_autotune(srj_batch *batch, int32_t precision, int32_t sweep
 
 srj_status srj_batch_destroy(srj_batch *batch);
 
+/* SRJ as the smoother of a geometric multigrid V-cycle (section 5 names
+ * SRJ as a candidate multigrid smoother; the paper gives no design, so the
+ * following is this library's reading).  For constant-coefficient stencil
+ * problems whose active sizes are odd: level l + 1 halves every active axis,
+ * n' = (n - 1) / 2, while all active sizes are odd and >= 3, with couplings
+ * and diagonal divided by 4 (rediscretisation on the doubled spacing).  One
+ * V-cycle on level l: `pre` SRJ cycles of the current scheme (section 2,
+ * Eq. 7), the residual restricted by full weighting (weights 1/4, 1/2, 1/4
+ * per axis), the coarse correction from zero by the V-cycle on level l + 1,
+ * multilinear interpolation of it added to x, `post` SRJ cycles.  The
+ * coarsest level used is solved by SRJ with Algorithm 1 from zero to the
+ * relative tolerance coarse_tol (at most coarse_max_cycles cycles).  After
+ * each V-cycle the binary64 residual norm is tested (tol_mode relative or
+ * absolute) and, with SRJ_RULE_HEURISTIC, the V-cycle's residual ratio picks
+ * the next V-cycle's smoothing scheme by Algorithm 1 (section 3) within
+ * start_level .. max_level; SRJ_RULE_FIXED keeps start_level.  Transfers and
+ * smoothing evaluate fixed-order expressions without contraction, so x is
+ * bit-identical to a CPU evaluation in the same order. */
+typedef struct srj_mg srj_mg;
+typedef struct {
+    srj_rule rule;             /* SRJ_RULE_HEURISTIC or SRJ_RULE_FIXED */
+    int32_t start_level;       /* smoothing scheme of the first V-cycle, 0..max_level */
+    int32_t max_level;         /* highest smoothing scheme, 0..24 */
+    int32_t pre, post;         /* SRJ cycles before / after the coarse correction, 0..1000 */
+    int32_t max_levels;        /* grid levels used at most, >= 2 */
+    double coarse_tol;         /* relative tolerance of the coarsest solve, > 0 */
+    int32_t coarse_max_cycles; /* >= 1 */
+    srj_tol_mode tol_mode;     /* SRJ_TOL_RELATIVE or SRJ_TOL_ABSOLUTE */
+    double tol;                /* > 0 */
+    int32_t max_vcycles;       /* >= 1 */
+} srj_mg_opts;
+
+typedef struct {
+    int32_t converged;
+    int32_t vcycles;
+    int32_t final_level;       /* smoothing scheme of the last V-cycle */
+    int32_t levels;            /* grid levels used */
+    int64_t sweeps;            /* smoothing sweeps on the finest grid */
+    int64_t coarse_sweeps;     /* SRJ sweeps of the coarsest solves */
+    double work;               /* all sweeps in finest-grid sweep equivalents */
+    double r0, r_final;        /* residual norms before the first and after the last V-cycle */
+} srj_mg_result;
+
+/* Defaults: heuristic, start level 0, max level 24, one pre- and one post-
+ * cycle, up to 32 grid levels, coarsest solve to 1e-8 (1000 cycles), relative
+ * tolerance 1e-10, 200 V-cycles. */
+void srj_mg_default_opts(srj_mg_opts *opts);
+
+/* Builds the level hierarchy for *p (device arrays as for srj_setup; b is
+ * borrowed, the coarse levels' arrays and contexts are owned by *out).
+ * SRJ_ERR_UNSUPPORTED for per-face couplings or a diagonal array, or a grid
+ * that cannot be coarsened once; SRJ_ERR_INVALID as srj_setup. */
+srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out);
+
+/* V-cycles from the initial guess in x (device, in/out) until the residual
+ * test holds or max_vcycles.  levels_out (host, max_vcycles entries): the
+ * smoothing scheme of each V-cycle; norms_out (host, max_vcycles + 1): the
+ * initial norm and each V-cycle's; either may be NULL.  Returns SRJ_OK,
+ * SRJ_ERR_NOT_CONVERGED at the cap or SRJ_ERR_NONFINITE, with *res filled;
+ * blocks until x is valid. */
+srj_status srj_mg_solve(srj_mg *mg, double *x, const srj_mg_opts *opts, srj_mg_result *res,
+                        int32_t *levels_out, double *norms_out);
+srj_status srj_mg_destroy(srj_mg *mg);
+
 /* Measurement aid, not a step of the method: one launch of a streaming
  * kernel of known traffic on hip_stream (no synchronisation), the ceiling
  * that sweep kernels' byte rates are quoted against and the reference

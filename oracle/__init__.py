@@ -277,8 +277,8 @@ def prolong_add(prob, ec: np.ndarray, x: np.ndarray) -> np.ndarray:
     return out
 
 
-def mg_solve(prob, x0: Optional[np.ndarray] = None, *, rule: str = "fixed",
-             start_level: int = 1, max_level: int = 24, pre: int = 1, post: int = 1,
+def mg_solve(prob, x0: Optional[np.ndarray] = None, *, rule: str = "heuristic",
+             start_level: int = 0, max_level: int = 24, pre: int = 1, post: int = 1,
              max_levels: int = 32, coarse_tol: float = 1e-8, coarse_max_cycles: int = 1000,
              tol: float = 1e-10, tol_mode: str = "relative", max_vcycles: int = 200) -> Dict:
     """V-cycles with SRJ smoothing to tolerance; per-V-cycle levels and norms."""

@@ -42,6 +42,7 @@ EXPORTS = [
     "srj_batch_autotune",
     "srj_batch_solve", "srj_batch_destroy", "srj_collect", "srj_cluster_samples",
     "srj_fit_rule", "srj_set_scheme_family", "srj_last_error", "srj_stream_probe",
+    "srj_mg_default_opts", "srj_mg_setup", "srj_mg_solve", "srj_mg_destroy",
 ]
 
 SRJ_ACTION_NONE = 2
@@ -72,6 +73,21 @@ class SrjSolveResult(ctypes.Structure):
                 ("final_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("sweeps", ctypes.c_int64), ("r0", ctypes.c_double),
                 ("r_final", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+class SrjMgOpts(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("start_level", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("pre", ctypes.c_int32), ("post", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("coarse_tol", ctypes.c_double),
+                ("coarse_max_cycles", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int32)]
+
+
+class SrjMgResult(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("vcycles", ctypes.c_int32),
+                ("final_level", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("sweeps", ctypes.c_int64), ("coarse_sweeps", ctypes.c_int64),
+                ("work", ctypes.c_double), ("r0", ctypes.c_double), ("r_final", ctypes.c_double)]
 
 
 class SrjSample(ctypes.Structure):
@@ -142,6 +158,10 @@ def load() -> ctypes.CDLL:
         "srj_fit_rule": (i32, [vp, i32, P(f64), P(f64), P(i32), P(i32)]),
         "srj_last_error": (ctypes.c_char_p, []),
         "srj_stream_probe": (i32, [i32, vp, vp, vp, i64, vp]),
+        "srj_mg_default_opts": (None, [P(SrjMgOpts)]),
+        "srj_mg_setup": (i32, [P(SrjProblem), vp, P(vp)]),
+        "srj_mg_solve": (i32, [vp, vp, P(SrjMgOpts), P(SrjMgResult), P(i32), P(f64)]),
+        "srj_mg_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -223,6 +243,31 @@ def srj_stream_probe(kind: int, a_ptr: int, b_ptr, out_ptr: int, n: int, stream:
     check(load().srj_stream_probe(kind, ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr),
                                   ctypes.c_void_p(out_ptr), n, ctypes.c_void_p(stream)),
           "srj_stream_probe")
+
+
+def srj_mg_default_opts() -> SrjMgOpts:
+    o = SrjMgOpts()
+    load().srj_mg_default_opts(ctypes.byref(o))
+    return o
+
+
+def srj_mg_setup(prob: SrjProblem, stream: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    check(load().srj_mg_setup(ctypes.byref(prob), ctypes.c_void_p(stream), ctypes.byref(h)),
+          "srj_mg_setup")
+    return h
+
+
+def srj_mg_solve(mg, x_ptr: int, opts: SrjMgOpts, levels=None, norms=None):
+    res = SrjMgResult()
+    st = load().srj_mg_solve(mg, ctypes.c_void_p(x_ptr), ctypes.byref(opts), ctypes.byref(res),
+                             levels, norms)
+    return st, res
+
+
+def srj_mg_destroy(mg) -> None:
+    if mg:
+        load().srj_mg_destroy(mg)
 
 
 def srj_solve(ctx, x_ptr: int, opts: SrjSolveOpts, levels=None, norms=None):

@@ -232,6 +232,79 @@ class Solver:
         return {"samples": samples, "steps": steps.cpu().numpy()}
 
 
+class MgSolver:
+    """SRJ-smoothed multigrid V-cycles on one problem: wraps srj_mg_setup /
+    srj_mg_solve (constant-coefficient stencils with odd active sizes)."""
+
+    def __init__(self, problem, device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        abi.load()
+        self.device = torch.device(device)
+        self.shape = tuple(problem.b.shape)
+        self.npoints = int(np.prod(self.shape))
+        self.b = _dev(problem.b, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # per-face couplings or a diagonal array are passed on (the library
+        # refuses them for multigrid)
+        faces = getattr(problem, "faces", None)
+        self.faces = [(_dev(f, self.device) if f is not None else None) for f in faces] \
+            if faces is not None else None
+        diag = getattr(problem, "diag", None)
+        self.diag = _dev(diag, self.device) if diag is not None else None
+        self._prob = make_problem(int(problem.ndim), problem.n, problem.c, problem.dconst, self.b,
+                                  self.faces, self.diag)
+        torch.cuda.synchronize(self.device)
+        self.handle = abi.srj_mg_setup(self._prob, self.stream.cuda_stream)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            abi.srj_mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def to_device(self, a) -> torch.Tensor:
+        return _dev(np.asarray(a).reshape(self.shape), self.device)
+
+    @staticmethod
+    def opts(rule: str = "heuristic", start_level: int = 0, max_level: int = 24, pre: int = 1,
+             post: int = 1, max_levels: int = 32, coarse_tol: float = 1e-8,
+             coarse_max_cycles: int = 1000, tol: float = 1e-10, tol_mode: str = "relative",
+             max_vcycles: int = 200) -> abi.SrjMgOpts:
+        o = abi.srj_mg_default_opts()
+        o.rule = abi.RULE[rule]
+        o.start_level, o.max_level, o.pre, o.post = start_level, max_level, pre, post
+        o.max_levels, o.coarse_tol, o.coarse_max_cycles = max_levels, coarse_tol, coarse_max_cycles
+        o.tol, o.tol_mode, o.max_vcycles = tol, abi.TOL_MODE[tol_mode], max_vcycles
+        return o
+
+    def solve(self, x: Optional[torch.Tensor] = None, **kw) -> Dict:
+        """V-cycles in place on x (zeros if None); returns counters, levels and norms."""
+        if x is None:
+            x = self.zeros()
+        o = self.opts(**kw)
+        levels = (ctypes.c_int32 * o.max_vcycles)()
+        norms = (ctypes.c_double * (o.max_vcycles + 1))()
+        check_iterate(x, self.device, self.npoints)
+        with _Ordered(self.device, self.stream):
+            st, res = abi.srj_mg_solve(self.handle, x.data_ptr(), o, levels, norms)
+        if st not in (abi.SRJ_OK, abi.SRJ_ERR_NOT_CONVERGED, abi.SRJ_ERR_NONFINITE):
+            raise abi.SrjError(st, "srj_mg_solve")
+        nv = res.vcycles
+        return {"status": abi.STATUS_NAMES[st], "x": x, "converged": bool(res.converged),
+                "vcycles": nv, "final_level": res.final_level, "levels_grid": res.levels,
+                "sweeps": int(res.sweeps), "coarse_sweeps": int(res.coarse_sweeps),
+                "work": res.work, "r0": res.r0, "r_final": res.r_final,
+                "levels": np.array(levels[:nv], dtype=np.int32),
+                "norms": np.array(norms[:nv + 1], dtype=np.float64)}
+
+
 class BatchSolver:
     """Many problems solved together: wraps srj_batch_setup / srj_batch_solve.
 

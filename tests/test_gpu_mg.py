@@ -1,0 +1,93 @@
+"""GPU parity of the multigrid V-cycle with SRJ smoothing (srj_mg_*,
+through the C ABI) against the oracle's (oracle/srj_mg.c).
+
+Transfers and smoothing evaluate the oracle's fixed-order expressions, so the
+iterate must be bit-identical, the smoothing scheme of every V-cycle the
+same, the counters (fine sweeps, coarsest-solve sweeps, work) equal, and the
+V-cycle norms equal to 1e-12 (sums in another order).  Grids: 1D, 2D with
+unequal sides that stop coarsening at an even size, 3D, a hierarchy cut by
+max_levels, fixed and heuristic smoothing schemes, pre/post counts."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rand(n, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(list(n) + [1] * (3 - len(n))))
+    return workloads.poisson(n, b=rng.uniform(-1, 1, shape))
+
+
+CASES = [
+    ("1d_255", lambda: workloads.c1(), dict()),
+    ("2d_c2_recipe_127", lambda: workloads.c2(n=127), dict()),
+    ("2d_95x47_fixed2", lambda: _rand([95, 47], 1), dict(rule="fixed", start_level=2)),
+    ("2d_63_pre2_post0", lambda: _rand([63, 63], 2), dict(pre=2, post=0, max_level=5)),
+    ("2d_255_3levels", lambda: _rand([255, 255], 3), dict(max_levels=3, coarse_tol=1e-6)),
+    ("3d_31", lambda: _rand([31, 31, 31], 4), dict()),
+    ("3d_aniso_63x31x15", lambda: workloads.anisotropic([63, 31, 15], [1.0, 0.3, 0.05],
+                                                         np.random.default_rng(5).uniform(-1, 1, (15, 31, 63))),
+     dict(rule="fixed", start_level=3)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_mg_matches_oracle(torch_cuda, orc, case):
+    from paper_2011_06636_amd.solver import MgSolver
+    name, make, kw = CASES[case]
+    prob = make()
+    print(f"mg case {name}: n = {prob.n}", flush=True)
+    kw = dict(tol=1e-10) | kw
+    ref = orc.mg_solve(prob, **kw)
+    s = MgSolver(prob)
+    out = s.solve(**kw)
+    assert out["status"] == ref["status"], (name, out["status"], ref["status"])
+    assert out["levels_grid"] == ref["levels_grid"]
+    np.testing.assert_array_equal(out["levels"], ref["levels"])
+    assert out["sweeps"] == ref["sweeps"] and out["coarse_sweeps"] == ref["coarse_sweeps"]
+    assert out["work"] == ref["work"]
+    np.testing.assert_allclose(out["norms"], ref["norms"], rtol=1e-12, atol=0)
+    got = out["x"].cpu().numpy()
+    assert np.array_equal(got, ref["x"]), (name, np.max(np.abs(got - ref["x"])))
+    s.close()
+
+
+def test_mg_resumes_from_initial_guess(torch_cuda, orc):
+    from paper_2011_06636_amd.solver import MgSolver
+    prob = _rand([63, 31], 7)
+    x0 = np.random.default_rng(8).uniform(-1, 1, prob.shape)
+    ref = orc.mg_solve(prob, x0, tol=1e-9)
+    s = MgSolver(prob)
+    out = s.solve(s.to_device(x0), tol=1e-9)
+    assert np.array_equal(out["x"].cpu().numpy(), ref["x"])
+    np.testing.assert_array_equal(out["levels"], ref["levels"])
+    s.close()
+
+
+def test_mg_rejects_what_it_cannot_coarsen(torch_cuda):
+    from paper_2011_06636_amd import abi
+    from paper_2011_06636_amd.solver import MgSolver
+    with pytest.raises(abi.SrjError) as e:
+        MgSolver(workloads.poisson([64, 63]))
+    assert e.value.status == abi.SRJ_ERR_UNSUPPORTED
+    with pytest.raises(abi.SrjError) as e:
+        MgSolver(workloads.variable_coefficient_2d(31, 31, seed=1))
+    assert e.value.status == abi.SRJ_ERR_UNSUPPORTED
+    s = MgSolver(workloads.poisson([31, 31]))
+    for bad in (dict(pre=-1), dict(max_levels=1), dict(rule="increasing"), dict(tol=0.0),
+                dict(start_level=5, max_level=3)):
+        with pytest.raises(abi.SrjError) as e:
+            s.solve(**bad)
+        assert e.value.status == abi.SRJ_ERR_INVALID, bad
+    s.close()
