@@ -196,6 +196,27 @@ __device__ __forceinline__ void plane3d_run(const Stencil3<typename V::A> &S,
     }
 }
 
+// Wave item of a plane kernel (four waves per workgroup).  Hardware places
+// workgroup i on XCD i % 8; each XCD takes a contiguous range of items, so a
+// tile's neighbours in y (tiles_x items away) run on the same XCD at about the
+// same time and its halo rows come from that XCD's L2.  Returns -1 for the
+// workgroups beyond the items (the grid is a multiple of 8 workgroups).
+__device__ __forceinline__ int plane_item(int64_t items)
+{
+    const int nwg = (int)((items + 3) / 4);
+    const int per_xcd = (nwg + 7) / 8;
+    const int logical = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (logical >= nwg) return -1;
+    return logical * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Workgroups to launch for `items` wave items: a multiple of 8.
+inline unsigned plane_grid(int64_t items)
+{
+    const int64_t nwg = (items + 3) / 4;
+    return (unsigned)((nwg + 7) / 8 * 8);
+}
+
 template <class V, int H, int ZC, bool FACE, bool DIAG>
 __global__ __launch_bounds__(256) void k_plane3d(Stencil3<typename V::A> S,
                                                  const typename V::T *__restrict__ x,
@@ -204,8 +225,8 @@ __global__ __launch_bounds__(256) void k_plane3d(Stencil3<typename V::A> S,
                                                  const typename V::A *__restrict__ wp, int tiles_x,
                                                  int tiles_y, int tiles_z)
 {
-    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
+    const int item = plane_item((int64_t)tiles_x * tiles_y * tiles_z);
+    if (item < 0 || item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
     const int tx = item % tiles_x, ty = (item / tiles_x) % tiles_y, tz = item / (tiles_x * tiles_y);
     plane3d_run<V, H, ZC, FACE, DIAG>(S, x, xo, b, wp[0], tx, ty, tz, threadIdx.x & 63);
 }
@@ -218,7 +239,8 @@ hipError_t launch_plane3d(const Stencil3<typename V::A> &S, const typename V::T 
     const int tx = (int)((S.n0 + 61) / 62), ty = (int)((S.n1 + H - 1) / H),
               tz = (int)((S.n2 + ZC - 1) / ZC);
     const int64_t items = (int64_t)tx * ty * tz;
-    const dim3 grid((unsigned)((items + 3) / 4));
+    if (items > INT32_MAX - 64) return hipErrorInvalidValue;
+    const dim3 grid(plane_grid(items));
     const bool face = S.face[0] && S.face[1] && S.face[2];
     const bool diag = S.diag != nullptr;
     if (face && diag)

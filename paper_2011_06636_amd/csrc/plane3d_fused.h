@@ -24,6 +24,7 @@
 #pragma once
 
 #include "internal.h"
+#include "plane3d.h"
 #include "stream3d.h"
 #include "tile2d.h"
 
@@ -161,8 +162,8 @@ __global__ __launch_bounds__(256) void k_plane3d2(Stencil3<typename V::A> S,
                                                   const typename V::A *__restrict__ wp,
                                                   int tiles_x, int tiles_y, int tiles_z)
 {
-    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
+    const int item = plane_item((int64_t)tiles_x * tiles_y * tiles_z);
+    if (item < 0 || item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
     const int tx = item % tiles_x, ty = (item / tiles_x) % tiles_y, tz = item / (tiles_x * tiles_y);
     plane3d2_run<V, H, ZC>(S, x, xo, b, wp[0], wp[1], tx, ty, tz, threadIdx.x & 63);
 }
@@ -177,8 +178,8 @@ hipError_t launch_plane3d2(const Stencil3<typename V::A> &S, const typename V::T
     if (S.n0 > INT32_MAX) return hipErrorInvalidValue;  // lane offsets are 32-bit
     const int64_t tx = (S.n0 + 59) / 60, ty = (S.n1 + H - 1) / H, tz = (S.n2 + ZC - 1) / ZC;
     const int64_t items = tx * ty * tz;
-    if (items > INT32_MAX - 3) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((items + 3) / 4));
+    if (items > INT32_MAX - 64) return hipErrorInvalidValue;
+    const dim3 grid(plane_grid(items));
     hipLaunchKernelGGL((k_plane3d2<V, H, ZC>), grid, dim3(256), 0, s, S, x, xo, b, w_dev, (int)tx,
                        (int)ty, (int)tz);
     return hipGetLastError();
@@ -359,8 +360,8 @@ __global__ __launch_bounds__(256) void k_plane3d2f(Stencil3<typename V::A> S,
                                                    const typename V::A *__restrict__ wp,
                                                    int tiles_x, int tiles_y, int tiles_z)
 {
-    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
+    const int item = plane_item((int64_t)tiles_x * tiles_y * tiles_z);
+    if (item < 0 || item >= tiles_x * tiles_y * tiles_z) return;  // whole wave leaves
     const int tx = item % tiles_x, ty = (item / tiles_x) % tiles_y, tz = item / (tiles_x * tiles_y);
     plane3d2f_run<V, H, ZC>(S, x, xo, b, wp[0], wp[1], tx, ty, tz, threadIdx.x & 63);
 }
@@ -377,8 +378,8 @@ hipError_t launch_plane3d2f(const Stencil3<typename V::A> &S, const typename V::
     if (S.n0 > INT32_MAX) return hipErrorInvalidValue;  // lane offsets are 32-bit
     const int64_t tx = (S.n0 + 59) / 60, ty = (S.n1 + H - 1) / H, tz = (S.n2 + ZC - 1) / ZC;
     const int64_t items = tx * ty * tz;
-    if (items > INT32_MAX - 3) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((items + 3) / 4));
+    if (items > INT32_MAX - 64) return hipErrorInvalidValue;
+    const dim3 grid(plane_grid(items));
     hipLaunchKernelGGL((k_plane3d2f<V, H, ZC>), grid, dim3(256), 0, s, S, x, xo, b, w_dev,
                        (int)tx, (int)ty, (int)tz);
     return hipGetLastError();
