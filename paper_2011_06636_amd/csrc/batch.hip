@@ -215,6 +215,84 @@ __device__ __forceinline__ double block_sum256(double v, double *lds)
 
 enum { OUT_STEP = 0, OUT_NORM = 1, OUT_CAST = 2 };
 
+// The points of one outer-pass item: thread t takes points base + t + 256 k,
+// k = 0..7.  Every load is unconditional: a neighbour outside the grid, and
+// a point beyond the instance, read a valid point (the centre, the last
+// point) and a select then drops the value, so that the term subtracted is
+// c * 0 = 0 and leaves the sum's bits unchanged; the loads of four points
+// are then in flight together (with a branch around each neighbour's load
+// the compiler waited for every load in turn; unrolled by 8 the registers
+// held occupancy at 2 waves per SIMD, no faster).  The sum of
+// squares accumulates in k order.  Returns this thread's sum of squares of
+// the binary64 residual.
+template <class St, bool REFINE, int MODE>
+__device__ __forceinline__ double outer_points(const BDesc d, const double *__restrict__ x,
+                                               const typename St::T *__restrict__ dl,
+                                               double *__restrict__ xn,
+                                               typename St::T *__restrict__ dz,
+                                               typename St::T *__restrict__ rh,
+                                               const double *__restrict__ bb, double inv_s,
+                                               double s_next, int64_t base)
+{
+    const int64_t s1 = d.n0, s2 = d.n0 * d.n1;
+    // instances below 2^31 points (every one of the batched workloads) split
+    // the point index with two 32-bit divisions instead of three 64-bit ones
+    const bool idx32 = d.npts < ((int64_t)1 << 31);
+    auto xv = [&](int64_t pp) -> double {
+        if (REFINE && MODE == OUT_STEP)
+            return x[pp] + static_cast<double>(St::load(dl[pp])) * inv_s;
+        return x[pp];
+    };
+    double acc = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < kOuterPts / 256; ++k) {
+        const int64_t qr = base + k * 256 + threadIdx.x;
+        const bool valid = qr < d.npts;
+        const int64_t q = valid ? qr : d.npts - 1;
+        int64_t i0, i1, i2;
+        if (idx32) {
+            const uint32_t qq = (uint32_t)q, m0 = (uint32_t)d.n0, m1 = (uint32_t)d.n1;
+            const uint32_t a0 = qq / m0, a1 = a0 / m1;
+            i0 = qq - a0 * m0;
+            i1 = a0 - a1 * m1;
+            i2 = a1;
+        } else {
+            i0 = q % d.n0;
+            i1 = (q / d.n0) % d.n1;
+            i2 = q / s2;
+        }
+        const bool h0 = i0 > 0, h1 = i0 < d.n0 - 1;
+        const bool h2 = d.ndim >= 2 && i1 > 0, h3 = d.ndim >= 2 && i1 < d.n1 - 1;
+        const bool h4 = d.ndim >= 3 && i2 > 0, h5 = d.ndim >= 3 && i2 < d.n2 - 1;
+        const double xc = xv(q);
+        const double v0 = xv(h0 ? q - 1 : q), v1 = xv(h1 ? q + 1 : q);
+        const double v2 = xv(h2 ? q - s1 : q), v3 = xv(h3 ? q + s1 : q);
+        const double v4 = xv(h4 ? q - s2 : q), v5 = xv(h5 ? q + s2 : q);
+        const double bq = bb[q];
+        double sacc = d.D * xc;
+        sacc = sacc - d.c[0] * (h0 ? v0 : 0.0);
+        sacc = sacc - d.c[0] * (h1 ? v1 : 0.0);
+        if (d.ndim >= 2) {
+            sacc = sacc - d.c[1] * (h2 ? v2 : 0.0);
+            sacc = sacc - d.c[1] * (h3 ? v3 : 0.0);
+        }
+        if (d.ndim >= 3) {
+            sacc = sacc - d.c[2] * (h4 ? v4 : 0.0);
+            sacc = sacc - d.c[2] * (h5 ? v5 : 0.0);
+        }
+        const double r = bq - sacc;
+        if (valid) {
+            acc += r * r;
+            if (REFINE && MODE != OUT_NORM) {
+                if (MODE == OUT_STEP) xn[q] = xc;
+                rh[q] = St::store(static_cast<float>(s_next * r));
+                dz[q] = St::store(0.0f);
+            }
+        }
+    }
+    return acc;
+}
+
 // 2. outer pass: one block of 256 threads per (instance, 2048 points) item.
 // REFINE: u = correction d (storage St), x ping-pong in binary64.
 // !REFINE: u is x itself (binary64).
@@ -254,7 +332,7 @@ __global__ __launch_bounds__(256) void k_bouter(const BDesc *__restrict__ desc,
             const int item = act[a];
             const int2 it = items[item];
             const BState s = st[it.x];
-            const BDesc &d = desc[it.x];
+            const BDesc d = desc[it.x];
             // which buffers hold the current iterate
             const double *x;
             const typename St::T *dl = nullptr;  // latest correction (REFINE, step)
@@ -280,38 +358,17 @@ __global__ __launch_bounds__(256) void k_bouter(const BDesc *__restrict__ desc,
                 const int cur = mode == OUT_STEP ? (s.pu ^ 1) : s.pu;
                 x = (cur ? v64 : u64) + d.off;
             }
-            const int64_t s1 = d.n0, s2 = d.n0 * d.n1;
             const int64_t base = (int64_t)(it.y - d.oitem_first) * kOuterPts;
-            double acc = 0.0;
-            for (int k = 0; k < kOuterPts / 256; ++k) {
-                const int64_t q = base + k * 256 + threadIdx.x;
-                if (q >= d.npts) break;
-                const int64_t i0 = q % d.n0, i1 = (q / d.n0) % d.n1, i2 = q / s2;
-                auto xv = [&](int64_t pp) -> double {
-                    if (REFINE && mode == OUT_STEP)
-                        return x[pp] + static_cast<double>(St::load(dl[pp])) * inv_s;
-                    return x[pp];
-                };
-                const double xc = xv(q);
-                double sacc = d.D * xc;
-                if (i0 > 0) sacc = sacc - d.c[0] * xv(q - 1);
-                if (i0 < d.n0 - 1) sacc = sacc - d.c[0] * xv(q + 1);
-                if (d.ndim >= 2) {
-                    if (i1 > 0) sacc = sacc - d.c[1] * xv(q - s1);
-                    if (i1 < d.n1 - 1) sacc = sacc - d.c[1] * xv(q + s1);
-                }
-                if (d.ndim >= 3) {
-                    if (i2 > 0) sacc = sacc - d.c[2] * xv(q - s2);
-                    if (i2 < d.n2 - 1) sacc = sacc - d.c[2] * xv(q + s2);
-                }
-                const double r = b[d.off + q] - sacc;
-                acc += r * r;
-                if (REFINE && mode != OUT_NORM) {
-                    if (mode == OUT_STEP) xn[q] = xc;
-                    rhat[d.off + q] = St::store(static_cast<float>(s_next * r));
-                    dz[q] = St::store(0.0f);
-                }
-            }
+            double acc;
+            if (REFINE && mode == OUT_STEP)
+                acc = outer_points<St, REFINE, OUT_STEP>(d, x, dl, xn, dz, rhat + d.off, b + d.off,
+                                                         inv_s, s_next, base);
+            else if (REFINE && mode == OUT_CAST)
+                acc = outer_points<St, REFINE, OUT_CAST>(d, x, dl, xn, dz, rhat + d.off, b + d.off,
+                                                         inv_s, s_next, base);
+            else
+                acc = outer_points<St, REFINE, OUT_NORM>(d, x, dl, xn, dz, rhat + d.off, b + d.off,
+                                                         inv_s, s_next, base);
             const double t = block_sum256(acc, lds);
             if (threadIdx.x == 0) partials[item] = t;
         }
