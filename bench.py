@@ -107,8 +107,10 @@ def parse():
     ap.add_argument("--ooc-n", type=int, default=8192,
                     help="side of the out-of-cache 2D grid (0 = skip)")
     ap.add_argument("--only", choices=["c1", "ooc", "mg", "c3", "c4", "c5", "c2vc", "training",
-                                       "neumann", "general"],
+                                       "neumann", "general", "c4once", "c5once"],
                     default="", help="run one leg alone and print its record")
+    ap.add_argument("--precision", default="bf16", choices=["f64", "f32", "bf16", "f16"],
+                    help="precision of --only c5once")
     ap.add_argument("--c3-cycles", type=int, default=200,
                     help="cycle cap of each 3D variable-coefficient solve")
     return ap.parse_args()
@@ -353,6 +355,31 @@ def extra_c2_varcoef(n=2048, cycles=40, tol=1e-6, tol_cycles=100):
               flush=True)
     s.close()
     return rec
+
+
+def batch_once(which, prec):
+    """One batched solve of workload 4 ("c4", binary32-refined) or 5 ("c5",
+    `prec`) with a fixed plan, no autotuning and no loop of single solves:
+    the run that the batched kernel traces are taken from."""
+    import torch
+
+    import workloads
+    from paper_2011_06636_amd.solver import BatchSolver
+    if which == "c4":
+        bs = BatchSolver(workloads.c4())
+        assert bs.set_plan(12, 8, 16, True, 8) == 0
+        kw = dict(tol=1e-10, precision="f32", max_cycles=300)
+    else:
+        bs = BatchSolver(workloads.c5())
+        bs.set_plan3d(8, 16, 2)
+        kw = dict(tol=1e-8, precision=prec, max_cycles=300)
+    out, dt = _timed(lambda: bs.solve(**kw))
+    conv = sum(i["converged"] for i in out["instances"])
+    plan = bs.get_plan() if which == "c4" else bs.get_plan3d()
+    bs.close()
+    torch.cuda.synchronize()
+    return {"workload": which, "precision": kw["precision"], "plan": list(plan),
+            "converged": conv, "instances": len(out["instances"]), "time_ms": round(dt * 1e3, 3)}
 
 
 def extra_batch(which):
@@ -849,7 +876,9 @@ def main():
                 "c3": lambda: extra_c3(args.c3_cycles), "c4": lambda: extra_batch("c4"),
                 "c5": lambda: extra_batch("c5"), "c2vc": extra_c2_varcoef,
                 "training": extra_training,
-                "neumann": extra_neumann, "general": extra_general}
+                "neumann": extra_neumann, "general": extra_general,
+                "c4once": lambda: batch_once("c4", "f32"),
+                "c5once": lambda: batch_once("c5", args.precision)}
         print(json.dumps({"only": args.only, "record": legs[args.only]()}), flush=True)
         return
     prob = workloads.c2(n=args.n)
