@@ -240,6 +240,22 @@ constexpr int64_t kResidentMax = 4000;
 bool resident_fits(const DevProblem &P);
 srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
                           int32_t *levels_out, double *norms_out);
+// The same solve launched with no host work (so that it can be captured in
+// a graph): the residual stopping test only, opts already validated and
+// clamped as srj_solve does, buffers made by resident_prepare for at least
+// o->max_cycles cycles.  The kernel appends its sweep count to rec.sweeps
+// (at index *rec.count, kept while below rec.cap; *rec.count is incremented)
+// and stores any status other than SRJ_OK and SRJ_ERR_NOT_CONVERGED in
+// *rec.bad, in stream order.
+struct ResidentRecord {
+    int64_t *sweeps = nullptr;
+    int32_t *count = nullptr;
+    int32_t *bad = nullptr;
+    int32_t cap = 0;
+};
+srj_status resident_prepare(srj_ctx *c, int max_cycles);
+srj_status resident_launch_recorded(srj_ctx *c, double *x, const srj_solve_opts *o,
+                                    const ResidentRecord &rec);
 // Autotuner cache (tune.hip): key -> plan and time per sweep.
 std::string tune_key(const char *what, int which, int ndim, const int64_t n[3], bool faces,
                      bool diag);

@@ -36,22 +36,87 @@ constexpr int kMgMaxLevels = 32;
 
 __device__ __forceinline__ double full_weight(int a) { return a == 0 ? 0.5 : 0.25; }
 
-// Coarse right-hand side bc = R (b - A x): one thread per coarse point; the
-// fine residuals of points 2 I + 1 + a (a in {-1, 0, 1} per active axis) are
-// weighted by the product of the per-axis full weights and summed with axis 2
-// outermost and axis 0 innermost.  Each residual is the sweep's expression.
+// Grid coordinates of point t of an n0 x n1 x n2 grid: two 32-bit divisions
+// when the grid has fewer than 2^31 points (every grid that fits in memory
+// with its other arrays), else 64-bit ones.
+__device__ __forceinline__ void grid_coords(int64_t t, int64_t n0, int64_t n1, int64_t n2,
+                                            int64_t &i0, int64_t &i1, int64_t &i2)
+{
+    if (n0 * n1 * n2 < ((int64_t)1 << 31)) {
+        const uint32_t u = (uint32_t)t, a0 = u / (uint32_t)n0, a1 = a0 / (uint32_t)n1;
+        i0 = u - a0 * (uint32_t)n0;
+        i1 = a0 - a1 * (uint32_t)n1;
+        i2 = a1;
+    } else {
+        i0 = t % n0;
+        i1 = (t / n0) % n1;
+        i2 = t / (n0 * n1);
+    }
+}
+
+// Fine residual r = b - A x at every point, the sweep's expression: D x,
+// then the axis-0, axis-1, axis-2 neighbours below and above, each
+// subtracted only where it lies in the grid.  Neighbour loads are
+// unconditional at clamped indices (a select drops the value), so that the
+// loads of a point are in flight together.  The restriction weights these
+// values; forming them once per fine point instead of once per coarse
+// point that uses them (up to 8 in 3D) leaves every value unchanged.
 template <int ND>
-__global__ __launch_bounds__(kMgBlock) void k_restrict_residual(DevProblem P,
-                                                                const double *__restrict__ x,
-                                                                double *__restrict__ bc,
-                                                                int64_t m0, int64_t m1,
-                                                                int64_t m2)
+__global__ __launch_bounds__(kMgBlock) void k_mg_residual(DevProblem P, const double *__restrict__ x,
+                                                          double *__restrict__ r)
+{
+    const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
+    const int64_t n0 = P.n0, n1 = P.n1, n2 = P.n2;
+    if (t >= n0 * n1 * n2) return;
+    int64_t i0, i1, i2;
+    grid_coords(t, n0, n1, n2, i0, i1, i2);
+    const int64_t s1 = n0, s2 = n0 * n1;
+    const bool h0 = i0 > 0, h1 = i0 < n0 - 1;
+    const bool h2 = ND > 1 && i1 > 0, h3 = ND > 1 && i1 < n1 - 1;
+    const bool h4 = ND > 2 && i2 > 0, h5 = ND > 2 && i2 < n2 - 1;
+    const double xc = x[t];
+    const double v0 = x[h0 ? t - 1 : t], v1 = x[h1 ? t + 1 : t];
+    double v2 = 0.0, v3 = 0.0, v4 = 0.0, v5 = 0.0;
+    if (ND > 1) {
+        v2 = x[h2 ? t - s1 : t];
+        v3 = x[h3 ? t + s1 : t];
+    }
+    if (ND > 2) {
+        v4 = x[h4 ? t - s2 : t];
+        v5 = x[h5 ? t + s2 : t];
+    }
+    double s = P.dconst * xc;
+    s = h0 ? s - P.c[0] * v0 : s;
+    s = h1 ? s - P.c[0] * v1 : s;
+    if (ND > 1) {
+        s = h2 ? s - P.c[1] * v2 : s;
+        s = h3 ? s - P.c[1] * v3 : s;
+    }
+    if (ND > 2) {
+        s = h4 ? s - P.c[2] * v4 : s;
+        s = h5 ? s - P.c[2] * v5 : s;
+    }
+    r[t] = P.b[t] - s;
+}
+
+// Coarse right-hand side bc = R r: one thread per coarse point; the fine
+// residuals of points 2 I + 1 + a (a in {-1, 0, 1} per active axis; all lie
+// in the grid, whose active sizes are 2 m + 1) are weighted by the product
+// of the per-axis full weights and summed with axis 2 outermost and axis 0
+// innermost.
+template <int ND>
+__global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restrict__ r,
+                                                          double *__restrict__ bc, int64_t n0,
+                                                          int64_t n1, int64_t m0, int64_t m1,
+                                                          int64_t m2)
 {
     const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
     if (t >= m0 * m1 * m2) return;
-    const int64_t I0 = t % m0, I1 = (t / m0) % m1, I2 = t / (m0 * m1);
-    const int64_t n0 = P.n0, n1 = P.n1, n2 = P.n2;
+    int64_t I0, I1, I2;
+    grid_coords(t, m0, m1, m2, I0, I1, I2);
     const int64_t s1 = n0, s2 = n0 * n1;
+    const int64_t c = (2 * I0 + 1) + (ND > 1 ? s1 * (2 * I1 + 1) : 0) +
+                      (ND > 2 ? s2 * (2 * I2 + 1) : 0);
     double s = 0.0;
 #pragma unroll
     for (int a2 = (ND > 2 ? -1 : 0); a2 <= (ND > 2 ? 1 : 0); ++a2)
@@ -62,31 +127,18 @@ __global__ __launch_bounds__(kMgBlock) void k_restrict_residual(DevProblem P,
                 double wt = full_weight(a0);
                 if (ND > 1) wt = wt * full_weight(a1);
                 if (ND > 2) wt = wt * full_weight(a2);
-                const int64_t i0 = 2 * I0 + 1 + a0;
-                const int64_t i1 = ND > 1 ? 2 * I1 + 1 + a1 : 0;
-                const int64_t i2 = ND > 2 ? 2 * I2 + 1 + a2 : 0;
-                const int64_t p = i0 + s1 * i1 + s2 * i2;
-                double r = P.dconst * x[p];
-                if (i0 > 0) r = r - P.c[0] * x[p - 1];
-                if (i0 < n0 - 1) r = r - P.c[0] * x[p + 1];
-                if (ND > 1) {
-                    if (i1 > 0) r = r - P.c[1] * x[p - s1];
-                    if (i1 < n1 - 1) r = r - P.c[1] * x[p + s1];
-                }
-                if (ND > 2) {
-                    if (i2 > 0) r = r - P.c[2] * x[p - s2];
-                    if (i2 < n2 - 1) r = r - P.c[2] * x[p + s2];
-                }
-                s = s + wt * (P.b[p] - r);
+                s = s + wt * r[c + a0 + s1 * a1 + s2 * a2];
             }
     bc[t] = s;
 }
 
 // x += P ec: one thread per fine point.  Per axis a fine index 2 J + 1 takes
 // coarse J with weight 1, a fine index 2 J takes coarse J - 1 and J with
-// weight 1/2 (indices outside the coarse grid are the zero boundary); terms
-// summed with axis 2 outermost, axis 0 innermost, candidates in increasing
-// order.
+// weight 1/2 (indices outside the coarse grid are the zero boundary and
+// give no term); terms summed with axis 2 outermost, axis 0 innermost,
+// candidates in increasing order.  Two candidate slots per axis, each with
+// a flag; a missing term is skipped by a select (its load reads coarse
+// point 0), so the sum is the same as over the present terms alone.
 template <int ND>
 __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restrict__ ec,
                                                           double *__restrict__ x, int64_t n0,
@@ -95,51 +147,50 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
 {
     const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
     if (t >= n0 * n1 * n2) return;
-    const int64_t ii[3] = {t % n0, (t / n0) % n1, t / (n0 * n1)};
+    int64_t ii[3];
+    grid_coords(t, n0, n1, n2, ii[0], ii[1], ii[2]);
     const int64_t mm[3] = {m0, m1, m2};
     int64_t cj[3][2];
     double cw[3][2];
-    int cnt[3];
+    bool has[3][2];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (d >= ND) {
-            cnt[d] = 1;
-            cj[d][0] = 0;
+            cj[d][0] = cj[d][1] = 0;
             cw[d][0] = 1.0;
-            cj[d][1] = 0;
             cw[d][1] = 0.0;
+            has[d][0] = true;
+            has[d][1] = false;
         } else if (ii[d] & 1) {
-            cnt[d] = 1;
             cj[d][0] = (ii[d] - 1) / 2;
-            cw[d][0] = 1.0;
             cj[d][1] = 0;
+            cw[d][0] = 1.0;
             cw[d][1] = 0.0;
+            has[d][0] = true;
+            has[d][1] = false;
         } else {
             const int64_t J = ii[d] / 2;
-            int c = 0;
-            cj[d][0] = cj[d][1] = 0;
-            cw[d][0] = cw[d][1] = 0.0;
-            if (J - 1 >= 0) {
-                cj[d][c] = J - 1;
-                cw[d][c] = 0.5;
-                ++c;
-            }
-            if (J < mm[d]) {
-                cj[d][c] = J;
-                cw[d][c] = 0.5;
-                ++c;
-            }
-            cnt[d] = c;
+            cj[d][0] = J - 1;
+            cj[d][1] = J;
+            cw[d][0] = cw[d][1] = 0.5;
+            has[d][0] = J - 1 >= 0;
+            has[d][1] = J < mm[d];
         }
     }
     double v = 0.0;
-    for (int k2 = 0; k2 < cnt[2]; ++k2)
-        for (int k1 = 0; k1 < cnt[1]; ++k1)
-            for (int k0 = 0; k0 < cnt[0]; ++k0) {
+#pragma unroll
+    for (int k2 = 0; k2 < (ND > 2 ? 2 : 1); ++k2)
+#pragma unroll
+        for (int k1 = 0; k1 < (ND > 1 ? 2 : 1); ++k1)
+#pragma unroll
+            for (int k0 = 0; k0 < 2; ++k0) {
+                const bool on = has[0][k0] && has[1][k1] && has[2][k2];
                 double wt = cw[0][k0];
                 if (ND > 1) wt = wt * cw[1][k1];
                 if (ND > 2) wt = wt * cw[2][k2];
-                v = v + wt * ec[cj[0][k0] + m0 * (cj[1][k1] + m1 * cj[2][k2])];
+                const int64_t q = cj[0][k0] + m0 * (cj[1][k1] + m1 * cj[2][k2]);
+                const double e = ec[on ? q : 0];
+                v = on ? v + wt * e : v;
             }
     x[t] = x[t] + v;
 }
@@ -163,10 +214,26 @@ using namespace srj;
 struct srj_mg {
     int L = 0;
     int ndim = 1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // every level's context launches here
+    hipStream_t own = nullptr;      // made when the caller passes no stream
+    hipEvent_t ready = nullptr;     // the caller's null-stream work -> own
     std::vector<srj_ctx *> ctx;
     std::vector<double *> xb, bb;   // index 0 unused
     std::vector<int64_t> npts;
+    // V-cycles replayed from graphs: one per smoothing level, starting
+    // buffer of the finest level and the options the cycle depends on
+    struct Graph {
+        int level, pre, post, Lc, coarse_max_cycles;
+        double coarse_tol;
+        const double *x, *start;  // caller's x, finest iterate at the start
+        double *end;              // finest iterate at the end
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    // device record of the coarsest solves: count, bad status, sweeps[rec_cap]
+    void *rec = nullptr;
+    int32_t rec_cap = 0;
+    std::vector<int> prepared;      // per level: resident buffers made for this many cycles
 };
 
 namespace {
@@ -179,6 +246,10 @@ srj_status mg_free(srj_mg *g)
     for (srj_ctx *c : g->ctx) srj_destroy(c);
     for (double *p : g->xb) (void)hipFree(p);
     for (double *p : g->bb) (void)hipFree(p);
+    for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+    (void)hipFree(g->rec);
+    if (g->ready) (void)hipEventDestroy(g->ready);
+    if (g->own) (void)hipStreamDestroy(g->own);
     delete g;
     return SRJ_OK;
 }
@@ -189,18 +260,46 @@ struct MgRun {
     int Lc;                 // coarsest level used
     std::vector<double *> cur;
     srj_mg_result *res;
+    bool graph = false;     // launches only: captured, the counters kept on the device
 };
 
-srj_status launch_restrict(const srj_ctx *c, const double *x, double *bc, hipStream_t s)
+// Options of the coarsest solve: SRJ with Algorithm 1 from zero to a
+// relative tolerance, clamped to the context's scheme family as srj_solve
+// clamps them.
+srj_solve_opts coarse_opts(const srj_ctx *c, const srj_mg_opts *o)
+{
+    srj_solve_opts so;
+    srj_default_opts(&so);
+    so.rule = SRJ_RULE_HEURISTIC;
+    so.tol_mode = SRJ_TOL_RELATIVE;
+    so.tol = o->coarse_tol;
+    so.max_cycles = o->coarse_max_cycles;
+    so.max_sweeps = 50000000;
+    so.max_level = std::min(SRJ_NUM_LEVELS - 1, c->nlevels - 1);
+    return so;
+}
+
+// bc = R (b - A x), through the fine residual in r (a free buffer of the
+// fine level's size)
+srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double *bc, hipStream_t s)
 {
     const DevProblem &P = c->P;
     const int64_t m0 = P.ndim > 0 ? (P.n0 - 1) / 2 : 1, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
-    const unsigned nb = blocks_for(m0 * m1 * m2);
+    const unsigned nf = blocks_for(P.n0 * P.n1 * P.n2), nb = blocks_for(m0 * m1 * m2);
     switch (P.ndim) {
-    case 1: hipLaunchKernelGGL(k_restrict_residual<1>, dim3(nb), dim3(kMgBlock), 0, s, P, x, bc, m0, m1, m2); break;
-    case 2: hipLaunchKernelGGL(k_restrict_residual<2>, dim3(nb), dim3(kMgBlock), 0, s, P, x, bc, m0, m1, m2); break;
-    default: hipLaunchKernelGGL(k_restrict_residual<3>, dim3(nb), dim3(kMgBlock), 0, s, P, x, bc, m0, m1, m2); break;
+    case 1:
+        hipLaunchKernelGGL(k_mg_residual<1>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
+        hipLaunchKernelGGL(k_mg_restrict<1>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_mg_residual<2>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
+        hipLaunchKernelGGL(k_mg_restrict<2>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        break;
+    default:
+        hipLaunchKernelGGL(k_mg_residual<3>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
+        hipLaunchKernelGGL(k_mg_restrict<3>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        break;
     }
     SRJ_HIP_CHECK(hipGetLastError());
     return SRJ_OK;
@@ -232,14 +331,17 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(g->npts[l])), dim3(kMgBlock), 0, g->stream, x,
                            g->npts[l]);
         SRJ_HIP_CHECK(hipGetLastError());
-        srj_solve_opts so;
-        srj_default_opts(&so);
-        so.rule = SRJ_RULE_HEURISTIC;
-        so.tol_mode = SRJ_TOL_RELATIVE;
-        so.tol = run.o->coarse_tol;
-        so.max_cycles = run.o->coarse_max_cycles;
-        so.max_sweeps = 50000000;
-        so.max_level = SRJ_NUM_LEVELS - 1;
+        const srj_solve_opts so = coarse_opts(c, run.o);
+        if (run.graph) {
+            ResidentRecord rec;
+            char *base = static_cast<char *>(g->rec);
+            rec.count = reinterpret_cast<int32_t *>(base);
+            rec.bad = reinterpret_cast<int32_t *>(base) + 1;
+            rec.sweeps = reinterpret_cast<int64_t *>(base + 8);
+            rec.cap = g->rec_cap;
+            run.cur[l] = x;
+            return resident_launch_recorded(c, x, &so, rec);
+        }
         srj_solve_result r;
         srj_status st = srj_solve(c, x, &so, &r, nullptr, nullptr);
         if (st != SRJ_OK && st != SRJ_ERR_NOT_CONVERGED) return st;
@@ -265,7 +367,12 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
     };
     srj_status st = pair_smooth(run.o->pre);
     if (st != SRJ_OK) return st;
-    if ((st = launch_restrict(c, run.cur[l], g->bb[l + 1], g->stream)) != SRJ_OK) return st;
+    {
+        // the level's other buffer holds nothing live until the post-smoothing
+        double *a = l == 0 ? x0 : g->xb[l];
+        double *spare = run.cur[l] == a ? c->ws : a;
+        if ((st = launch_restrict(c, run.cur[l], spare, g->bb[l + 1], g->stream)) != SRJ_OK) return st;
+    }
     // the coarse correction starts from zero
     double *xc = g->xb[l + 1];
     hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(g->npts[l + 1])), dim3(kMgBlock), 0, g->stream, xc,
@@ -275,8 +382,85 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
     if ((st = vcycle(run, l + 1, level, x0)) != SRJ_OK) return st;
     if ((st = launch_prolong(c, run.cur[l + 1], run.cur[l], g->stream)) != SRJ_OK) return st;
     if ((st = pair_smooth(run.o->post)) != SRJ_OK) return st;
-    if (l == 0) run.res->sweeps += sw;
-    run.res->work += (double)sw * frac;
+    if (!run.graph) {
+        if (l == 0) run.res->sweeps += sw;
+        run.res->work += (double)sw * frac;
+    }
+    return SRJ_OK;
+}
+
+// V-cycles can be replayed from graphs when the coarsest grid is solved in
+// one workgroup and nothing times the launches.
+bool graphable(const srj_mg *g, int Lc)
+{
+    const srj_ctx *c = g->ctx[Lc];
+    if (!c->resident || !resident_fits(c->P)) return false;
+    for (int l = 0; l <= Lc; ++l)
+        if (g->ctx[l]->profiling) return false;
+    return true;
+}
+
+// The V-cycle at smoothing level `level` from the finest iterate run.cur[0],
+// captured once per (level, starting buffer, options) and replayed; leaves
+// run.cur[0] at the finest iterate it ends on.
+srj_status vcycle_graph(MgRun &run, int level, double *x)
+{
+    srj_mg *g = run.g;
+    const srj_mg_opts *o = run.o;
+    double *start = run.cur[0];
+    for (const auto &e : g->graphs)
+        if (e.level == level && e.pre == o->pre && e.post == o->post && e.Lc == run.Lc &&
+            e.coarse_max_cycles == o->coarse_max_cycles && e.coarse_tol == o->coarse_tol &&
+            e.x == x && e.start == start) {
+            SRJ_HIP_CHECK(hipGraphLaunch(e.exec, g->stream));
+            run.cur[0] = e.end;
+            return SRJ_OK;
+        }
+    SRJ_HIP_CHECK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    const srj_status st = vcycle(run, 0, level, x);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (st != SRJ_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SRJ_ERR_HIP, std::string("V-cycle capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(SRJ_ERR_HIP, std::string("V-cycle graph: ") + hipGetErrorString(ei));
+    g->graphs.push_back({level, o->pre, o->post, run.Lc, o->coarse_max_cycles, o->coarse_tol, x,
+                         start, run.cur[0], exec});
+    SRJ_HIP_CHECK(hipGraphLaunch(exec, g->stream));
+    return SRJ_OK;
+}
+
+// Device record and coarsest-context buffers for V-cycles replayed from
+// graphs; drops the graphs when the record moves.
+srj_status prepare_graphs(srj_mg *g, const srj_mg_opts *o, int Lc)
+{
+    if (g->rec_cap < o->max_vcycles) {
+        for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+        g->graphs.clear();
+        (void)hipFree(g->rec);
+        g->rec = nullptr;
+        g->rec_cap = 0;
+        if (hipMalloc(&g->rec, 8 + sizeof(int64_t) * (size_t)o->max_vcycles) != hipSuccess) {
+            g->rec = nullptr;
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the multigrid record");
+        }
+        g->rec_cap = o->max_vcycles;
+    }
+    if (g->prepared[Lc] < o->coarse_max_cycles) {
+        // the graphs hold the buffers' addresses: reallocation drops them
+        for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+        g->graphs.clear();
+        srj_status st = resident_prepare(g->ctx[Lc], o->coarse_max_cycles);
+        if (st != SRJ_OK) return st;
+        g->prepared[Lc] = o->coarse_max_cycles;
+    }
+    // hipMemsetAsync stays outside the captured graphs
+    SRJ_HIP_CHECK(hipMemsetAsync(g->rec, 0, 8, g->stream));
     return SRJ_OK;
 }
 
@@ -347,6 +531,18 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
     g->L = (int)dims.size();
     g->ndim = p->ndim;
     g->stream = static_cast<hipStream_t>(hip_stream);
+    if (!g->stream) {
+        // V-cycles are captured into graphs, which the null stream cannot
+        // do: the levels run on a stream of their own, ordered after the
+        // caller's null-stream work at the start of every solve
+        if (hipStreamCreateWithFlags(&g->own, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&g->ready, hipEventDisableTiming) != hipSuccess) {
+            mg_free(g);
+            return fail(SRJ_ERR_HIP, "multigrid stream");
+        }
+        g->stream = g->own;
+    }
+    g->prepared.assign(g->L, 0);
     g->ctx.assign(g->L, nullptr);
     g->xb.assign(g->L, nullptr);
     g->bb.assign(g->L, nullptr);
@@ -367,7 +563,7 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             q.b = g->bb[l];
         }
         srj_ctx *c = nullptr;
-        st = srj_setup(&q, hip_stream, &c);
+        st = srj_setup(&q, g->stream, &c);
         if (st != SRJ_OK) {
             const std::string msg = srj_last_error();
             mg_free(g);
@@ -392,6 +588,13 @@ srj_status srj_mg_solve(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_resul
     MgRun run{g, o, std::min(g->L, o->max_levels) - 1, std::vector<double *>(g->L, nullptr), res};
     res->levels = run.Lc + 1;
     run.cur[0] = x;
+    if (g->own) {
+        SRJ_HIP_CHECK(hipEventRecord(g->ready, nullptr));
+        SRJ_HIP_CHECK(hipStreamWaitEvent(g->own, g->ready, 0));
+    }
+    run.graph = graphable(g, run.Lc);
+    if (run.graph && (st = prepare_graphs(g, o, run.Lc)) != SRJ_OK) return st;
+    std::vector<int> vlevels;
 
     double norm0 = 0.0;
     if ((st = residual_norm(c0, x, &norm0)) != SRJ_OK) return st;
@@ -410,7 +613,9 @@ srj_status srj_mg_solve(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_resul
     } else {
         for (int v = 0; v < o->max_vcycles; ++v) {
             const int lv = o->rule == SRJ_RULE_FIXED ? o->start_level : level;
-            if ((st = vcycle(run, 0, lv, x)) != SRJ_OK) return st;
+            st = run.graph ? vcycle_graph(run, lv, x) : vcycle(run, 0, lv, x);
+            if (st != SRJ_OK) return st;
+            vlevels.push_back(lv);
             double norm = 0.0;
             if ((st = residual_norm(c0, run.cur[0], &norm)) != SRJ_OK) return st;
             if (levels_out) levels_out[v] = lv;
@@ -437,6 +642,28 @@ srj_status srj_mg_solve(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_resul
         SRJ_HIP_CHECK(hipMemcpyAsync(x, run.cur[0], sizeof(double) * (size_t)g->npts[0],
                                      hipMemcpyDeviceToDevice, g->stream));
     SRJ_HIP_CHECK(hipStreamSynchronize(g->stream));
+    if (run.graph && !vlevels.empty()) {
+        // the counters in the order the launches made them: per V-cycle the
+        // coarsest solve, then the levels from the coarsest up
+        int32_t head[2] = {0, 0};
+        SRJ_HIP_CHECK(hipMemcpy(head, g->rec, sizeof(head), hipMemcpyDeviceToHost));
+        if (head[0] != (int32_t)vlevels.size())
+            return fail(SRJ_ERR_HIP, "multigrid record holds a different number of coarsest solves");
+        std::vector<int64_t> cs(vlevels.size());
+        SRJ_HIP_CHECK(hipMemcpy(cs.data(), static_cast<char *>(g->rec) + 8,
+                                sizeof(int64_t) * cs.size(), hipMemcpyDeviceToHost));
+        for (size_t v = 0; v < vlevels.size(); ++v) {
+            res->coarse_sweeps += cs[v];
+            res->work += (double)cs[v] * ((double)g->npts[run.Lc] / (double)g->npts[0]);
+            for (int l = run.Lc - 1; l >= 0; --l) {
+                const int64_t sw = (int64_t)(o->pre + o->post) *
+                                   (int64_t)g->ctx[l]->factors[vlevels[v]].size();
+                if (l == 0) res->sweeps += sw;
+                res->work += (double)sw * ((double)g->npts[l] / (double)g->npts[0]);
+            }
+        }
+        if (head[1] != 0) return fail((srj_status)head[1], "coarsest-grid solve failed");
+    }
     if (status == SRJ_ERR_NONFINITE) return fail(status, "non-finite residual norm");
     if (status == SRJ_ERR_NOT_CONVERGED) return fail(status, "V-cycle cap reached");
     return SRJ_OK;

@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
                                                        const int32_t *__restrict__ levelM,
                                                        ResidentArgs a, int32_t *__restrict__ levels_hist,
                                                        double *__restrict__ norms_hist,
-                                                       ResidentOut *__restrict__ out)
+                                                       ResidentOut *__restrict__ out,
+                                                       ResidentRecord rec)
 {
     extern __shared__ double lds[];
     const int64_t N = P.n0 * P.n1 * P.n2;
@@ -219,6 +220,13 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
         out->r0 = r0;
         out->r_final = last;
         out->min_margin = margin;
+        if (rec.sweeps) {
+            // appended to the caller's device record in stream order
+            const int32_t i = *rec.count;
+            if (i < rec.cap) rec.sweeps[i] = sweeps;
+            *rec.count = i + 1;
+            if (status != SRJ_OK && status != SRJ_ERR_NOT_CONVERGED) *rec.bad = status;
+        }
     }
 }
 
@@ -226,8 +234,11 @@ __global__ __launch_bounds__(kThreads) void k_resident(DevProblem P, double *__r
 
 bool resident_fits(const DevProblem &P) { return P.n0 * P.n1 * P.n2 <= kResidentMax; }
 
-srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
-                          int32_t *levels_out, double *norms_out)
+namespace {
+
+constexpr size_t kOutBytes = 256, kLmBytes = 128, kOffsBytes = 128;
+
+ResidentArgs resident_args(const srj_solve_opts *o)
 {
     ResidentArgs a{};
     a.rule = o->rule;
@@ -239,12 +250,13 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
     a.max_sweeps = o->max_sweeps;
     a.tol = o->tol;
     a.r0_given = o->r0;
-    const int64_t N = c->npoints;
-    std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
-    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
-    // device buffers kept by the context from one solve to the next: the
-    // result record, the level sizes and offsets (fixed size), the histories
-    constexpr size_t kOutBytes = 256, kLmBytes = 128, kOffsBytes = 128;
+    return a;
+}
+
+// Device buffers kept by the context from one solve to the next: the result
+// record, the level sizes and offsets (fixed size), the histories.
+srj_status resident_buffers(srj_ctx *c, int max_cycles)
+{
     static_assert(sizeof(ResidentOut) <= kOutBytes, "result record");
     static_assert(sizeof(int32_t) * SRJ_NUM_LEVELS <= kLmBytes, "level sizes");
     static_assert(sizeof(int32_t) * (SRJ_NUM_LEVELS + 1) <= kOffsBytes, "level offsets");
@@ -254,20 +266,81 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
         c->rs_fixed = nullptr;
         return fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
     }
-    if (c->rs_cap < o->max_cycles) {
+    if (c->rs_cap < max_cycles) {
         (void)hipFree(c->rs_levels);
         (void)hipFree(c->rs_norms);
         c->rs_levels = nullptr;
         c->rs_norms = nullptr;
         c->rs_cap = 0;
-        if (hipMalloc(&c->rs_levels, sizeof(int32_t) * (size_t)o->max_cycles) != hipSuccess ||
-            hipMalloc(&c->rs_norms, sizeof(double) * ((size_t)o->max_cycles + 1)) != hipSuccess) {
+        if (hipMalloc(&c->rs_levels, sizeof(int32_t) * (size_t)max_cycles) != hipSuccess ||
+            hipMalloc(&c->rs_norms, sizeof(double) * ((size_t)max_cycles + 1)) != hipSuccess) {
             (void)hipFree(c->rs_levels);
             c->rs_levels = nullptr;
             c->rs_norms = nullptr;
             return fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
         }
-        c->rs_cap = o->max_cycles;
+        c->rs_cap = max_cycles;
+    }
+    return SRJ_OK;
+}
+
+std::vector<int32_t> level_sizes(const srj_ctx *c)
+{
+    std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
+    return lmh;
+}
+
+size_t resident_shmem(int64_t N) { return sizeof(double) * (size_t)(2 * N + kThreads / 64 + 1); }
+
+// one point per thread up to 1024 points (latency hiding across waves), then
+// up to kPPT points per thread
+int resident_threads(int64_t N)
+{
+    return (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
+}
+
+}  // namespace
+
+srj_status resident_prepare(srj_ctx *c, int max_cycles)
+{
+    srj_status st = resident_buffers(c, max_cycles);
+    if (st != SRJ_OK) return st;
+    char *fixed = static_cast<char *>(c->rs_fixed);
+    const std::vector<int32_t> lmh = level_sizes(c);
+    SRJ_HIP_CHECK(hipMemcpy(fixed + kOutBytes, lmh.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
+                            hipMemcpyHostToDevice));
+    SRJ_HIP_CHECK(hipMemcpy(fixed + kOutBytes + kLmBytes, c->offsets.data(),
+                            sizeof(int32_t) * c->offsets.size(), hipMemcpyHostToDevice));
+    return SRJ_OK;
+}
+
+srj_status resident_launch_recorded(srj_ctx *c, double *x, const srj_solve_opts *o,
+                                    const ResidentRecord &rec)
+{
+    if (o->tol_mode == SRJ_TOL_UPDATE_INF || o->max_cycles > c->rs_cap || !c->rs_fixed)
+        return fail(SRJ_ERR_INVALID, "resident launch: buffers not prepared for these options");
+    char *fixed = static_cast<char *>(c->rs_fixed);
+    ResidentOut *dout = reinterpret_cast<ResidentOut *>(fixed);
+    const int32_t *lm = reinterpret_cast<const int32_t *>(fixed + kOutBytes);
+    const int32_t *offs = reinterpret_cast<const int32_t *>(fixed + kOutBytes + kLmBytes);
+    const int64_t N = c->npoints;
+    hipLaunchKernelGGL(k_resident<false>, dim3(1), dim3(resident_threads(N)), resident_shmem(N),
+                       c->stream, c->P, x, c->omega_dev, offs, lm, resident_args(o), c->rs_levels,
+                       c->rs_norms, dout, rec);
+    SRJ_HIP_CHECK(hipGetLastError());
+    return SRJ_OK;
+}
+
+srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
+                          int32_t *levels_out, double *norms_out)
+{
+    const ResidentArgs a = resident_args(o);
+    const int64_t N = c->npoints;
+    const std::vector<int32_t> lmh = level_sizes(c);
+    {
+        const srj_status sb = resident_buffers(c, o->max_cycles);
+        if (sb != SRJ_OK) return sb;
     }
     int32_t *lh = c->rs_levels;
     double *nh = c->rs_norms;
@@ -283,18 +356,16 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
         if (e == hipSuccess)
             e = hipMemcpyAsync(offs, c->offsets.data(), sizeof(int32_t) * c->offsets.size(),
                                hipMemcpyHostToDevice, c->stream);
-        const size_t shmem = sizeof(double) * (size_t)(2 * N + kThreads / 64 + 1);
+        const size_t shmem = resident_shmem(N);
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
         if (e == hipSuccess) {
-            // one point per thread up to 1024 points (latency hiding across
-            // waves), then up to kPPT points per thread
-            const int threads = (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
+            const int threads = resident_threads(N);
             if (a.tol_mode == SRJ_TOL_UPDATE_INF)
                 hipLaunchKernelGGL(k_resident<true>, dim3(1), dim3(threads), shmem, c->stream, c->P,
-                                   x, c->omega_dev, offs, lm, a, lh, nh, dout);
+                                   x, c->omega_dev, offs, lm, a, lh, nh, dout, ResidentRecord{});
             else
                 hipLaunchKernelGGL(k_resident<false>, dim3(1), dim3(threads), shmem, c->stream,
-                                   c->P, x, c->omega_dev, offs, lm, a, lh, nh, dout);
+                                   c->P, x, c->omega_dev, offs, lm, a, lh, nh, dout, ResidentRecord{});
             e = hipGetLastError();
         }
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
