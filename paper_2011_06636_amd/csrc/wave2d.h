@@ -25,6 +25,11 @@
 
 namespace srj {
 
+// Rows loaded ahead of the one being swept: a wave keeps the loads of the
+// next kWavePrefetch rows in flight while it sweeps, so that one wave has
+// several rows' worth of HBM requests outstanding instead of one.
+constexpr int kWavePrefetch = 8;
+
 template <class V, int OH, int T>
 __device__ __forceinline__ void wave2d_run(int64_t n0, int64_t n1, const typename V::T *__restrict__ x,
                                            typename V::T *__restrict__ xo,
@@ -35,6 +40,7 @@ __device__ __forceinline__ void wave2d_run(int64_t n0, int64_t n1, const typenam
     using A = typename V::A;
     constexpr int R = OH + 2 * T;  // rows of the strip chunk, halo included
     constexpr int OW = 64 - 2 * T;
+    constexpr int PF = kWavePrefetch;
     const int64_t gx = (int64_t)tx * OW - T + lane;
     const int64_t gy0 = (int64_t)ty * OH - T;
     const bool col_in = gx >= 0 && gx < n0;
@@ -53,21 +59,40 @@ __device__ __forceinline__ void wave2d_run(int64_t n0, int64_t n1, const typenam
     for (int j = 0; j < T; ++j) W[j][0] = W[j][1] = W[j][2] = A(0);
 #pragma unroll
     for (int j = 0; j <= 2 * T; ++j) Bw[j] = A(0);
-    const int64_t base = gy0 * n0 + gx;
+    // Loads are unconditional: a point outside the grid reads a point inside
+    // it (row and column clamped), and when the row is used a select
+    // replaces the value by the ghost's zero, so the compiler never branches
+    // around a load and waits for it alone.  Rows past the chunk read its
+    // last row and are dropped.
+    const int64_t cx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx);
+    auto load_row = [&](int i, typename V::T &xv, typename V::T &bv) {
+        const int64_t gy = gy0 + i;
+        const int64_t cy = gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy);
+        const int64_t p = cy * n0 + cx;
+        xv = x[p];
+        bv = b[p];
+    };
+    auto row_ok = [&](int i) {
+        const int64_t gy = gy0 + i;
+        return i < R && (interior || (col_in && gy >= 0 && gy < n1));
+    };
+    typename V::T xq[PF], bq[PF];  // raw rows i .. i + PF - 1
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_row(j, xq[j], bq[j]);
+#pragma unroll
     for (int i = 0; i < R + T; ++i) {
         // b of row i enters the ring
 #pragma unroll
         for (int j = 2 * T; j > 0; --j) Bw[j] = Bw[j - 1];
-        A xin = A(0), bin = A(0);
-        if (i < R) {
-            const int64_t gy = gy0 + i;
-            if (interior || (col_in && gy >= 0 && gy < n1)) {
-                const int64_t p = base + (int64_t)i * n0;
-                xin = V::load(x[p]);
-                bin = V::load(b[p]);
-            }
+        const bool ok = row_ok(i);
+        const A xin = ok ? V::load(xq[0]) : A(0);
+        Bw[0] = ok ? V::load(bq[0]) : A(0);
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) {
+            xq[j] = xq[j + 1];
+            bq[j] = bq[j + 1];
         }
-        Bw[0] = bin;
+        load_row(i + PF, xq[PF - 1], bq[PF - 1]);
         A nxt[T + 1];
 #pragma unroll
         for (int k = 1; k <= T; ++k) {
