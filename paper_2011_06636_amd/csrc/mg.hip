@@ -24,6 +24,8 @@
 #include <vector>
 
 #include "internal.h"
+#include "resident_run.h"
+#include "rowsum.h"
 
 #pragma clang fp contract(off)
 
@@ -195,6 +197,235 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
     x[t] = x[t] + v;
 }
 
+// The coarse end of the V-cycle in three launches: every level from the
+// first one of at most kTailMaxPoints points down to the coarsest is held in
+// one workgroup's LDS (per level x, its ping-pong partner and b) by
+// k_mg_tail<true> (pre-smoothing, fine residual and restriction level by
+// level down), the coarsest grid is solved by the resident solver, and
+// k_mg_tail<false> interpolates and post-smooths level by level up.  The
+// operations are those of the kernels above and of the sweep kernels, in
+// their order, so the values are the same bits.  One thread per point (every
+// tail grid has at most kThreads points); the workgroup synchronises after
+// every pass.
+constexpr int kTailMaxLevels = 12;
+constexpr int64_t kTailMaxPoints = kThreads;
+constexpr size_t kTailLdsDoubles = 8192;  // 64 KiB
+
+struct TailLevel {
+    DevProblem P;       // the level's sizes and constants (b lives in LDS)
+    const double *w;    // this V-cycle's smoothing factors for the level
+    int32_t M;          // their number
+    int32_t off;        // LDS offset of x; its partner at off + N, b at off + 2 N
+};
+
+struct TailArgs {
+    int32_t count, pre, post, pad;
+    TailLevel lv[kTailMaxLevels];
+    double *xg[kTailMaxLevels];  // each level's correction in global memory
+    double *bg[kTailMaxLevels];  // and its right-hand side
+};
+
+// Per-level values of the tail, copied into LDS once: every pass reads its
+// level's sizes and constants from there.
+struct TailTab {
+    int32_t n0, n1, n2, nd, N, off, M, pad;
+    double c0, c1, c2, D, Dinv;
+    const double *w;
+};
+
+// DOWN: from the first tail level's b (in bg[0]) down to the coarsest
+// grid's b, leaving every level's pre-smoothed correction and b in xg / bg
+// (the coarsest correction zero); !DOWN: from those and the coarsest
+// solution back up, the first level's correction to xg[0].
+template <bool DOWN>
+__global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
+{
+    extern __shared__ double lds[];
+    __shared__ TailTab tab[kTailMaxLevels];
+    const int p = threadIdx.x;
+    if (p < t.count) {
+        const TailLevel &L = t.lv[p];
+        TailTab e;
+        e.n0 = (int32_t)L.P.n0;
+        e.n1 = (int32_t)L.P.n1;
+        e.n2 = (int32_t)L.P.n2;
+        e.nd = L.P.ndim;
+        e.N = e.n0 * e.n1 * e.n2;
+        e.off = L.off;
+        e.M = L.M;
+        e.pad = 0;
+        e.c0 = L.P.c[0];
+        e.c1 = L.P.c[1];
+        e.c2 = L.P.c[2];
+        e.D = L.P.dconst;
+        e.Dinv = L.P.dinvconst;
+        e.w = L.w;
+        tab[p] = e;
+    }
+    __syncthreads();
+    // which of a level's two buffers holds its iterate: bit l of par
+    uint32_t par = 0;
+    auto xbuf = [&](int l) { return lds + tab[l].off + (((par >> l) & 1) ? tab[l].N : 0); };
+    auto spare = [&](int l) { return lds + tab[l].off + (((par >> l) & 1) ? 0 : tab[l].N); };
+    auto bbuf = [&](int l) { return lds + tab[l].off + 2 * tab[l].N; };
+    auto coords = [&](const TailTab &e, int q, int &i0, int &i1, int &i2) {
+        const int a0 = q / e.n0;
+        i0 = q - a0 * e.n0;
+        i1 = a0 % e.n1;
+        i2 = a0 / e.n1;
+    };
+    // (A u)_p in the library's order: D u_p, then per axis the lower and the
+    // upper neighbour, terms of ghost neighbours omitted
+    auto rows = [&](const TailTab &e, const double *u, int q, int i0, int i1, int i2) {
+        double s = e.D * u[q];
+        if (i0 > 0) s = s - e.c0 * u[q - 1];
+        if (i0 < e.n0 - 1) s = s - e.c0 * u[q + 1];
+        if (e.nd >= 2) {
+            if (i1 > 0) s = s - e.c1 * u[q - e.n0];
+            if (i1 < e.n1 - 1) s = s - e.c1 * u[q + e.n0];
+        }
+        if (e.nd >= 3) {
+            const int s2 = e.n0 * e.n1;
+            if (i2 > 0) s = s - e.c2 * u[q - s2];
+            if (i2 < e.n2 - 1) s = s - e.c2 * u[q + s2];
+        }
+        return s;
+    };
+    // nu whole cycles of the level's scheme, as the sweep kernels form them
+    auto smooth = [&](int l, int nu) {
+        const TailTab e = tab[l];
+        int i0 = 0, i1 = 0, i2 = 0;
+        if (p < e.N) coords(e, p, i0, i1, i2);
+        const double *b = bbuf(l);
+        const double bp = p < e.N ? b[p] : 0.0;
+        for (int k = 0; k < nu; ++k) {
+            double wnext = e.w[0];
+            for (int j = 0; j < e.M; ++j) {
+                const double wj = wnext;
+                if (j + 1 < e.M) wnext = e.w[j + 1];  // in flight during this sweep
+                const double *cur = xbuf(l);
+                double *nxt = spare(l);
+                if (p < e.N) {
+                    const double s = rows(e, cur, p, i0, i1, i2);
+                    const double r = bp - s;
+                    const double tt = e.Dinv * r;
+                    nxt[p] = cur[p] + wj * tt;
+                }
+                __syncthreads();
+                par ^= 1u << l;
+            }
+        }
+    };
+    if constexpr (DOWN) {
+        if (p < tab[0].N) {
+            bbuf(0)[p] = t.bg[0][p];
+            xbuf(0)[p] = 0.0;
+        }
+        __syncthreads();
+        for (int l = 0; l + 1 < t.count; ++l) {
+            smooth(l, t.pre);
+            // fine residual into the level's spare buffer, then full weighting
+            const TailTab e = tab[l], ec = tab[l + 1];
+            double *r = spare(l);
+            if (p < e.N) {
+                int i0, i1, i2;
+                coords(e, p, i0, i1, i2);
+                r[p] = bbuf(l)[p] - rows(e, xbuf(l), p, i0, i1, i2);
+            }
+            __syncthreads();
+            if (p < ec.N) {
+                int I0, I1, I2;
+                coords(ec, p, I0, I1, I2);
+                const int s1 = e.n0, s2 = e.n0 * e.n1;
+                const int c = (2 * I0 + 1) + (e.nd > 1 ? s1 * (2 * I1 + 1) : 0) +
+                              (e.nd > 2 ? s2 * (2 * I2 + 1) : 0);
+                double sum = 0.0;
+                for (int a2 = (e.nd > 2 ? -1 : 0); a2 <= (e.nd > 2 ? 1 : 0); ++a2)
+                    for (int a1 = (e.nd > 1 ? -1 : 0); a1 <= (e.nd > 1 ? 1 : 0); ++a1)
+#pragma unroll
+                        for (int a0 = -1; a0 <= 1; ++a0) {
+                            double wt = full_weight(a0);
+                            if (e.nd > 1) wt = wt * full_weight(a1);
+                            if (e.nd > 2) wt = wt * full_weight(a2);
+                            sum = sum + wt * r[c + a0 + s1 * a1 + s2 * a2];
+                        }
+                bbuf(l + 1)[p] = sum;
+                xbuf(l + 1)[p] = 0.0;
+            }
+            __syncthreads();
+        }
+        for (int l = 0; l < t.count; ++l)
+            if (p < tab[l].N) {
+                t.xg[l][p] = xbuf(l)[p];
+                if (l > 0) t.bg[l][p] = bbuf(l)[p];
+            }
+    } else {
+        for (int l = 0; l < t.count; ++l)
+            if (p < tab[l].N) {
+                xbuf(l)[p] = t.xg[l][p];
+                if (l + 1 < t.count) bbuf(l)[p] = t.bg[l][p];
+            }
+        __syncthreads();
+        for (int l = t.count - 2; l >= 0; --l) {
+            // x += P e: per axis the candidates in increasing order
+            const TailTab e = tab[l], ec = tab[l + 1];
+            const double *ev = xbuf(l + 1);
+            double *x = xbuf(l);
+            if (p < e.N) {
+                int ii[3];
+                coords(e, p, ii[0], ii[1], ii[2]);
+                const int mm[3] = {ec.n0, ec.n1, ec.n2};
+                int cj[3][2];
+                double cw[3][2];
+                bool has[3][2];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d >= e.nd) {
+                        cj[d][0] = cj[d][1] = 0;
+                        cw[d][0] = 1.0;
+                        cw[d][1] = 0.0;
+                        has[d][0] = true;
+                        has[d][1] = false;
+                    } else if (ii[d] & 1) {
+                        cj[d][0] = (ii[d] - 1) / 2;
+                        cj[d][1] = 0;
+                        cw[d][0] = 1.0;
+                        cw[d][1] = 0.0;
+                        has[d][0] = true;
+                        has[d][1] = false;
+                    } else {
+                        const int J = ii[d] / 2;
+                        cj[d][0] = J - 1;
+                        cj[d][1] = J;
+                        cw[d][0] = cw[d][1] = 0.5;
+                        has[d][0] = J - 1 >= 0;
+                        has[d][1] = J < mm[d];
+                    }
+                }
+                double v = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < 2; ++k2)
+#pragma unroll
+                    for (int k1 = 0; k1 < 2; ++k1)
+#pragma unroll
+                        for (int k0 = 0; k0 < 2; ++k0) {
+                            const bool on = has[0][k0] && has[1][k1] && has[2][k2];
+                            double wt = cw[0][k0];
+                            if (e.nd > 1) wt = wt * cw[1][k1];
+                            if (e.nd > 2) wt = wt * cw[2][k2];
+                            const int q = cj[0][k0] + mm[0] * (cj[1][k1] + mm[1] * cj[2][k2]);
+                            const double val = ev[on ? q : 0];
+                            v = on ? v + wt * val : v;
+                        }
+                x[p] = x[p] + v;
+            }
+            __syncthreads();
+            smooth(l, t.post);
+        }
+        if (p < tab[0].N) t.xg[0][p] = xbuf(0)[p];
+    }
+}
+
 __global__ void k_mg_zero(double *__restrict__ x, int64_t n)
 {
     const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
@@ -261,6 +492,7 @@ struct MgRun {
     std::vector<double *> cur;
     srj_mg_result *res;
     bool graph = false;     // launches only: captured, the counters kept on the device
+    int tail = -1;          // first level of the one-workgroup tail (graph mode), or -1
 };
 
 // Options of the coarsest solve: SRJ with Algorithm 1 from zero to a
@@ -320,9 +552,67 @@ srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStre
     return SRJ_OK;
 }
 
+// The levels from run.tail down in one launch of k_mg_tail: b of the first
+// one is g->bb[run.tail], its correction goes to g->xb[run.tail].
+srj_status launch_tail(MgRun &run, int level)
+{
+    srj_mg *g = run.g;
+    const int Ls = run.tail, K = run.Lc - Ls + 1;
+    TailArgs t{};
+    t.count = K;
+    t.pre = run.o->pre;
+    t.post = run.o->post;
+    int32_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        srj_ctx *c = g->ctx[Ls + k];
+        t.lv[k].P = c->P;
+        t.lv[k].w = c->omega_dev + c->offsets[level];
+        t.lv[k].M = (int32_t)c->factors[level].size();
+        t.lv[k].off = off;
+        t.xg[k] = g->xb[Ls + k];
+        t.bg[k] = g->bb[Ls + k];
+        off += (int32_t)(3 * g->npts[Ls + k]);
+    }
+    const size_t shmem = sizeof(double) * (size_t)off;
+    hipLaunchKernelGGL(k_mg_tail<true>, dim3(1), dim3(kThreads), shmem, g->stream, t);
+    SRJ_HIP_CHECK(hipGetLastError());
+    // the coarsest grid, from the zero correction the first launch left
+    ResidentRecord rec;
+    char *base = static_cast<char *>(g->rec);
+    rec.count = reinterpret_cast<int32_t *>(base);
+    rec.bad = reinterpret_cast<int32_t *>(base) + 1;
+    rec.sweeps = reinterpret_cast<int64_t *>(base + 8);
+    rec.cap = g->rec_cap;
+    srj_ctx *cc = g->ctx[run.Lc];
+    const srj_solve_opts so = coarse_opts(cc, run.o);
+    srj_status st = resident_launch_recorded(cc, g->xb[run.Lc], &so, rec);
+    if (st != SRJ_OK) return st;
+    hipLaunchKernelGGL(k_mg_tail<false>, dim3(1), dim3(kThreads), shmem, g->stream, t);
+    SRJ_HIP_CHECK(hipGetLastError());
+    run.cur[Ls] = g->xb[Ls];
+    return SRJ_OK;
+}
+
+// First level of the one-workgroup tail: the finest level of at most
+// kTailMaxPoints points below the finest grid and above the coarsest one,
+// whose levels down to the coarsest fit the tail's LDS and level count; -1
+// if there is none.
+int tail_start(const srj_mg *g, int Lc)
+{
+    for (int l = 1; l < Lc; ++l) {
+        if (g->npts[l] > kTailMaxPoints) continue;
+        int64_t doubles = 0;
+        for (int k = l; k <= Lc; ++k) doubles += 3 * g->npts[k];
+        if (doubles <= (int64_t)kTailLdsDoubles && Lc - l + 1 <= kTailMaxLevels) return l;
+        return -1;
+    }
+    return -1;
+}
+
 srj_status vcycle(MgRun &run, int l, int level, double *x0)
 {
     srj_mg *g = run.g;
+    if (run.graph && l == run.tail) return launch_tail(run, level);
     srj_ctx *c = g->ctx[l];
     const double frac = (double)g->npts[l] / (double)g->npts[0];
     if (l == run.Lc) {
@@ -373,11 +663,13 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         double *spare = run.cur[l] == a ? c->ws : a;
         if ((st = launch_restrict(c, run.cur[l], spare, g->bb[l + 1], g->stream)) != SRJ_OK) return st;
     }
-    // the coarse correction starts from zero
+    // the coarse correction starts from zero (the tail starts its own)
     double *xc = g->xb[l + 1];
-    hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(g->npts[l + 1])), dim3(kMgBlock), 0, g->stream, xc,
-                       g->npts[l + 1]);
-    SRJ_HIP_CHECK(hipGetLastError());
+    if (!(run.graph && l + 1 == run.tail)) {
+        hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(g->npts[l + 1])), dim3(kMgBlock), 0,
+                           g->stream, xc, g->npts[l + 1]);
+        SRJ_HIP_CHECK(hipGetLastError());
+    }
     run.cur[l + 1] = xc;
     if ((st = vcycle(run, l + 1, level, x0)) != SRJ_OK) return st;
     if ((st = launch_prolong(c, run.cur[l + 1], run.cur[l], g->stream)) != SRJ_OK) return st;
@@ -594,6 +886,7 @@ srj_status srj_mg_solve(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_resul
     }
     run.graph = graphable(g, run.Lc);
     if (run.graph && (st = prepare_graphs(g, o, run.Lc)) != SRJ_OK) return st;
+    if (run.graph) run.tail = tail_start(g, run.Lc);
     std::vector<int> vlevels;
 
     double norm0 = 0.0;
