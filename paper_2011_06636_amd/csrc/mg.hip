@@ -101,14 +101,16 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_residual(DevProblem P, const do
     r[t] = P.b[t] - s;
 }
 
-// Coarse right-hand side bc = R r: one thread per coarse point; the fine
+// Coarse right-hand side bc = R r (and, unless xc is null, xc = 0): one
+// thread per coarse point; the fine
 // residuals of points 2 I + 1 + a (a in {-1, 0, 1} per active axis; all lie
 // in the grid, whose active sizes are 2 m + 1) are weighted by the product
 // of the per-axis full weights and summed with axis 2 outermost and axis 0
 // innermost.
 template <int ND>
 __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restrict__ r,
-                                                          double *__restrict__ bc, int64_t n0,
+                                                          double *__restrict__ bc,
+                                                          double *__restrict__ xc, int64_t n0,
                                                           int64_t n1, int64_t m0, int64_t m1,
                                                           int64_t m2)
 {
@@ -132,6 +134,7 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restri
                 s = s + wt * r[c + a0 + s1 * a1 + s2 * a2];
             }
     bc[t] = s;
+    if (xc) xc[t] = 0.0;  // the coarse correction starts from zero
 }
 
 // x += P ec: one thread per fine point.  Per axis a fine index 2 J + 1 takes
@@ -465,6 +468,9 @@ struct srj_mg {
     void *rec = nullptr;
     int32_t rec_cap = 0;
     std::vector<int> prepared;      // per level: resident buffers made for this many cycles
+    // per level: the plan for smoothing cycles of at most two sweeps (2D
+    // grids whose default plan fuses many sweeps per launch), kind 0 if none
+    std::vector<SweepPlan> short_plan;
 };
 
 namespace {
@@ -512,8 +518,9 @@ srj_solve_opts coarse_opts(const srj_ctx *c, const srj_mg_opts *o)
 }
 
 // bc = R (b - A x), through the fine residual in r (a free buffer of the
-// fine level's size)
-srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double *bc, hipStream_t s)
+// fine level's size); xc = 0 unless xc is null
+srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double *bc, double *xc,
+                           hipStream_t s)
 {
     const DevProblem &P = c->P;
     const int64_t m0 = P.ndim > 0 ? (P.n0 - 1) / 2 : 1, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
@@ -522,15 +529,15 @@ srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double 
     switch (P.ndim) {
     case 1:
         hipLaunchKernelGGL(k_mg_residual<1>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
-        hipLaunchKernelGGL(k_mg_restrict<1>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        hipLaunchKernelGGL(k_mg_restrict<1>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
         break;
     case 2:
         hipLaunchKernelGGL(k_mg_residual<2>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
-        hipLaunchKernelGGL(k_mg_restrict<2>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        hipLaunchKernelGGL(k_mg_restrict<2>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
         break;
     default:
         hipLaunchKernelGGL(k_mg_residual<3>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
-        hipLaunchKernelGGL(k_mg_restrict<3>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, P.n0, P.n1, m0, m1, m2);
+        hipLaunchKernelGGL(k_mg_restrict<3>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
         break;
     }
     SRJ_HIP_CHECK(hipGetLastError());
@@ -647,11 +654,17 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         double *a = l == 0 ? x0 : g->xb[l];
         double *cur = run.cur[l];
         double *nxt = cur == a ? c->ws : a;
-        for (int k = 0; k < nu; ++k) {
-            srj_status st = run_sweeps(c, &cur, &nxt, level);
-            if (st != SRJ_OK) return st;
+        // cycles of one or two sweeps run as single-sweep strips (one launch
+        // per cycle either way, bit-identical), not as blocks built to fuse ten
+        const SweepPlan keep = c->plan;
+        if (g->short_plan[l].kind != 0 && c->factors[level].size() <= 2) c->plan = g->short_plan[l];
+        srj_status st = SRJ_OK;
+        for (int k = 0; k < nu && st == SRJ_OK; ++k) {
+            st = run_sweeps(c, &cur, &nxt, level);
             sw += (int64_t)c->factors[level].size();
         }
+        c->plan = keep;
+        if (st != SRJ_OK) return st;
         run.cur[l] = cur;
         return SRJ_OK;
     };
@@ -661,15 +674,12 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         // the level's other buffer holds nothing live until the post-smoothing
         double *a = l == 0 ? x0 : g->xb[l];
         double *spare = run.cur[l] == a ? c->ws : a;
-        if ((st = launch_restrict(c, run.cur[l], spare, g->bb[l + 1], g->stream)) != SRJ_OK) return st;
+        // the coarse correction starts from zero (the tail starts its own)
+        double *xz = run.graph && l + 1 == run.tail ? nullptr : g->xb[l + 1];
+        if ((st = launch_restrict(c, run.cur[l], spare, g->bb[l + 1], xz, g->stream)) != SRJ_OK)
+            return st;
     }
-    // the coarse correction starts from zero (the tail starts its own)
     double *xc = g->xb[l + 1];
-    if (!(run.graph && l + 1 == run.tail)) {
-        hipLaunchKernelGGL(k_mg_zero, dim3(blocks_for(g->npts[l + 1])), dim3(kMgBlock), 0,
-                           g->stream, xc, g->npts[l + 1]);
-        SRJ_HIP_CHECK(hipGetLastError());
-    }
     run.cur[l + 1] = xc;
     if ((st = vcycle(run, l + 1, level, x0)) != SRJ_OK) return st;
     if ((st = launch_prolong(c, run.cur[l + 1], run.cur[l], g->stream)) != SRJ_OK) return st;
@@ -835,6 +845,7 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
         g->stream = g->own;
     }
     g->prepared.assign(g->L, 0);
+    g->short_plan.assign(g->L, SweepPlan{});
     g->ctx.assign(g->L, nullptr);
     g->xb.assign(g->L, nullptr);
     g->bb.assign(g->L, nullptr);
@@ -862,6 +873,14 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             return fail(st, "multigrid level " + std::to_string(l) + ": " + msg);
         }
         g->ctx[l] = c;
+        if (c->P.ndim == 2 && c->plan.kind != 0 && c->plan.T > 2) {
+            SweepPlan sp;
+            sp.kind = 5;  // wavefront strips of 8 rows, up to two sweeps per launch
+            sp.by = 8;
+            sp.T = 2;
+            sp.occ = 1;
+            if (fused_supported(c->P, sp)) g->short_plan[l] = sp;
+        }
     }
     *out = g;
     return SRJ_OK;
