@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "rowband.h"
 #include "resident_run.h"
 #include "rowsum.h"
 
@@ -34,27 +35,10 @@ namespace srj {
 namespace {
 
 constexpr int kMgBlock = 256;
+static_assert(kMgBlock == kRowUnit, "one transfer workgroup per row unit");
 constexpr int kMgMaxLevels = 32;
 
 __device__ __forceinline__ double full_weight(int a) { return a == 0 ? 0.5 : 0.25; }
-
-// Grid coordinates of point t of an n0 x n1 x n2 grid: two 32-bit divisions
-// when the grid has fewer than 2^31 points (every grid that fits in memory
-// with its other arrays), else 64-bit ones.
-__device__ __forceinline__ void grid_coords(int64_t t, int64_t n0, int64_t n1, int64_t n2,
-                                            int64_t &i0, int64_t &i1, int64_t &i2)
-{
-    if (n0 * n1 * n2 < ((int64_t)1 << 31)) {
-        const uint32_t u = (uint32_t)t, a0 = u / (uint32_t)n0, a1 = a0 / (uint32_t)n1;
-        i0 = u - a0 * (uint32_t)n0;
-        i1 = a0 - a1 * (uint32_t)n1;
-        i2 = a1;
-    } else {
-        i0 = t % n0;
-        i1 = (t / n0) % n1;
-        i2 = t / (n0 * n1);
-    }
-}
 
 // Fine residual r = b - A x at every point, the sweep's expression: D x,
 // then the axis-0, axis-1, axis-2 neighbours below and above, each
@@ -67,11 +51,12 @@ template <int ND>
 __global__ __launch_bounds__(kMgBlock) void k_mg_residual(DevProblem P, const double *__restrict__ x,
                                                           double *__restrict__ r)
 {
-    const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
     const int64_t n0 = P.n0, n1 = P.n1, n2 = P.n2;
-    if (t >= n0 * n1 * n2) return;
-    int64_t i0, i1, i2;
-    grid_coords(t, n0, n1, n2, i0, i1, i2);
+    int64_t xb, i1, i2;
+    if (!row_unit(blockIdx.x, n0, n1, n2, xb, i1, i2)) return;
+    const int64_t i0 = xb * kRowUnit + threadIdx.x;
+    if (i0 >= n0) return;
+    const int64_t t = i0 + n0 * (i1 + n1 * i2);
     const int64_t s1 = n0, s2 = n0 * n1;
     const bool h0 = i0 > 0, h1 = i0 < n0 - 1;
     const bool h2 = ND > 1 && i1 > 0, h3 = ND > 1 && i1 < n1 - 1;
@@ -114,10 +99,11 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restri
                                                           int64_t n1, int64_t m0, int64_t m1,
                                                           int64_t m2)
 {
-    const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
-    if (t >= m0 * m1 * m2) return;
-    int64_t I0, I1, I2;
-    grid_coords(t, m0, m1, m2, I0, I1, I2);
+    int64_t xb, I1, I2;
+    if (!row_unit(blockIdx.x, m0, m1, m2, xb, I1, I2)) return;
+    const int64_t I0 = xb * kRowUnit + threadIdx.x;
+    if (I0 >= m0) return;
+    const int64_t t = I0 + m0 * (I1 + m1 * I2);
     const int64_t s1 = n0, s2 = n0 * n1;
     const int64_t c = (2 * I0 + 1) + (ND > 1 ? s1 * (2 * I1 + 1) : 0) +
                       (ND > 2 ? s2 * (2 * I2 + 1) : 0);
@@ -150,10 +136,11 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
                                                           int64_t n1, int64_t n2, int64_t m0,
                                                           int64_t m1, int64_t m2)
 {
-    const int64_t t = (int64_t)blockIdx.x * kMgBlock + threadIdx.x;
-    if (t >= n0 * n1 * n2) return;
-    int64_t ii[3];
-    grid_coords(t, n0, n1, n2, ii[0], ii[1], ii[2]);
+    int64_t xb, ii[3];
+    if (!row_unit(blockIdx.x, n0, n1, n2, xb, ii[1], ii[2])) return;
+    ii[0] = xb * kRowUnit + threadIdx.x;
+    if (ii[0] >= n0) return;
+    const int64_t t = ii[0] + n0 * (ii[1] + n1 * ii[2]);
     const int64_t mm[3] = {m0, m1, m2};
     int64_t cj[3][2];
     double cw[3][2];
@@ -525,7 +512,7 @@ srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double 
     const DevProblem &P = c->P;
     const int64_t m0 = P.ndim > 0 ? (P.n0 - 1) / 2 : 1, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
-    const unsigned nf = blocks_for(P.n0 * P.n1 * P.n2), nb = blocks_for(m0 * m1 * m2);
+    const unsigned nf = (unsigned)row_grid(P.n0, P.n1, P.n2), nb = (unsigned)row_grid(m0, m1, m2);
     switch (P.ndim) {
     case 1:
         hipLaunchKernelGGL(k_mg_residual<1>, dim3(nf), dim3(kMgBlock), 0, s, P, x, r);
@@ -549,7 +536,7 @@ srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStre
     const DevProblem &P = c->P;
     const int64_t m0 = (P.n0 - 1) / 2, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
-    const unsigned nb = blocks_for(P.n0 * P.n1 * P.n2);
+    const unsigned nb = (unsigned)row_grid(P.n0, P.n1, P.n2);
     switch (P.ndim) {
     case 1: hipLaunchKernelGGL(k_prolong_add<1>, dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, P.n2, m0, m1, m2); break;
     case 2: hipLaunchKernelGGL(k_prolong_add<2>, dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, P.n2, m0, m1, m2); break;

@@ -115,7 +115,6 @@ __device__ double *resident_run(const DevProblem &P, double *cur, double *nxt, d
         }
         return sqrt(group_sum(acc, red));
     };
-    const int hist = a.max_cycles + 1;
     const double norm0 = norm_of(cur);
     const double r0 = a.r0_given > 0.0 ? a.r0_given : norm0;
     const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
