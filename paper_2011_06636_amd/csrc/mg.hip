@@ -128,42 +128,46 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restri
 // weight 1/2 (indices outside the coarse grid are the zero boundary and
 // give no term); terms summed with axis 2 outermost, axis 0 innermost,
 // candidates in increasing order.  Two candidate slots per axis, each with
-// a flag; a missing term is skipped by a select (its load reads coarse
-// point 0), so the sum is the same as over the present terms alone.
-template <int ND>
+// a flag, and each slot's share of the coarse index formed once; a missing
+// term is skipped by a select (its load reads coarse point 0), so the sum is
+// the same as over the present terms alone.  I: the index type (32-bit
+// when both grids have fewer than 2^31 points).
+template <int ND, class I>
 __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restrict__ ec,
                                                           double *__restrict__ x, int64_t n0,
                                                           int64_t n1, int64_t n2, int64_t m0,
                                                           int64_t m1, int64_t m2)
 {
-    int64_t xb, ii[3];
-    if (!row_unit(blockIdx.x, n0, n1, n2, xb, ii[1], ii[2])) return;
-    ii[0] = xb * kRowUnit + threadIdx.x;
-    if (ii[0] >= n0) return;
-    const int64_t t = ii[0] + n0 * (ii[1] + n1 * ii[2]);
-    const int64_t mm[3] = {m0, m1, m2};
-    int64_t cj[3][2];
+    int64_t xb, y, z;
+    if (!row_unit(blockIdx.x, n0, n1, n2, xb, y, z)) return;
+    const I i0 = (I)(xb * kRowUnit + threadIdx.x);
+    if (i0 >= (I)n0) return;
+    const I ii[3] = {i0, (I)y, (I)z};
+    const I t = i0 + (I)n0 * ((I)y + (I)n1 * (I)z);
+    const I mm[3] = {(I)m0, (I)m1, (I)m2};
+    const I stride[3] = {1, (I)m0, (I)m0 * (I)m1};
+    I off[3][2];
     double cw[3][2];
     bool has[3][2];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (d >= ND) {
-            cj[d][0] = cj[d][1] = 0;
+            off[d][0] = off[d][1] = 0;
             cw[d][0] = 1.0;
             cw[d][1] = 0.0;
             has[d][0] = true;
             has[d][1] = false;
         } else if (ii[d] & 1) {
-            cj[d][0] = (ii[d] - 1) / 2;
-            cj[d][1] = 0;
+            off[d][0] = stride[d] * ((ii[d] - 1) / 2);
+            off[d][1] = 0;
             cw[d][0] = 1.0;
             cw[d][1] = 0.0;
             has[d][0] = true;
             has[d][1] = false;
         } else {
-            const int64_t J = ii[d] / 2;
-            cj[d][0] = J - 1;
-            cj[d][1] = J;
+            const I J = ii[d] / 2;
+            off[d][0] = stride[d] * (J - 1);
+            off[d][1] = stride[d] * J;
             cw[d][0] = cw[d][1] = 0.5;
             has[d][0] = J - 1 >= 0;
             has[d][1] = J < mm[d];
@@ -180,7 +184,7 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
                 double wt = cw[0][k0];
                 if (ND > 1) wt = wt * cw[1][k1];
                 if (ND > 2) wt = wt * cw[2][k2];
-                const int64_t q = cj[0][k0] + m0 * (cj[1][k1] + m1 * cj[2][k2]);
+                const I q = off[0][k0] + off[1][k1] + off[2][k2];
                 const double e = ec[on ? q : 0];
                 v = on ? v + wt * e : v;
             }
@@ -537,11 +541,16 @@ srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStre
     const int64_t m0 = (P.n0 - 1) / 2, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
     const unsigned nb = (unsigned)row_grid(P.n0, P.n1, P.n2);
+    const bool small = P.n0 * P.n1 * P.n2 < ((int64_t)1 << 31);
+#define SRJ_PROLONG(ND, I)                                                                        \
+    hipLaunchKernelGGL((k_prolong_add<ND, I>), dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, \
+                       P.n2, m0, m1, m2)
     switch (P.ndim) {
-    case 1: hipLaunchKernelGGL(k_prolong_add<1>, dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, P.n2, m0, m1, m2); break;
-    case 2: hipLaunchKernelGGL(k_prolong_add<2>, dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, P.n2, m0, m1, m2); break;
-    default: hipLaunchKernelGGL(k_prolong_add<3>, dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, P.n2, m0, m1, m2); break;
+    case 1: if (small) SRJ_PROLONG(1, int32_t); else SRJ_PROLONG(1, int64_t); break;
+    case 2: if (small) SRJ_PROLONG(2, int32_t); else SRJ_PROLONG(2, int64_t); break;
+    default: if (small) SRJ_PROLONG(3, int32_t); else SRJ_PROLONG(3, int64_t); break;
     }
+#undef SRJ_PROLONG
     SRJ_HIP_CHECK(hipGetLastError());
     return SRJ_OK;
 }
