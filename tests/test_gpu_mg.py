@@ -39,6 +39,8 @@ CASES = [
     ("3d_aniso_63x31x15", lambda: workloads.anisotropic([63, 31, 15], [1.0, 0.3, 0.05],
                                                          np.random.default_rng(5).uniform(-1, 1, (15, 31, 63))),
      dict(rule="fixed", start_level=3)),
+    # rows of at least 64 per plane are dealt to the XCDs in bands (3D)
+    ("3d_127x127x7", lambda: _rand([127, 127, 7], 9), dict()),
 ]
 
 
@@ -72,6 +74,38 @@ def test_mg_resumes_from_initial_guess(torch_cuda, orc):
     out = s.solve(s.to_device(x0), tol=1e-9)
     assert np.array_equal(out["x"].cpu().numpy(), ref["x"])
     np.testing.assert_array_equal(out["levels"], ref["levels"])
+    s.close()
+
+
+def test_mg_replays_match_across_solves_options_and_streams(torch_cuda, orc):
+    # V-cycles are replayed from graphs cached per smoothing level, starting
+    # buffer and options: a second solve on the same solver, a solve with
+    # other options, one into another x, and one on a caller's stream must
+    # each give the oracle's bits
+    import torch
+    from paper_2011_06636_amd.solver import MgSolver
+    prob = workloads.c2(n=127)
+    runs = [dict(tol=1e-10), dict(tol=1e-10), dict(tol=1e-10, pre=2, post=1),
+            dict(tol=1e-8, rule="fixed", start_level=1), dict(tol=1e-10)]
+    s = MgSolver(prob)
+    for i, kw in enumerate(runs):
+        ref = orc.mg_solve(prob, **kw)
+        x = s.zeros() if i != 4 else s.zeros().clone()
+        out = s.solve(x, **kw)
+        print(f"mg replay run {i}: {kw}", flush=True)
+        np.testing.assert_array_equal(out["levels"], ref["levels"])
+        assert out["work"] == ref["work"] and out["coarse_sweeps"] == ref["coarse_sweeps"]
+        assert np.array_equal(out["x"].cpu().numpy(), ref["x"]), i
+    s.close()
+    st = torch.cuda.Stream()
+    s = MgSolver(prob, stream=st)
+    ref = orc.mg_solve(prob, tol=1e-10)
+    for _ in range(2):
+        with torch.cuda.stream(st):
+            out = s.solve(tol=1e-10)
+        st.synchronize()
+        assert np.array_equal(out["x"].cpu().numpy(), ref["x"])
+        np.testing.assert_array_equal(out["levels"], ref["levels"])
     s.close()
 
 
