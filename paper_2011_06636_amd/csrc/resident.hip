@@ -19,12 +19,232 @@
 #include "internal.h"
 #include "resident_run.h"
 #include "rowsum.h"
+#include "tile2d.h"
 
 #pragma clang fp contract(off)
 
 namespace srj {
 
 namespace {
+
+// Constant-coefficient 1D grids of at most 64 K points in one wave: lane l
+// holds points l K .. l K + K - 1 in registers, the neighbours across lanes
+// come by DPP, and nothing waits at a barrier.  The per-point arithmetic is
+// the sweep's expression (row_s order: D u, then the lower and the upper
+// neighbour, ghost terms omitted), so iterates are bit-identical to the
+// workgroup kernel's; the norm is a fixed-order wave reduction (each lane's
+// points in order, then a shift-down tree), broadcast from lane 0.  The
+// factor table is staged in LDS as far as the levels reached need it, up to
+// its first kWaveTab values (the library's family up to level 21); a level
+// beyond them is staged cycle by cycle, kWaveW factors at a time.  Each
+// sweep's factor is read from LDS one sweep ahead.
+constexpr int kWaveTab = 6144;
+constexpr int kWaveW = 2048;
+constexpr int64_t kWaveMaxPoints = 64 * 8;
+
+// dst[0 .. n) = src[0 .. n) by one wave, eight loads per lane in flight at a
+// time (each load is unconditional, at an index clamped into the array)
+__device__ __forceinline__ void wave_stage(double *dst, const double *__restrict__ src, int n)
+{
+    const int lane = threadIdx.x;
+    for (int i0 = 0; i0 < n; i0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + q * 64 + lane;
+            v[q] = src[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + q * 64 + lane;
+            if (i < n) dst[i] = v[q];
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_bcast0(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_total(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return wave_bcast0(v);
+}
+
+template <bool UPD, int K>
+__global__ __launch_bounds__(64) void k_resident_wave1d(DevProblem P, double *__restrict__ x,
+                                                        const double *__restrict__ omega,
+                                                        const int32_t *__restrict__ offsets,
+                                                        const int32_t *__restrict__ levelM,
+                                                        ResidentArgs a,
+                                                        int32_t *__restrict__ levels_hist,
+                                                        double *__restrict__ norms_hist,
+                                                        ResidentOut *__restrict__ out,
+                                                        ResidentRecord rec)
+{
+    __shared__ double tab[kWaveTab];
+    __shared__ double wl[kWaveW];
+    const int lane = threadIdx.x;
+    int staged = 0;  // factors [0, staged) of the table are in tab
+    const int64_t N = P.n0;
+    const double D = P.dconst, c = P.c[0], Dinv = P.dinvconst;
+    double u[K], bv[K];
+    bool in[K], lo[K], hi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t p = (int64_t)lane * K + k;
+        in[k] = p < N;
+        lo[k] = p > 0;
+        hi[k] = p < N - 1;
+        u[k] = in[k] ? x[p] : 0.0;
+        bv[k] = in[k] ? P.b[p] : 0.0;
+    }
+    // s_p = D u_p - c u_{p-1} - c u_{p+1}, ghost terms omitted
+    auto row = [&](const double *v, int k, double left, double right) {
+        double s = D * v[k];
+        if (lo[k]) s = s - c * (k > 0 ? v[k - 1] : left);
+        if (hi[k]) s = s - c * (k + 1 < K ? v[k + 1] : right);
+        return s;
+    };
+    auto norm_of = [&]() -> double {
+        const double left = dpp_prev(u[K - 1]), right = dpp_next(u[0]);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double r = bv[k] - row(u, k, left, right);
+            acc = in[k] ? acc + r * r : acc;
+        }
+        return sqrt(wave_total(acc));
+    };
+    const double norm0 = norm_of();
+    const double r0 = a.r0_given > 0.0 ? a.r0_given : norm0;
+    const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
+    if (lane == 0) norms_hist[0] = norm0;
+    int status = SRJ_ERR_NOT_CONVERGED, cycles = 0, level = a.start_level, last_level = a.start_level;
+    int64_t sweeps = 0;
+    double prev = norm0, last = norm0, margin = INFINITY;
+    if (!isfinite(norm0)) {
+        status = SRJ_ERR_NONFINITE;
+    } else if (norm0 == 0.0 || (!UPD && norm0 < target)) {
+        status = SRJ_OK;
+    } else {
+        for (int cycle = 0; cycle < a.max_cycles; ++cycle) {
+            const int lv = a.rule == SRJ_RULE_FIXED ? a.fixed_level : level;
+            const int M = levelM[lv];
+            if (sweeps + M > a.max_sweeps) break;
+            const int off = offsets[lv];
+            int done = M;          // sweeps of this cycle that count
+            bool stopped = false;  // the update test held after sweep done - 1
+            // sweeps base .. base + cnt - 1 of the cycle with factors src[0 ..)
+            auto sweep_run = [&](const double *src, int base, int cnt) {
+                double wnext = src[0];
+                for (int j = 0; j < cnt; ++j) {
+                    const double wj = wnext;
+                    if (j + 1 < cnt) wnext = src[j + 1];  // in flight during this sweep
+                    const double left = dpp_prev(u[K - 1]), right = dpp_next(u[0]);
+                    double un[K];
+                    unsigned long long dmax = 0ull;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const double r = bv[k] - row(u, k, left, right);
+                        const double t = Dinv * r;
+                        const double xn = u[k] + wj * t;
+                        un[k] = in[k] ? xn : 0.0;
+                        if (UPD && in[k]) {
+                            const unsigned long long d =
+                                (unsigned long long)__double_as_longlong(fabs(xn - u[k]));
+                            dmax = d > dmax ? d : dmax;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k) u[k] = un[k];
+                    if (UPD) {
+#pragma unroll
+                        for (int sh = 32; sh > 0; sh >>= 1) {
+                            const unsigned long long o = __shfl_xor(dmax, sh);
+                            dmax = o > dmax ? o : dmax;
+                        }
+                        if (__longlong_as_double((long long)dmax) < a.tol) {
+                            done = base + j + 1;
+                            stopped = true;
+                            return;
+                        }
+                    }
+                }
+            };
+            if (off + M <= kWaveTab) {
+                if (off + M > staged) {  // stage up to this level's last factor
+                    wave_stage(tab + staged, omega + staged, off + M - staged);
+                    __syncthreads();
+                    staged = off + M;
+                }
+                if (M > 0) sweep_run(tab + off, 0, M);
+            } else {
+                for (int base = 0; base < M && !stopped; base += kWaveW) {
+                    const int cnt = M - base < kWaveW ? M - base : kWaveW;
+                    __syncthreads();  // the previous chunk's factors are read
+                    wave_stage(wl, omega + off + base, cnt);
+                    __syncthreads();
+                    sweep_run(wl, base, cnt);
+                }
+            }
+            sweeps += done;
+            const double norm = norm_of();
+            cycles = cycle + 1;
+            last = norm;
+            last_level = lv;
+            if (lane == 0) {
+                levels_hist[cycle] = lv;
+                norms_hist[cycle + 1] = norm;
+            }
+            if (!isfinite(norm)) {
+                status = SRJ_ERR_NONFINITE;
+                break;
+            }
+            if (UPD ? stopped : norm < target) {
+                status = SRJ_OK;
+                break;
+            }
+            const double ratio = norm / prev;
+            prev = norm;
+            int nl = level;
+            if (a.rule == SRJ_RULE_HEURISTIC) {
+                margin = fmin(margin, fmin(fabs(ratio - 0.2), fabs(ratio - 0.4)));
+                if (ratio > 0.4)
+                    nl = level + 1;
+                else if (ratio < 0.4 && ratio > 0.2)
+                    nl = level - 1;
+            } else if (a.rule == SRJ_RULE_INCREASING) {
+                nl = level + 1;
+            }
+            level = nl < 0 ? 0 : (nl > a.max_level ? a.max_level : nl);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (in[k]) x[(int64_t)lane * K + k] = u[k];
+    if (lane == 0) {
+        out->status = status;
+        out->converged = status == SRJ_OK;
+        out->cycles = cycles;
+        out->final_level = cycles > 0 ? last_level : a.start_level;
+        out->sweeps = sweeps;
+        out->r0 = r0;
+        out->r_final = last;
+        out->min_margin = margin;
+        if (rec.sweeps) {
+            const int32_t i = *rec.count;
+            if (i < rec.cap) rec.sweeps[i] = sweeps;
+            *rec.count = i + 1;
+            if (status != SRJ_OK && status != SRJ_ERR_NOT_CONVERGED) *rec.bad = status;
+        }
+    }
+}
 
 // One workgroup solves the whole grid: x is copied into LDS, solved there
 // and copied back.
@@ -117,6 +337,35 @@ int resident_threads(int64_t N)
     return (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
 }
 
+bool wave1d_fits(const DevProblem &P)
+{
+    return P.ndim == 1 && !P.diag && !P.face[0] && !P.ell_len && P.n0 <= kWaveMaxPoints;
+}
+
+// The resident kernel for c's grid: one wave for small constant-coefficient
+// 1D grids, else one workgroup with the grid in LDS.
+template <bool UPD>
+void launch_resident(const srj_ctx *c, double *x, const int32_t *offs, const int32_t *lm,
+                     const ResidentArgs &a, int32_t *lh, double *nh, ResidentOut *dout,
+                     const ResidentRecord &rec)
+{
+    const int64_t N = c->npoints;
+    if (wave1d_fits(c->P)) {
+        const int64_t K = (N + 63) / 64;
+#define SRJ_W1(KK)                                                                              \
+        hipLaunchKernelGGL((k_resident_wave1d<UPD, KK>), dim3(1), dim3(64), 0, c->stream, c->P, x, \
+                           c->omega_dev, offs, lm, a, lh, nh, dout, rec)
+        if (K <= 1) SRJ_W1(1);
+        else if (K <= 2) SRJ_W1(2);
+        else if (K <= 4) SRJ_W1(4);
+        else SRJ_W1(8);
+#undef SRJ_W1
+        return;
+    }
+    hipLaunchKernelGGL(k_resident<UPD>, dim3(1), dim3(resident_threads(N)), resident_shmem(N),
+                       c->stream, c->P, x, c->omega_dev, offs, lm, a, lh, nh, dout, rec);
+}
+
 }  // namespace
 
 srj_status resident_prepare(srj_ctx *c, int max_cycles)
@@ -141,10 +390,7 @@ srj_status resident_launch_recorded(srj_ctx *c, double *x, const srj_solve_opts 
     ResidentOut *dout = reinterpret_cast<ResidentOut *>(fixed);
     const int32_t *lm = reinterpret_cast<const int32_t *>(fixed + kOutBytes);
     const int32_t *offs = reinterpret_cast<const int32_t *>(fixed + kOutBytes + kLmBytes);
-    const int64_t N = c->npoints;
-    hipLaunchKernelGGL(k_resident<false>, dim3(1), dim3(resident_threads(N)), resident_shmem(N),
-                       c->stream, c->P, x, c->omega_dev, offs, lm, resident_args(o), c->rs_levels,
-                       c->rs_norms, dout, rec);
+    launch_resident<false>(c, x, offs, lm, resident_args(o), c->rs_levels, c->rs_norms, dout, rec);
     SRJ_HIP_CHECK(hipGetLastError());
     return SRJ_OK;
 }
@@ -173,16 +419,12 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
         if (e == hipSuccess)
             e = hipMemcpyAsync(offs, c->offsets.data(), sizeof(int32_t) * c->offsets.size(),
                                hipMemcpyHostToDevice, c->stream);
-        const size_t shmem = resident_shmem(N);
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
         if (e == hipSuccess) {
-            const int threads = resident_threads(N);
             if (a.tol_mode == SRJ_TOL_UPDATE_INF)
-                hipLaunchKernelGGL(k_resident<true>, dim3(1), dim3(threads), shmem, c->stream, c->P,
-                                   x, c->omega_dev, offs, lm, a, lh, nh, dout, ResidentRecord{});
+                launch_resident<true>(c, x, offs, lm, a, lh, nh, dout, ResidentRecord{});
             else
-                hipLaunchKernelGGL(k_resident<false>, dim3(1), dim3(threads), shmem, c->stream,
-                                   c->P, x, c->omega_dev, offs, lm, a, lh, nh, dout, ResidentRecord{});
+                launch_resident<false>(c, x, offs, lm, a, lh, nh, dout, ResidentRecord{});
             e = hipGetLastError();
         }
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);

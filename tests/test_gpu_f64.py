@@ -521,6 +521,13 @@ RESIDENT_CASES = [
     ("3d_15x16x15", lambda: workloads.c5_instance(9, lo=15, hi=16), dict(tol=1e-8)),
     ("3d_varcoef_15", lambda: workloads.variable_coefficient(15, seed=8, corr_len=3.0), dict(tol=1e-10)),
     ("cap", lambda: workloads.c1(), dict(tol=1e-10, max_cycles=3)),
+    # 1D grids of at most 512 points run in one wave (1, 2, 4 and 8 points
+    # per lane); the update test stops inside a cycle
+    ("n40", lambda: workloads.poisson_1d(40), dict(tol=1e-10)),
+    ("n97", lambda: workloads.poisson_1d(97), dict(tol=1e-10)),
+    ("n512", lambda: workloads.poisson_1d(512), dict(tol=1e-9, max_cycles=40)),
+    ("n255_update", lambda: workloads.c1(), dict(tol=1e-9, tol_mode="update_inf")),
+    ("n513_workgroup", lambda: workloads.poisson_1d(513), dict(tol=1e-9, max_cycles=40)),
 ]
 
 
