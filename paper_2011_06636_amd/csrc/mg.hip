@@ -123,34 +123,36 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restri
     if (xc) xc[t] = 0.0;  // the coarse correction starts from zero
 }
 
-// x += P ec: one thread per fine point.  Per axis a fine index 2 J + 1 takes
-// coarse J with weight 1, a fine index 2 J takes coarse J - 1 and J with
-// weight 1/2 (indices outside the coarse grid are the zero boundary and
-// give no term); terms summed with axis 2 outermost, axis 0 innermost,
-// candidates in increasing order.  Two candidate slots per axis, each with
-// a flag, and each slot's share of the coarse index formed once; a missing
-// term is skipped by a select (its load reads coarse point 0), so the sum is
-// the same as over the present terms alone.  I: the index type (32-bit
-// when both grids have fewer than 2^31 points).
+// x += P ec.  Per axis a fine index 2 J + 1 takes coarse J with weight 1, a
+// fine index 2 J takes coarse J - 1 and J with weight 1/2 (indices outside
+// the coarse grid are the zero boundary and give no term); the terms of a
+// fine point are summed with axis 2 outermost, axis 0 innermost, candidates
+// in increasing order.  One thread per pair of fine points 2 J, 2 J + 1 of a
+// row: both take their coarse values from axis-0 columns J - 1 and J of the
+// same rows and planes, so each of those is loaded once for the pair.
+// Missing terms are skipped by selects (their loads read coarse point 0), so
+// each sum is the same as over its present terms alone.  I: the index type
+// (32-bit when the fine grid has fewer than 2^31 points).
 template <int ND, class I>
 __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restrict__ ec,
                                                           double *__restrict__ x, int64_t n0,
                                                           int64_t n1, int64_t n2, int64_t m0,
                                                           int64_t m1, int64_t m2)
 {
+    const int64_t pairs = m0 + 1;  // fine columns 2 J, 2 J + 1 for J = 0 .. m0 (n0 = 2 m0 + 1)
     int64_t xb, y, z;
-    if (!row_unit(blockIdx.x, n0, n1, n2, xb, y, z)) return;
-    const I i0 = (I)(xb * kRowUnit + threadIdx.x);
-    if (i0 >= (I)n0) return;
-    const I ii[3] = {i0, (I)y, (I)z};
-    const I t = i0 + (I)n0 * ((I)y + (I)n1 * (I)z);
+    if (!row_unit(blockIdx.x, pairs, n1, n2, xb, y, z)) return;
+    const I J = (I)(xb * kRowUnit + threadIdx.x);
+    if (J > (I)m0) return;
+    const I ii[3] = {0, (I)y, (I)z};
     const I mm[3] = {(I)m0, (I)m1, (I)m2};
     const I stride[3] = {1, (I)m0, (I)m0 * (I)m1};
+    // axes 1 and 2: candidate slots, their share of the coarse index, weights
     I off[3][2];
     double cw[3][2];
     bool has[3][2];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 1; d < 3; ++d) {
         if (d >= ND) {
             off[d][0] = off[d][1] = 0;
             cw[d][0] = 1.0;
@@ -165,30 +167,45 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
             has[d][0] = true;
             has[d][1] = false;
         } else {
-            const I J = ii[d] / 2;
-            off[d][0] = stride[d] * (J - 1);
-            off[d][1] = stride[d] * J;
+            const I K = ii[d] / 2;
+            off[d][0] = stride[d] * (K - 1);
+            off[d][1] = stride[d] * K;
             cw[d][0] = cw[d][1] = 0.5;
-            has[d][0] = J - 1 >= 0;
-            has[d][1] = J < mm[d];
+            has[d][0] = K - 1 >= 0;
+            has[d][1] = K < mm[d];
         }
     }
-    double v = 0.0;
+    // axis 0: the even point 2 J takes J - 1 and J, the odd point 2 J + 1 takes J
+    const bool hm = J - 1 >= 0, h0 = J < mm[0];
+    const bool odd_in = J < mm[0];  // 2 J + 1 <= n0 - 1
+    double ve = 0.0, vo = 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < (ND > 2 ? 2 : 1); ++k2)
 #pragma unroll
-        for (int k1 = 0; k1 < (ND > 1 ? 2 : 1); ++k1)
-#pragma unroll
-            for (int k0 = 0; k0 < 2; ++k0) {
-                const bool on = has[0][k0] && has[1][k1] && has[2][k2];
-                double wt = cw[0][k0];
+        for (int k1 = 0; k1 < (ND > 1 ? 2 : 1); ++k1) {
+            const bool on12 = has[1][k1] && has[2][k2];
+            const I base = off[1][k1] + off[2][k2];
+            const double em = ec[on12 && hm ? base + J - 1 : 0];
+            const double e0 = ec[on12 && h0 ? base + J : 0];
+            // even point: candidates J - 1 then J, weight 1/2 on axis 0
+            {
+                double wt = 0.5;
                 if (ND > 1) wt = wt * cw[1][k1];
                 if (ND > 2) wt = wt * cw[2][k2];
-                const I q = off[0][k0] + off[1][k1] + off[2][k2];
-                const double e = ec[on ? q : 0];
-                v = on ? v + wt * e : v;
+                ve = (on12 && hm) ? ve + wt * em : ve;
+                ve = (on12 && h0) ? ve + wt * e0 : ve;
             }
-    x[t] = x[t] + v;
+            // odd point: candidate J, weight 1 on axis 0
+            {
+                double wt = 1.0;
+                if (ND > 1) wt = wt * cw[1][k1];
+                if (ND > 2) wt = wt * cw[2][k2];
+                vo = (on12 && h0) ? vo + wt * e0 : vo;
+            }
+        }
+    const I row = (I)n0 * ((I)y + (I)n1 * (I)z);
+    x[row + 2 * J] = x[row + 2 * J] + ve;
+    if (odd_in) x[row + 2 * J + 1] = x[row + 2 * J + 1] + vo;
 }
 
 // The coarse end of the V-cycle in three launches: every level from the
@@ -540,7 +557,7 @@ srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStre
     const DevProblem &P = c->P;
     const int64_t m0 = (P.n0 - 1) / 2, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
-    const unsigned nb = (unsigned)row_grid(P.n0, P.n1, P.n2);
+    const unsigned nb = (unsigned)row_grid(m0 + 1, P.n1, P.n2);  // pairs of fine columns
     const bool small = P.n0 * P.n1 * P.n2 < ((int64_t)1 << 31);
 #define SRJ_PROLONG(ND, I)                                                                        \
     hipLaunchKernelGGL((k_prolong_add<ND, I>), dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, \
