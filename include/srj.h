@@ -211,8 +211,11 @@ srj_status srj_residual_norm(srj_ctx *ctx, const double *x, double *norm_out);
  * hip_stream (a hipStream_t, NULL: null stream); the call does not
  * synchronise, so *norm_out is valid once that stream has reached it.
  * Partial sums go to a fixed 2 MiB device array that each GPU holds from the
- * first call until the process ends: grids needing more than 2^18 residual
- * blocks (ceil(n0 / 256) * n1 * n2) return SRJ_ERR_UNSUPPORTED.  Every call
+ * first call until the process ends: grids needing more than 2^18 partial
+ * sums return SRJ_ERR_UNSUPPORTED: one partial per 256 columns x 4 rows of
+ * a plane, 8 * ceil(n0 / 256) * ceil(ceil(n1 / 8) / 4) * n2 of them when
+ * n1 >= 64, else ceil(n0 / 256) * ceil(n1 / 4) * n2 (16384^2 and 512^3
+ * fit).  Every call
  * on one GPU shares that array, so calls whose work overlaps on one GPU (two
  * streams, two threads) race: order them on one stream.  Validation as
  * srj_setup, plus x and norm_out (SRJ_ERR_INVALID). */

@@ -704,6 +704,10 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
     return SRJ_OK;
 }
 
+// Most V-cycle graphs kept per multigrid context: 25 smoothing levels times
+// two starting buffers for one x and one set of options.
+constexpr size_t kMaxGraphs = 64;
+
 // V-cycles can be replayed from graphs when the coarsest grid is solved in
 // one workgroup and nothing times the launches.
 bool graphable(const srj_mg *g, int Lc)
@@ -744,6 +748,14 @@ srj_status vcycle_graph(MgRun &run, int level, double *x)
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) return fail(SRJ_ERR_HIP, std::string("V-cycle graph: ") + hipGetErrorString(ei));
+    if (g->graphs.size() >= kMaxGraphs) {
+        // a bounded cache (callers that pass a new x on every solve would
+        // otherwise grow it without end): the oldest entry goes, once the
+        // stream has finished every replay of it
+        SRJ_HIP_CHECK(hipStreamSynchronize(g->stream));
+        (void)hipGraphExecDestroy(g->graphs.front().exec);
+        g->graphs.erase(g->graphs.begin());
+    }
     g->graphs.push_back({level, o->pre, o->post, run.Lc, o->coarse_max_cycles, o->coarse_tol, x,
                          start, run.cur[0], exec});
     SRJ_HIP_CHECK(hipGraphLaunch(exec, g->stream));

@@ -13,8 +13,11 @@
 
 namespace srj {
 
-// Partial sums for up to 2^18 residual blocks (2 MiB): a 2D grid with n0 <=
-// 256 and n1 <= 65535 rows, a 8192^2 grid, or a 256^3 box fits.
+// Partial sums for up to 2^18 workgroups of the residual norm (2 MiB), one
+// per 256 columns x 4 rows of a plane, rows counted per eighth of the plane
+// when it has at least 64 rows: 8 ceil(n0 / 256) ceil(ceil(n1 / 8) / 4) n2
+// partials then, else ceil(n0 / 256) ceil(n1 / 4) n2.  A 16384^2 grid, a
+// 512^3 box or a 2D grid with n0 <= 256 and n1 <= 2^20 rows fits.
 constexpr int64_t kScratchPartials = int64_t(1) << 18;
 
 static __device__ __align__(256) double scratch[kScratchPartials];
@@ -60,8 +63,8 @@ srj_status srj_residual_norm_noalloc(const srj_problem *p, const double *x, void
     if (residual_blocks(P) > kScratchPartials)
         return fail(SRJ_ERR_UNSUPPORTED,
                     "grid needs " + std::to_string(residual_blocks(P)) +
-                        " residual blocks (ceil(n0 / 256) n1 n2); the static scratch holds " +
-                        std::to_string(kScratchPartials));
+                        " partial sums (one per 256 columns x 4 rows of a plane); the static "
+                        "scratch holds " + std::to_string(kScratchPartials));
     int dev = 0;
     SRJ_HIP_CHECK(hipGetDevice(&dev));
     if ((st = check_problem_arrays(p, dev)) != SRJ_OK) return st;

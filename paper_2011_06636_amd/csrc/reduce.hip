@@ -43,61 +43,75 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return t;
 }
 
-// One unit (256 points of a row, rowband.h) per workgroup, one point per
-// thread; the partial of unit (xb, y, z) goes to slot xb + nx (y + n1 z), so
-// the fold adds the same partials in the same order whatever the mapping of
-// units to workgroups.  Neighbour values and couplings are loaded from
-// clamped indices unconditionally and a select drops the terms of ghost
-// neighbours, leaving the expression's operations and order unchanged: with
-// a branch around each neighbour's load the compiler waited for every load
-// in turn.
+// One unit (256 columns of kNormRows rows, rowband.h) per workgroup: each
+// thread forms the residuals of its column's rows, all loads of all rows in
+// flight together, and sums their squares in row order; the workgroup's sum
+// goes to slot blockIdx.x (zero for a workgroup without a unit), so the fold
+// adds the same partials in the same order for a given grid.  Neighbour
+// values and couplings are loaded from clamped indices unconditionally and a
+// select drops the terms of ghost neighbours, leaving the expression's
+// operations and order unchanged: with a branch around each neighbour's load
+// the compiler waited for every load in turn.
 template <int ND>
 __global__ __launch_bounds__(kBlock) void k_residual_sumsq(DevProblem P,
                                                            const double *__restrict__ x,
                                                            double *__restrict__ partials)
 {
     __shared__ double lds[kBlock / 64];
-    int64_t xb, i1, i2;
-    if (!row_unit(blockIdx.x, P.n0, P.n1, P.n2, xb, i1, i2)) return;  // whole workgroup
+    int64_t xb, y, i2;
+    int ny;
+    if (!row_unit(blockIdx.x, P.n0, P.n1, P.n2, kNormRows, xb, y, ny, i2)) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;  // whole workgroup
+    }
     const int64_t i0 = xb * kBlock + threadIdx.x;
     const bool in = i0 < P.n0;
     const int64_t n0 = P.n0, n1 = P.n1, n2 = P.n2;
     const int64_t s1 = n0, s2 = n0 * n1;
-    const int64_t p = (in ? i0 : n0 - 1) + s1 * i1 + s2 * i2;
     const int64_t c0 = in ? i0 : n0 - 1;
     const bool h0 = c0 > 0, h1 = c0 < n0 - 1;
-    const bool h2 = ND >= 2 && i1 > 0, h3 = ND >= 2 && i1 < n1 - 1;
     const bool h4 = ND >= 3 && i2 > 0, h5 = ND >= 3 && i2 < n2 - 1;
-    const int64_t q0 = h0 ? p - 1 : p, q1 = h1 ? p + 1 : p;
-    const int64_t q2 = h2 ? p - s1 : p, q3 = h3 ? p + s1 : p;
-    const int64_t q4 = h4 ? p - s2 : p, q5 = h5 ? p + s2 : p;
-    const double xc = x[p];
-    double s = (P.diag ? P.diag[p] : P.dconst) * xc;
-    {
-        const double v0 = x[q0], v1 = x[q1];
-        const double f0 = P.face[0] ? P.face[0][q0] : P.c[0];
-        const double f1 = P.face[0] ? P.face[0][p] : P.c[0];
-        s = h0 ? s - f0 * v0 : s;
-        s = h1 ? s - f1 * v1 : s;
+    double rr[kNormRows];
+#pragma unroll
+    for (int j = 0; j < kNormRows; ++j) {
+        // rows past the unit's last repeat its first row and are not summed
+        const int64_t i1 = y + (j < ny ? j : 0);
+        const int64_t p = c0 + s1 * i1 + s2 * i2;
+        const bool h2 = ND >= 2 && i1 > 0, h3 = ND >= 2 && i1 < n1 - 1;
+        const int64_t q0 = h0 ? p - 1 : p, q1 = h1 ? p + 1 : p;
+        const int64_t q2 = h2 ? p - s1 : p, q3 = h3 ? p + s1 : p;
+        const int64_t q4 = h4 ? p - s2 : p, q5 = h5 ? p + s2 : p;
+        const double xc = x[p];
+        double s = (P.diag ? P.diag[p] : P.dconst) * xc;
+        {
+            const double v0 = x[q0], v1 = x[q1];
+            const double f0 = P.face[0] ? P.face[0][q0] : P.c[0];
+            const double f1 = P.face[0] ? P.face[0][p] : P.c[0];
+            s = h0 ? s - f0 * v0 : s;
+            s = h1 ? s - f1 * v1 : s;
+        }
+        if (ND >= 2) {
+            const double v2 = x[q2], v3 = x[q3];
+            const double f2 = P.face[1] ? P.face[1][q2] : P.c[1];
+            const double f3 = P.face[1] ? P.face[1][p] : P.c[1];
+            s = h2 ? s - f2 * v2 : s;
+            s = h3 ? s - f3 * v3 : s;
+        }
+        if (ND >= 3) {
+            const double v4 = x[q4], v5 = x[q5];
+            const double f4 = P.face[2] ? P.face[2][q4] : P.c[2];
+            const double f5 = P.face[2] ? P.face[2][p] : P.c[2];
+            s = h4 ? s - f4 * v4 : s;
+            s = h5 ? s - f5 * v5 : s;
+        }
+        const double r = P.b[p] - s;
+        rr[j] = (in && j < ny) ? r * r : 0.0;
     }
-    if (ND >= 2) {
-        const double v2 = x[q2], v3 = x[q3];
-        const double f2 = P.face[1] ? P.face[1][q2] : P.c[1];
-        const double f3 = P.face[1] ? P.face[1][p] : P.c[1];
-        s = h2 ? s - f2 * v2 : s;
-        s = h3 ? s - f3 * v3 : s;
-    }
-    if (ND >= 3) {
-        const double v4 = x[q4], v5 = x[q5];
-        const double f4 = P.face[2] ? P.face[2][q4] : P.c[2];
-        const double f5 = P.face[2] ? P.face[2][p] : P.c[2];
-        s = h4 ? s - f4 * v4 : s;
-        s = h5 ? s - f5 * v5 : s;
-    }
-    const double r = P.b[p] - s;
-    const double rr = in ? r * r : 0.0;
-    const double t = block_sum<kBlock / 64>(rr, lds);
-    if (threadIdx.x == 0) partials[xb + row_units_x(n0) * (i1 + n1 * i2)] = t;
+    double acc = rr[0];
+#pragma unroll
+    for (int j = 1; j < kNormRows; ++j) acc += rr[j];
+    const double t = block_sum<kBlock / 64>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 // General sparse matrix: the same per-row expression as k_sweep_ell.
@@ -141,7 +155,7 @@ void launch_stencil_residual(const DevProblem &P, const double *x, double *parti
 
 dim3 residual_grid(const DevProblem &P)
 {
-    return dim3((unsigned)row_grid(P.n0, P.n1, P.n2));
+    return dim3((unsigned)row_grid(P.n0, P.n1, P.n2, kNormRows));
 }
 
 }  // namespace
@@ -155,14 +169,14 @@ hipError_t launch_fold(ReduceScratch &rs, int64_t nblocks, hipStream_t s)
 
 int64_t residual_blocks(const DevProblem &P)
 {
-    return ((P.n0 + kBlock - 1) / kBlock) * P.n1 * P.n2;
+    return row_grid(P.n0, P.n1, P.n2, kNormRows);  // one partial per workgroup
 }
 
 hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
                                  hipStream_t s)
 {
     const dim3 grid = residual_grid(P);
-    const int64_t nb = residual_blocks(P);  // partials: one per unit
+    const int64_t nb = residual_blocks(P);  // partials: one per workgroup
     if (nb > rs.capacity) return hipErrorInvalidValue;
     if (P.ell_len) {
         hipLaunchKernelGGL(k_residual_ell, grid, dim3(kBlock), 0, s, P, x, rs.partials);
@@ -183,7 +197,7 @@ hipError_t launch_residual_norm_into(const DevProblem &P, const double *x, doubl
                                      int64_t capacity, double *norm_out, hipStream_t s)
 {
     const dim3 grid = residual_grid(P);
-    const int64_t nb = residual_blocks(P);  // partials: one per unit
+    const int64_t nb = residual_blocks(P);  // partials: one per workgroup
     if (nb > capacity || P.ell_len) return hipErrorInvalidValue;
     switch (P.ndim) {
     case 1: launch_stencil_residual<1>(P, x, partials, grid, s); break;

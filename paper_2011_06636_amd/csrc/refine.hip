@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "rowband.h"
 #include "storage.h"
 #include "tile2d.h"
 #include "stream3d.h"
@@ -85,7 +86,11 @@ __global__ __launch_bounds__(kBlock) void k_inner_generic(DevProblem32 Q,
 
 // Outer pass: x' = x + d / s_prev (UPDATE), r = b - A x' in binary64 with the
 // neighbours' x' formed on the fly, partial sums of r^2, and
-// rhat = storage(binary32(s_next * r)).
+// rhat = storage(binary32(s_next * r)).  One unit of 256 columns x kNormRows
+// rows per workgroup (rowband.h), as the residual norm: the partial of
+// workgroup b goes to slot b (zero without a unit).  Neighbours are loaded
+// from clamped indices unconditionally and a select drops the terms of ghost
+// neighbours, which leaves every operation and its order unchanged.
 template <int ND, class St, bool UPDATE>
 __global__ __launch_bounds__(kBlock) void k_outer(DevProblem P, const double *__restrict__ x,
                                                   const typename St::T *__restrict__ d,
@@ -94,36 +99,66 @@ __global__ __launch_bounds__(kBlock) void k_outer(DevProblem P, const double *__
                                                   double *__restrict__ partials)
 {
     __shared__ double lds[kBlock / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i1 = blockIdx.y, i2 = blockIdx.z;
-    double rr = 0.0;
-    if (i0 < P.n0) {
-        const int64_t s1 = P.n0, s2 = P.n0 * P.n1;
-        const int64_t p = i0 + s1 * i1 + s2 * i2;
-        auto xn = [&](int64_t q) -> double {
-            if (UPDATE) return x[q] + static_cast<double>(St::load(d[q])) * inv_s;
-            return x[q];
-        };
+    int64_t xb, y, i2;
+    int ny;
+    if (!row_unit(blockIdx.x, P.n0, P.n1, P.n2, kNormRows, xb, y, ny, i2)) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+        return;  // whole workgroup
+    }
+    const int64_t n0 = P.n0, n1 = P.n1, n2 = P.n2;
+    const int64_t s1 = n0, s2 = n0 * n1;
+    const int64_t i0 = xb * kBlock + threadIdx.x;
+    const bool in = i0 < n0;
+    const int64_t c0 = in ? i0 : n0 - 1;
+    const bool h0 = c0 > 0, h1 = c0 < n0 - 1;
+    const bool h4 = ND >= 3 && i2 > 0, h5 = ND >= 3 && i2 < n2 - 1;
+    auto xn = [&](int64_t q) -> double {
+        if (UPDATE) return x[q] + static_cast<double>(St::load(d[q])) * inv_s;
+        return x[q];
+    };
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < kNormRows; ++j) {
+        // rows past the unit's last repeat its first row and are dropped
+        const bool ok = in && j < ny;
+        const int64_t i1 = y + (j < ny ? j : 0);
+        const int64_t p = c0 + s1 * i1 + s2 * i2;
+        const bool h2 = ND >= 2 && i1 > 0, h3 = ND >= 2 && i1 < n1 - 1;
+        const int64_t q0 = h0 ? p - 1 : p, q1 = h1 ? p + 1 : p;
+        const int64_t q2 = h2 ? p - s1 : p, q3 = h3 ? p + s1 : p;
+        const int64_t q4 = h4 ? p - s2 : p, q5 = h5 ? p + s2 : p;
         const double xc = xn(p);
         double s = (P.diag ? P.diag[p] : P.dconst) * xc;
-        if (i0 > 0) s = s - (P.face[0] ? P.face[0][p - 1] : P.c[0]) * xn(p - 1);
-        if (i0 < P.n0 - 1) s = s - (P.face[0] ? P.face[0][p] : P.c[0]) * xn(p + 1);
+        {
+            const double v0 = xn(q0), v1 = xn(q1);
+            const double f0 = P.face[0] ? P.face[0][q0] : P.c[0];
+            const double f1 = P.face[0] ? P.face[0][p] : P.c[0];
+            s = h0 ? s - f0 * v0 : s;
+            s = h1 ? s - f1 * v1 : s;
+        }
         if (ND >= 2) {
-            if (i1 > 0) s = s - (P.face[1] ? P.face[1][p - s1] : P.c[1]) * xn(p - s1);
-            if (i1 < P.n1 - 1) s = s - (P.face[1] ? P.face[1][p] : P.c[1]) * xn(p + s1);
+            const double v2 = xn(q2), v3 = xn(q3);
+            const double f2 = P.face[1] ? P.face[1][q2] : P.c[1];
+            const double f3 = P.face[1] ? P.face[1][p] : P.c[1];
+            s = h2 ? s - f2 * v2 : s;
+            s = h3 ? s - f3 * v3 : s;
         }
         if (ND >= 3) {
-            if (i2 > 0) s = s - (P.face[2] ? P.face[2][p - s2] : P.c[2]) * xn(p - s2);
-            if (i2 < P.n2 - 1) s = s - (P.face[2] ? P.face[2][p] : P.c[2]) * xn(p + s2);
+            const double v4 = xn(q4), v5 = xn(q5);
+            const double f4 = P.face[2] ? P.face[2][q4] : P.c[2];
+            const double f5 = P.face[2] ? P.face[2][p] : P.c[2];
+            s = h4 ? s - f4 * v4 : s;
+            s = h5 ? s - f5 * v5 : s;
         }
         const double r = P.b[p] - s;
-        rr = r * r;
-        if (UPDATE) xo[p] = xc;
-        rhat[p] = St::store(static_cast<float>(s_next * r));
+        if (ok) {
+            if (UPDATE) xo[p] = xc;
+            rhat[p] = St::store(static_cast<float>(s_next * r));
+        }
+        acc = j == 0 ? (ok ? r * r : 0.0) : acc + (ok ? r * r : 0.0);
     }
-    const double t = block_sum256(rr, lds);
-    if (threadIdx.x == 0)
-        partials[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = t;
+    const double t = block_sum256(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 template <class T>
@@ -145,7 +180,8 @@ __global__ void k_inv_to_f32(const double *__restrict__ a, float *__restrict__ o
     if (i < n) o[i] = static_cast<float>(1.0 / a[i]);
 }
 
-dim3 row_grid(int64_t n0, int64_t n1, int64_t n2)
+// One workgroup per 256 points of a row (x), rows (y), planes (z).
+dim3 point_grid(int64_t n0, int64_t n1, int64_t n2)
 {
     return dim3((unsigned)((n0 + kBlock - 1) / kBlock), (unsigned)n1, (unsigned)n2);
 }
@@ -252,7 +288,7 @@ hipError_t launch_inner(const DevProblem32 &Q, const void *d, void *dout, const 
                         hipStream_t s)
 {
     using T = typename St::T;
-    const dim3 g = row_grid(Q.n0, Q.n1, Q.n2);
+    const dim3 g = point_grid(Q.n0, Q.n1, Q.n2);
     const T *dd = static_cast<const T *>(d);
     T *oo = static_cast<T *>(dout);
     const T *rr = static_cast<const T *>(rhat);
@@ -269,7 +305,7 @@ hipError_t launch_outer_t(const DevProblem &P, const double *x, const void *d, d
                           double *xo, void *rhat, double s_next, double *partials, hipStream_t s)
 {
     using T = typename St::T;
-    const dim3 g = row_grid(P.n0, P.n1, P.n2);
+    const dim3 g((unsigned)residual_blocks(P));  // one workgroup per partial
     const T *dd = static_cast<const T *>(d);
     T *rh = static_cast<T *>(rhat);
     switch (P.ndim) {

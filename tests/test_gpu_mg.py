@@ -109,6 +109,23 @@ def test_mg_replays_match_across_solves_options_and_streams(torch_cuda, orc):
     s.close()
 
 
+def test_mg_graph_cache_stays_bounded(torch_cuda, orc):
+    # every new x gets graphs of its own; past the cache's bound the oldest
+    # are dropped, and solves into old and new tensors keep the oracle's bits
+    from paper_2011_06636_amd.solver import MgSolver
+    prob = workloads.c2(n=127)
+    ref = orc.mg_solve(prob, tol=1e-10)
+    s = MgSolver(prob)
+    xs = [s.zeros() for _ in range(40)]
+    for i in list(range(40)) + [0, 1, 39]:
+        xs[i].zero_()
+        out = s.solve(xs[i], tol=1e-10)
+        assert np.array_equal(out["x"].cpu().numpy(), ref["x"]), i
+        assert out["work"] == ref["work"], i
+    print("mg graph cache: 43 solves into 40 tensors", flush=True)
+    s.close()
+
+
 def test_mg_rejects_what_it_cannot_coarsen(torch_cuda):
     from paper_2011_06636_amd import abi
     from paper_2011_06636_amd.solver import MgSolver

@@ -73,9 +73,10 @@ def test_noalloc_refuses_grid_beyond_scratch(torch_cuda):
     torch = torch_cuda
     b = torch.zeros(8, dtype=torch.float64, device="cuda")
     out = torch.zeros(1, dtype=torch.float64, device="cuda")
-    # 2 x 65535 x 3 blocks of 256 points (> 2^18): refused on the block count,
-    # before the (too small) arrays are looked at or any kernel runs
-    p = make_problem(3, [257, 65535, 3], [1.0, 1.0, 1.0], 6.0, b)
+    # 8 x 2 x 2048 x 20 partial sums of 256 columns x 4 rows (> 2^18): refused
+    # on their count, before the (too small) arrays are looked at or any
+    # kernel runs
+    p = make_problem(3, [257, 65535, 20], [1.0, 1.0, 1.0], 6.0, b)
     st = abi.load().srj_residual_norm_noalloc(p, b.data_ptr(), None, out.data_ptr())
     assert st == abi.SRJ_ERR_UNSUPPORTED
     assert "static scratch" in abi.last_error()
