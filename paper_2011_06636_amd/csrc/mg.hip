@@ -40,6 +40,12 @@ constexpr int kMgMaxLevels = 32;
 
 __device__ __forceinline__ double full_weight(int a) { return a == 0 ? 0.5 : 0.25; }
 
+// Rows per unit of the interpolation: in 3D four, whose loads a thread has
+// in flight together (255^3: 25.7 -> 21.8 us per launch on average over the
+// levels); in 2D one, since four left the coarser levels too few workgroups
+// (the residual and the restriction, tried the same way, gained nothing).
+__host__ __device__ constexpr int prolong_rows(int nd) { return nd == 3 ? 4 : 1; }
+
 // Fine residual r = b - A x at every point, the sweep's expression: D x,
 // then the axis-0, axis-1, axis-2 neighbours below and above, each
 // subtracted only where it lies in the grid.  Neighbour loads are
@@ -127,9 +133,10 @@ __global__ __launch_bounds__(kMgBlock) void k_mg_restrict(const double *__restri
 // fine index 2 J takes coarse J - 1 and J with weight 1/2 (indices outside
 // the coarse grid are the zero boundary and give no term); the terms of a
 // fine point are summed with axis 2 outermost, axis 0 innermost, candidates
-// in increasing order.  One thread per pair of fine points 2 J, 2 J + 1 of a
-// row: both take their coarse values from axis-0 columns J - 1 and J of the
-// same rows and planes, so each of those is loaded once for the pair.
+// in increasing order.  One thread per pair of fine points 2 J, 2 J + 1 in
+// each of a unit's prolong_rows(ND) rows (rowband.h): both take their coarse
+// values from axis-0 columns J - 1 and J of the same rows and planes, so each
+// of those is loaded once for the pair.
 // Missing terms are skipped by selects (their loads read coarse point 0), so
 // each sum is the same as over its present terms alone.  I: the index type
 // (32-bit when the fine grid has fewer than 2^31 points).
@@ -139,73 +146,90 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
                                                           int64_t n1, int64_t n2, int64_t m0,
                                                           int64_t m1, int64_t m2)
 {
+    constexpr int R = prolong_rows(ND);
     const int64_t pairs = m0 + 1;  // fine columns 2 J, 2 J + 1 for J = 0 .. m0 (n0 = 2 m0 + 1)
-    int64_t xb, y, z;
-    if (!row_unit(blockIdx.x, pairs, n1, n2, xb, y, z)) return;
+    int64_t xb, y0, z;
+    int ny;
+    if (!row_unit(blockIdx.x, pairs, n1, n2, R, xb, y0, ny, z)) return;
     const I J = (I)(xb * kRowUnit + threadIdx.x);
     if (J > (I)m0) return;
-    const I ii[3] = {0, (I)y, (I)z};
     const I mm[3] = {(I)m0, (I)m1, (I)m2};
     const I stride[3] = {1, (I)m0, (I)m0 * (I)m1};
-    // axes 1 and 2: candidate slots, their share of the coarse index, weights
-    I off[3][2];
-    double cw[3][2];
-    bool has[3][2];
-#pragma unroll
-    for (int d = 1; d < 3; ++d) {
-        if (d >= ND) {
-            off[d][0] = off[d][1] = 0;
-            cw[d][0] = 1.0;
-            cw[d][1] = 0.0;
-            has[d][0] = true;
-            has[d][1] = false;
-        } else if (ii[d] & 1) {
-            off[d][0] = stride[d] * ((ii[d] - 1) / 2);
-            off[d][1] = 0;
-            cw[d][0] = 1.0;
-            cw[d][1] = 0.0;
-            has[d][0] = true;
-            has[d][1] = false;
-        } else {
-            const I K = ii[d] / 2;
-            off[d][0] = stride[d] * (K - 1);
-            off[d][1] = stride[d] * K;
-            cw[d][0] = cw[d][1] = 0.5;
-            has[d][0] = K - 1 >= 0;
-            has[d][1] = K < mm[d];
-        }
-    }
     // axis 0: the even point 2 J takes J - 1 and J, the odd point 2 J + 1 takes J
     const bool hm = J - 1 >= 0, h0 = J < mm[0];
     const bool odd_in = J < mm[0];  // 2 J + 1 <= n0 - 1
-    double ve = 0.0, vo = 0.0;
+    double ue[R], uo[R];  // the updated even and odd points of each row
 #pragma unroll
-    for (int k2 = 0; k2 < (ND > 2 ? 2 : 1); ++k2)
+    for (int j = 0; j < R; ++j) {
+        // rows past the unit's last repeat its first row and are not stored
+        const int64_t y = y0 + (j < ny ? j : 0);
+        const I ii[3] = {0, (I)y, (I)z};
+        // axes 1 and 2: candidate slots, their share of the coarse index, weights
+        I off[3][2];
+        double cw[3][2];
+        bool has[3][2];
 #pragma unroll
-        for (int k1 = 0; k1 < (ND > 1 ? 2 : 1); ++k1) {
-            const bool on12 = has[1][k1] && has[2][k2];
-            const I base = off[1][k1] + off[2][k2];
-            const double em = ec[on12 && hm ? base + J - 1 : 0];
-            const double e0 = ec[on12 && h0 ? base + J : 0];
-            // even point: candidates J - 1 then J, weight 1/2 on axis 0
-            {
-                double wt = 0.5;
-                if (ND > 1) wt = wt * cw[1][k1];
-                if (ND > 2) wt = wt * cw[2][k2];
-                ve = (on12 && hm) ? ve + wt * em : ve;
-                ve = (on12 && h0) ? ve + wt * e0 : ve;
-            }
-            // odd point: candidate J, weight 1 on axis 0
-            {
-                double wt = 1.0;
-                if (ND > 1) wt = wt * cw[1][k1];
-                if (ND > 2) wt = wt * cw[2][k2];
-                vo = (on12 && h0) ? vo + wt * e0 : vo;
+        for (int d = 1; d < 3; ++d) {
+            if (d >= ND) {
+                off[d][0] = off[d][1] = 0;
+                cw[d][0] = 1.0;
+                cw[d][1] = 0.0;
+                has[d][0] = true;
+                has[d][1] = false;
+            } else if (ii[d] & 1) {
+                off[d][0] = stride[d] * ((ii[d] - 1) / 2);
+                off[d][1] = 0;
+                cw[d][0] = 1.0;
+                cw[d][1] = 0.0;
+                has[d][0] = true;
+                has[d][1] = false;
+            } else {
+                const I K = ii[d] / 2;
+                off[d][0] = stride[d] * (K - 1);
+                off[d][1] = stride[d] * K;
+                cw[d][0] = cw[d][1] = 0.5;
+                has[d][0] = K - 1 >= 0;
+                has[d][1] = K < mm[d];
             }
         }
-    const I row = (I)n0 * ((I)y + (I)n1 * (I)z);
-    x[row + 2 * J] = x[row + 2 * J] + ve;
-    if (odd_in) x[row + 2 * J + 1] = x[row + 2 * J + 1] + vo;
+        double ve = 0.0, vo = 0.0;
+#pragma unroll
+        for (int k2 = 0; k2 < (ND > 2 ? 2 : 1); ++k2)
+#pragma unroll
+            for (int k1 = 0; k1 < (ND > 1 ? 2 : 1); ++k1) {
+                const bool on12 = has[1][k1] && has[2][k2];
+                const I base = off[1][k1] + off[2][k2];
+                const double em = ec[on12 && hm ? base + J - 1 : 0];
+                const double e0 = ec[on12 && h0 ? base + J : 0];
+                // even point: candidates J - 1 then J, weight 1/2 on axis 0
+                {
+                    double wt = 0.5;
+                    if (ND > 1) wt = wt * cw[1][k1];
+                    if (ND > 2) wt = wt * cw[2][k2];
+                    ve = (on12 && hm) ? ve + wt * em : ve;
+                    ve = (on12 && h0) ? ve + wt * e0 : ve;
+                }
+                // odd point: candidate J, weight 1 on axis 0
+                {
+                    double wt = 1.0;
+                    if (ND > 1) wt = wt * cw[1][k1];
+                    if (ND > 2) wt = wt * cw[2][k2];
+                    vo = (on12 && h0) ? vo + wt * e0 : vo;
+                }
+            }
+        const I row = (I)n0 * ((I)y + (I)n1 * (I)z);
+        ue[j] = x[row + 2 * J] + ve;
+        uo[j] = x[row + 2 * J + (odd_in ? 1 : 0)] + vo;
+    }
+    // stores after every load: the compiler cannot tell that the stores of
+    // one row leave the loads of the next unchanged
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (j >= ny) break;
+        const I row = (I)n0 * ((I)(y0 + j) + (I)n1 * (I)z);
+        x[row + 2 * J] = ue[j];
+        if (odd_in) x[row + 2 * J + 1] = uo[j];
+    }
 }
 
 // The coarse end of the V-cycle in three launches: every level from the
@@ -557,7 +581,7 @@ srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStre
     const DevProblem &P = c->P;
     const int64_t m0 = (P.n0 - 1) / 2, m1 = P.ndim > 1 ? (P.n1 - 1) / 2 : 1,
                   m2 = P.ndim > 2 ? (P.n2 - 1) / 2 : 1;
-    const unsigned nb = (unsigned)row_grid(m0 + 1, P.n1, P.n2);  // pairs of fine columns
+    const unsigned nb = (unsigned)row_grid(m0 + 1, P.n1, P.n2, prolong_rows(P.ndim));  // pairs
     const bool small = P.n0 * P.n1 * P.n2 < ((int64_t)1 << 31);
 #define SRJ_PROLONG(ND, I)                                                                        \
     hipLaunchKernelGGL((k_prolong_add<ND, I>), dim3(nb), dim3(kMgBlock), 0, s, ec, x, P.n0, P.n1, \
