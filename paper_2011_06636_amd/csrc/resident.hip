@@ -337,9 +337,14 @@ int resident_threads(int64_t N)
     return (int)std::min<int64_t>(kThreads, std::max<int64_t>(64, (N + 63) / 64 * 64));
 }
 
+// Constant-coefficient grids of one row (any dimension: with n1 = n2 = 1 the
+// axis-1 and axis-2 neighbours are all ghosts, whose terms the expression
+// omits, so it is the 1D one; the coarsest grids of 2D and 3D multigrid
+// hierarchies are such) of at most kWaveMaxPoints points.
 bool wave1d_fits(const DevProblem &P)
 {
-    return P.ndim == 1 && !P.diag && !P.face[0] && !P.ell_len && P.n0 <= kWaveMaxPoints;
+    return P.n1 == 1 && P.n2 == 1 && !P.diag && !P.face[0] && !P.face[1] && !P.face[2] &&
+           !P.ell_len && P.n0 <= kWaveMaxPoints;
 }
 
 // The resident kernel for c's grid: one wave for small constant-coefficient

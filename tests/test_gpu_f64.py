@@ -528,6 +528,11 @@ RESIDENT_CASES = [
     ("n512", lambda: workloads.poisson_1d(512), dict(tol=1e-9, max_cycles=40)),
     ("n255_update", lambda: workloads.c1(), dict(tol=1e-9, tol_mode="update_inf")),
     ("n513_workgroup", lambda: workloads.poisson_1d(513), dict(tol=1e-9, max_cycles=40)),
+    # grids of one row in 2D and 3D (the coarsest grids of multigrid
+    # hierarchies) run in the single wave too
+    ("2d_row_37x1", lambda: workloads.poisson([37, 1], b=np.random.default_rng(12).uniform(-1, 1, (1, 1, 37))), dict(tol=1e-10)),
+    ("2d_point_1x1", lambda: workloads.poisson([1, 1], b=np.array([[[0.3]]])), dict(tol=1e-10)),
+    ("3d_row_130x1x1", lambda: workloads.poisson([130, 1, 1], b=np.random.default_rng(13).uniform(-1, 1, (1, 1, 130))), dict(tol=1e-10)),
 ]
 
 
