@@ -239,12 +239,19 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
 // level down), the coarsest grid is solved by the resident solver, and
 // k_mg_tail<false> interpolates and post-smooths level by level up.  The
 // operations are those of the kernels above and of the sweep kernels, in
-// their order, so the values are the same bits.  One thread per point (every
-// tail grid has at most kThreads points); the workgroup synchronises after
-// every pass.
+// their order, so the values are the same bits.  Thread p takes points p,
+// p + kThreads, ... of a level (every tail grid has at most kTailPerThread
+// kThreads points); the workgroup synchronises after every pass.
 constexpr int kTailMaxLevels = 12;
-constexpr int64_t kTailMaxPoints = kThreads;
-constexpr size_t kTailLdsDoubles = 8192;  // 64 KiB
+constexpr int kTailPerThread = 4;
+constexpr int64_t kTailMaxPoints = (int64_t)kTailPerThread * kThreads;
+constexpr size_t kTailLdsDoubles = 19968;  // 156 KiB of the 160 KiB per workgroup
+
+// Largest first tail level: in 3D four points per thread (the 15^3 level
+// joins the tail: 255^3 to 1e-10 10.95 -> 10.71 ms); in 1D and 2D one, since
+// taking the 63^2 level into the tail cost more than its six launches
+// (2047^2 to 2e-9 3.90 -> 4.01 ms).
+int64_t tail_max_points(int ndim) { return ndim == 3 ? kTailMaxPoints : kThreads; }
 
 struct TailLevel {
     DevProblem P;       // the level's sizes and constants (b lives in LDS)
@@ -329,10 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
     // nu whole cycles of the level's scheme, as the sweep kernels form them
     auto smooth = [&](int l, int nu) {
         const TailTab e = tab[l];
-        int i0 = 0, i1 = 0, i2 = 0;
-        if (p < e.N) coords(e, p, i0, i1, i2);
         const double *b = bbuf(l);
-        const double bp = p < e.N ? b[p] : 0.0;
         for (int k = 0; k < nu; ++k) {
             double wnext = e.w[0];
             for (int j = 0; j < e.M; ++j) {
@@ -340,11 +344,13 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
                 if (j + 1 < e.M) wnext = e.w[j + 1];  // in flight during this sweep
                 const double *cur = xbuf(l);
                 double *nxt = spare(l);
-                if (p < e.N) {
-                    const double s = rows(e, cur, p, i0, i1, i2);
-                    const double r = bp - s;
+                for (int q = p; q < e.N; q += kThreads) {
+                    int i0, i1, i2;
+                    coords(e, q, i0, i1, i2);
+                    const double s = rows(e, cur, q, i0, i1, i2);
+                    const double r = b[q] - s;
                     const double tt = e.Dinv * r;
-                    nxt[p] = cur[p] + wj * tt;
+                    nxt[q] = cur[q] + wj * tt;
                 }
                 __syncthreads();
                 par ^= 1u << l;
@@ -352,9 +358,9 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
         }
     };
     if constexpr (DOWN) {
-        if (p < tab[0].N) {
-            bbuf(0)[p] = t.bg[0][p];
-            xbuf(0)[p] = 0.0;
+        for (int q = p; q < tab[0].N; q += kThreads) {
+            bbuf(0)[q] = t.bg[0][q];
+            xbuf(0)[q] = 0.0;
         }
         __syncthreads();
         for (int l = 0; l + 1 < t.count; ++l) {
@@ -362,15 +368,15 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
             // fine residual into the level's spare buffer, then full weighting
             const TailTab e = tab[l], ec = tab[l + 1];
             double *r = spare(l);
-            if (p < e.N) {
+            for (int q = p; q < e.N; q += kThreads) {
                 int i0, i1, i2;
-                coords(e, p, i0, i1, i2);
-                r[p] = bbuf(l)[p] - rows(e, xbuf(l), p, i0, i1, i2);
+                coords(e, q, i0, i1, i2);
+                r[q] = bbuf(l)[q] - rows(e, xbuf(l), q, i0, i1, i2);
             }
             __syncthreads();
-            if (p < ec.N) {
+            for (int q = p; q < ec.N; q += kThreads) {
                 int I0, I1, I2;
-                coords(ec, p, I0, I1, I2);
+                coords(ec, q, I0, I1, I2);
                 const int s1 = e.n0, s2 = e.n0 * e.n1;
                 const int c = (2 * I0 + 1) + (e.nd > 1 ? s1 * (2 * I1 + 1) : 0) +
                               (e.nd > 2 ? s2 * (2 * I2 + 1) : 0);
@@ -384,21 +390,21 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
                             if (e.nd > 2) wt = wt * full_weight(a2);
                             sum = sum + wt * r[c + a0 + s1 * a1 + s2 * a2];
                         }
-                bbuf(l + 1)[p] = sum;
-                xbuf(l + 1)[p] = 0.0;
+                bbuf(l + 1)[q] = sum;
+                xbuf(l + 1)[q] = 0.0;
             }
             __syncthreads();
         }
         for (int l = 0; l < t.count; ++l)
-            if (p < tab[l].N) {
-                t.xg[l][p] = xbuf(l)[p];
-                if (l > 0) t.bg[l][p] = bbuf(l)[p];
+            for (int q = p; q < tab[l].N; q += kThreads) {
+                t.xg[l][q] = xbuf(l)[q];
+                if (l > 0) t.bg[l][q] = bbuf(l)[q];
             }
     } else {
         for (int l = 0; l < t.count; ++l)
-            if (p < tab[l].N) {
-                xbuf(l)[p] = t.xg[l][p];
-                if (l + 1 < t.count) bbuf(l)[p] = t.bg[l][p];
+            for (int q = p; q < tab[l].N; q += kThreads) {
+                xbuf(l)[q] = t.xg[l][q];
+                if (l + 1 < t.count) bbuf(l)[q] = t.bg[l][q];
             }
         __syncthreads();
         for (int l = t.count - 2; l >= 0; --l) {
@@ -406,9 +412,9 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
             const TailTab e = tab[l], ec = tab[l + 1];
             const double *ev = xbuf(l + 1);
             double *x = xbuf(l);
-            if (p < e.N) {
+            for (int q = p; q < e.N; q += kThreads) {
                 int ii[3];
-                coords(e, p, ii[0], ii[1], ii[2]);
+                coords(e, q, ii[0], ii[1], ii[2]);
                 const int mm[3] = {ec.n0, ec.n1, ec.n2};
                 int cj[3][2];
                 double cw[3][2];
@@ -448,16 +454,16 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
                             double wt = cw[0][k0];
                             if (e.nd > 1) wt = wt * cw[1][k1];
                             if (e.nd > 2) wt = wt * cw[2][k2];
-                            const int q = cj[0][k0] + mm[0] * (cj[1][k1] + mm[1] * cj[2][k2]);
-                            const double val = ev[on ? q : 0];
+                            const int qc = cj[0][k0] + mm[0] * (cj[1][k1] + mm[1] * cj[2][k2]);
+                            const double val = ev[on ? qc : 0];
                             v = on ? v + wt * val : v;
                         }
-                x[p] = x[p] + v;
+                x[q] = x[q] + v;
             }
             __syncthreads();
             smooth(l, t.post);
         }
-        if (p < tab[0].N) t.xg[0][p] = xbuf(0)[p];
+        for (int q = p; q < tab[0].N; q += kThreads) t.xg[0][q] = xbuf(0)[q];
     }
 }
 
@@ -638,13 +644,13 @@ srj_status launch_tail(MgRun &run, int level)
 }
 
 // First level of the one-workgroup tail: the finest level of at most
-// kTailMaxPoints points below the finest grid and above the coarsest one,
+// tail_max_points(ndim) points below the finest grid and above the coarsest one,
 // whose levels down to the coarsest fit the tail's LDS and level count; -1
 // if there is none.
 int tail_start(const srj_mg *g, int Lc)
 {
     for (int l = 1; l < Lc; ++l) {
-        if (g->npts[l] > kTailMaxPoints) continue;
+        if (g->npts[l] > tail_max_points(g->ndim)) continue;
         int64_t doubles = 0;
         for (int k = l; k <= Lc; ++k) doubles += 3 * g->npts[k];
         if (doubles <= (int64_t)kTailLdsDoubles && Lc - l + 1 <= kTailMaxLevels) return l;
@@ -929,6 +935,17 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             sp.T = 2;
             sp.occ = 1;
             if (fused_supported(c->P, sp)) g->short_plan[l] = sp;
+        }
+    }
+    // the tail launches take up to kTailLdsDoubles doubles of dynamic LDS
+    const void *tails[2] = {reinterpret_cast<const void *>(&k_mg_tail<true>),
+                            reinterpret_cast<const void *>(&k_mg_tail<false>)};
+    for (const void *f : tails) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)(sizeof(double) * kTailLdsDoubles));
+        if (e != hipSuccess) {
+            mg_free(g);
+            return fail(SRJ_ERR_HIP, std::string("multigrid tail LDS: ") + hipGetErrorString(e));
         }
     }
     *out = g;
