@@ -159,7 +159,9 @@ srj_status validate_problem(const srj_problem *p);
 srj_status check_problem_arrays(const srj_problem *p, int dev);
 void fill_dev_problem(const srj_problem *p, DevProblem &P);
 
-// Sum of (b - A x)^2 into scratch.sum (device); blocks needed for scratch sizing.
+// Sum of (b - A x)^2 into scratch.sum (device).  residual_blocks: the
+// partial sums (one per workgroup of the norm, and of the refinement's outer
+// pass, which uses the same units) that the scratch must hold.
 int64_t residual_blocks(const DevProblem &P);
 hipError_t launch_residual_sumsq(const DevProblem &P, const double *x, ReduceScratch &rs,
                                  hipStream_t s);

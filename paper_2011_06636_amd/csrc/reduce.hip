@@ -3,9 +3,10 @@
 // section 3 and the stopping tests of section 4, e.g. Eq. (27)).
 //
 // The per-point residual uses the same expression order as the sweeps.  The
-// sum of squares is deterministic: wave shuffles and an LDS tree inside each
-// block, one partial per block, then one block folds the partials in a fixed
-// order.  No floating-point atomics.
+// sum of squares is deterministic: each thread adds its column's rows of a
+// unit in row order, then wave shuffles and an LDS tree inside the
+// workgroup give one partial per workgroup, and one workgroup folds the
+// partials in a fixed order.  No floating-point atomics.
 #include "internal.h"
 #include "rowband.h"
 
