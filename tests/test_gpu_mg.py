@@ -4,9 +4,11 @@ through the C ABI) against the oracle's (oracle/srj_mg.c).
 Transfers and smoothing evaluate the oracle's fixed-order expressions, so the
 iterate must be bit-identical, the smoothing scheme of every V-cycle the
 same, the counters (fine sweeps, coarsest-solve sweeps, work) equal, and the
-V-cycle norms equal to 1e-12 (sums in another order).  Grids: 1D, 2D with
+V-cycle norms equal to 1e-12 (sums in another order; on grids of more than
+about 9000 points to the error bound of the oracle's sequential sum).  Grids: 1D, 2D with
 unequal sides that stop coarsening at an even size, 3D, a hierarchy cut by
-max_levels, fixed and heuristic smoothing schemes, pre/post counts."""
+max_levels, fixed and heuristic smoothing schemes, pre/post counts, and the
+benchmark's full 2047^2 and 255^3 problems."""
 import numpy as np
 import pytest
 
@@ -41,6 +43,11 @@ CASES = [
      dict(rule="fixed", start_level=3)),
     # rows of at least 64 per plane are dealt to the XCDs in bands (3D)
     ("3d_127x127x7", lambda: _rand([127, 127, 7], 9), dict()),
+    # the benchmark's grids, as bench.py solves them (graph replays, the
+    # one-workgroup tail, the single-wave coarsest solve)
+    ("2d_c2_recipe_2047_full", lambda: workloads.c2(n=2047), dict(tol=2e-9)),
+    ("3d_255_full", lambda: workloads.poisson([255, 255, 255], b=np.random.default_rng(0).uniform(-1, 1, (255, 255, 255))),
+     dict()),
 ]
 
 
@@ -59,7 +66,11 @@ def test_mg_matches_oracle(torch_cuda, orc, case):
     np.testing.assert_array_equal(out["levels"], ref["levels"])
     assert out["sweeps"] == ref["sweeps"] and out["coarse_sweeps"] == ref["coarse_sweeps"]
     assert out["work"] == ref["work"]
-    np.testing.assert_allclose(out["norms"], ref["norms"], rtol=1e-12, atol=0)
+    # the oracle adds the squares in point order, whose relative error is
+    # bounded by (n - 1) 2^-53 for n positive terms (the GPU's tree sum by
+    # far less); the bar is 1e-12 wherever that bound is below it
+    rtol = max(1e-12, prob.npoints * 2.0 ** -53)
+    np.testing.assert_allclose(out["norms"], ref["norms"], rtol=rtol, atol=0)
     got = out["x"].cpu().numpy()
     assert np.array_equal(got, ref["x"]), (name, np.max(np.abs(got - ref["x"])))
     s.close()
