@@ -271,12 +271,13 @@ def test_3d_two_sweep_plans_bit_identical(torch_cuda, orc, case):
     s.close()
 
 
-@pytest.mark.parametrize("n", [27, 65, 5])
+@pytest.mark.parametrize("n", [27, 65, 5, 130])
 def test_3d_two_sweep_face_plans_bit_identical(torch_cuda, orc, n):
     # the per-face two-sweep plane kernels (plan kind 12, every tile shape,
     # odd and even cycle lengths) give the bits of the one-sweep kernel on
-    # variable-coefficient boxes (65: wider than one 60-column tile), and the
-    # oracle agrees; constant-coefficient boxes refuse them
+    # variable-coefficient boxes (65: wider than one 60-column tile; 130:
+    # tiles away from every face of the box too), and the oracle agrees;
+    # constant-coefficient boxes refuse them
     from paper_2011_06636_amd import abi
     prob = workloads.variable_coefficient(n, seed=n, corr_len=3.0)
     s = _solver(prob)
