@@ -230,7 +230,13 @@ srj_status srj_residual_norm_noalloc(const srj_problem *p, const double *x, void
  * cycle and norms_out (host, max_cycles + 1 entries) the initial norm and
  * each cycle-end norm; either may be NULL.  Returns SRJ_OK when converged,
  * SRJ_ERR_NOT_CONVERGED at a cap and SRJ_ERR_NONFINITE on a NaN/Inf norm,
- * with *res filled in every one of these cases. */
+ * with *res filled in every one of these cases.
+ * With the environment variable SRJ_LOG set (1 or "stderr": standard error;
+ * any other value except 0: a file appended to), a solve that ends with one
+ * of those statuses writes one line per cycle (level, its sweeps M, norm,
+ * ratio to the previous norm, -log(ratio) / M) and a summary line, formed
+ * from the histories after the solve (srj_mg_solve does the same per
+ * V-cycle). */
 srj_status srj_solve(srj_ctx *ctx, double *x, const srj_solve_opts *opts, srj_solve_result *res,
                      int32_t *levels_out, double *norms_out);
 

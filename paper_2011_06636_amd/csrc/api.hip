@@ -924,8 +924,35 @@ srj_status srj_run_cycle(srj_ctx *c, double *x, int32_t level, double *resnorm_o
     return residual_norm(c, x, resnorm_out);
 }
 
+static srj_status solve_dispatch(srj_ctx *c, double *x, const srj_solve_opts *o,
+                                 srj_solve_result *res, int32_t *levels_out, double *norms_out);
+
 srj_status srj_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_result *res,
                      int32_t *levels_out, double *norms_out)
+{
+    // the per-cycle log (SRJ_LOG) needs the histories: the solve then fills
+    // arrays of its own where the caller passes none
+    if (!log_enabled() || !c || !x || !o || !res || o->max_cycles < 1 || o->max_cycles > (1 << 24))
+        return solve_dispatch(c, x, o, res, levels_out, norms_out);
+    std::vector<int32_t> lv;
+    std::vector<double> nv;
+    if (!levels_out) {
+        lv.resize((size_t)o->max_cycles);
+        levels_out = lv.data();
+    }
+    if (!norms_out) {
+        nv.resize((size_t)o->max_cycles + 1);
+        norms_out = nv.data();
+    }
+    const srj_status st = solve_dispatch(c, x, o, res, levels_out, norms_out);
+    if (st == SRJ_OK || st == SRJ_ERR_NOT_CONVERGED || st == SRJ_ERR_NONFINITE)
+        log_cycles("solve", st, res->cycles, levels_out, c->levelM.data(), (int)c->levelM.size(),
+                   norms_out, res->sweeps, res->r0, res->r_final);
+    return st;
+}
+
+static srj_status solve_dispatch(srj_ctx *c, double *x, const srj_solve_opts *o,
+                                 srj_solve_result *res, int32_t *levels_out, double *norms_out)
 {
     if (!c || !x || !res) return fail(SRJ_ERR_INVALID, "NULL argument");
     srj_status st = validate_opts(o);

@@ -19,6 +19,14 @@ struct Refine;
 void set_error(const std::string &msg);
 srj_status fail(srj_status st, const std::string &msg);
 
+// The per-cycle solve log (log.cpp): whether SRJ_LOG asks for it, and the
+// lines of one ended solve from its level and norm histories (norms holds
+// cycles + 1 values, level_sweeps the sweeps of each of nlevels levels).
+bool log_enabled();
+void log_cycles(const char *what, srj_status st, int cycles, const int32_t *levels,
+                const int32_t *level_sweeps, int nlevels, const double *norms, int64_t sweeps,
+                double r0, double r_final);
+
 // Does [p, p + bytes) lie inside one allocation of device (or managed)
 // memory of device dev?  Host memory, pinned or not, is refused: the kernels
 // would fault on pageable memory.  Returns SRJ_OK, or SRJ_ERR_INVALID with a

@@ -952,8 +952,41 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
     return SRJ_OK;
 }
 
+static srj_status mg_solve_run(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_result *res,
+                               int32_t *levels_out, double *norms_out);
+
 srj_status srj_mg_solve(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_result *res,
                         int32_t *levels_out, double *norms_out)
+{
+    // the per-V-cycle log (SRJ_LOG) needs the histories: the solve then
+    // fills arrays of its own where the caller passes none
+    if (!log_enabled() || !g || !x || !o || !res || o->max_vcycles < 1 ||
+        o->max_vcycles > (1 << 24))
+        return mg_solve_run(g, x, o, res, levels_out, norms_out);
+    std::vector<int32_t> lv;
+    std::vector<double> nv;
+    if (!levels_out) {
+        lv.resize((size_t)o->max_vcycles);
+        levels_out = lv.data();
+    }
+    if (!norms_out) {
+        nv.resize((size_t)o->max_vcycles + 1);
+        norms_out = nv.data();
+    }
+    const srj_status st = mg_solve_run(g, x, o, res, levels_out, norms_out);
+    if (st == SRJ_OK || st == SRJ_ERR_NOT_CONVERGED || st == SRJ_ERR_NONFINITE) {
+        // finest-grid smoothing sweeps of a V-cycle at each smoothing level
+        const std::vector<int32_t> &lm = g->ctx[0]->levelM;
+        std::vector<int32_t> per(lm.size());
+        for (size_t l = 0; l < lm.size(); ++l) per[l] = (o->pre + o->post) * lm[l];
+        log_cycles("mg", st, res->vcycles, levels_out, per.data(), (int)per.size(), norms_out,
+                   res->sweeps, res->r0, res->r_final);
+    }
+    return st;
+}
+
+static srj_status mg_solve_run(srj_mg *g, double *x, const srj_mg_opts *o, srj_mg_result *res,
+                               int32_t *levels_out, double *norms_out)
 {
     if (!g || !x || !res) return fail(SRJ_ERR_INVALID, "NULL argument");
     srj_status st = validate_mg_opts(o);
