@@ -27,6 +27,8 @@
 #include "rowband.h"
 #include "resident_run.h"
 #include "rowsum.h"
+#include "tile2d.h"
+#include "wave2d.h"
 
 #pragma clang fp contract(off)
 
@@ -230,6 +232,162 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
         x[row + 2 * J] = ue[j];
         if (odd_in) x[row + 2 * J + 1] = uo[j];
     }
+}
+
+// The last pre-smoothing cycle of a 2D level (T <= 2 sweeps) and the fine
+// residual of its result in one pass: the wavefront strips of k_wave2d with a
+// halo of T + 1 rows and columns, whose extra stage, one row behind the last
+// sweep, forms r = b - A x of every written point from the last sweep's rows
+// (D x, then the axis-0 neighbours' c0 u moved by DPP, then the axis-1
+// neighbours: the fine residual's order; ghost values are zero, so an absent
+// neighbour's term subtracts +0 and changes no bit).  x and r of the strip's
+// 64 - 2 (T + 1) centre columns and OH centre rows are written.
+constexpr int kResOH = 8;
+
+template <int T>
+__device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const double *__restrict__ x,
+                                               double *__restrict__ xo, double *__restrict__ rout,
+                                               const double *__restrict__ b,
+                                               const double *__restrict__ wlist, Coef2D<double> k2,
+                                               int tx, int ty, int lane)
+{
+    using A = double;
+    constexpr int H = T + 1;  // halo: T sweeps and the residual
+    constexpr int R = kResOH + 2 * H;
+    constexpr int OW = 64 - 2 * H;
+    constexpr int PF = kWavePrefetch;
+    const int64_t gx = (int64_t)tx * OW - H + lane;
+    const int64_t gy0 = (int64_t)ty * kResOH - H;
+    const bool col_in = gx >= 0 && gx < n0;
+    const bool interior = (int64_t)tx * OW - H >= 0 && (int64_t)tx * OW - H + 64 <= n0 &&
+                          gy0 >= 0 && gy0 + R <= n1;
+    A w[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) w[k] = wlist[k];
+    // W[j]: the three latest rows of sweep level j (0: input), WT those of
+    // the last sweep, Bw[m]: b of row i - m
+    A W[T][3], WT[3], Bw[2 * T + 2];
+#pragma unroll
+    for (int j = 0; j < T; ++j) W[j][0] = W[j][1] = W[j][2] = A(0);
+    WT[0] = WT[1] = WT[2] = A(0);
+#pragma unroll
+    for (int j = 0; j < 2 * T + 2; ++j) Bw[j] = A(0);
+    const int64_t cx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx);
+    auto load_row = [&](int i, double &xv, double &bv) {
+        const int64_t gy = gy0 + i;
+        const int64_t cy = gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy);
+        const int64_t p = cy * n0 + cx;
+        xv = x[p];
+        bv = b[p];
+    };
+    auto in_grid = [&](int i) {
+        const int64_t gy = gy0 + i;
+        return interior || (col_in && gy >= 0 && gy < n1);
+    };
+    double xq[PF], bq[PF];  // raw rows i .. i + PF - 1
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_row(j, xq[j], bq[j]);
+    const bool lane_out = lane >= H && lane < 64 - H && col_in;
+#pragma unroll
+    for (int i = 0; i < R + T; ++i) {
+#pragma unroll
+        for (int j = 2 * T + 1; j > 0; --j) Bw[j] = Bw[j - 1];
+        const bool ok = i < R && in_grid(i);
+        const A xin = ok ? xq[0] : A(0);
+        Bw[0] = ok ? bq[0] : A(0);
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) {
+            xq[j] = xq[j + 1];
+            bq[j] = bq[j + 1];
+        }
+        load_row(i + PF, xq[PF - 1], bq[PF - 1]);
+        A nxt[T + 1];
+#pragma unroll
+        for (int k = 1; k <= T; ++k) {
+            const int r = i - 2 * k;  // row of sweep level k made at this step
+            const A xc = W[k - 1][1];
+            const A p0 = k2.c0 * xc;
+            A s = k2.D * xc;
+            s = s - dpp_prev(p0);
+            s = s - dpp_next(p0);
+            s = s - k2.c1 * W[k - 1][0];
+            s = s - k2.c1 * W[k - 1][2];
+            const A rr = Bw[2 * k] - s;
+            const A t = k2.Dinv * rr;
+            A nx = xc + w[k - 1] * t;
+            if (!(r >= 0 && r < R && in_grid(r))) nx = A(0);  // ghosts stay zero
+            nxt[k] = nx;
+            if (k == T && r >= H && r < R - H && lane_out && gy0 + r < n1)
+                xo[(gy0 + r) * n0 + gx] = nx;
+        }
+        W[0][0] = W[0][1];
+        W[0][1] = W[0][2];
+        W[0][2] = xin;
+#pragma unroll
+        for (int k = 1; k < T; ++k) {
+            W[k][0] = W[k][1];
+            W[k][1] = W[k][2];
+            W[k][2] = nxt[k];
+        }
+        WT[0] = WT[1];
+        WT[1] = WT[2];
+        WT[2] = nxt[T];
+        // the residual of row q = i - 2 T - 1 of the last sweep's iterate
+        const int q = i - 2 * T - 1;
+        if (q >= H && q < R - H) {
+            const A xc = WT[1];
+            const A p0 = k2.c0 * xc;
+            A s = k2.D * xc;
+            s = s - dpp_prev(p0);
+            s = s - dpp_next(p0);
+            s = s - k2.c1 * WT[0];
+            s = s - k2.c1 * WT[2];
+            const A v = Bw[2 * T + 1] - s;
+            if (lane_out && gy0 + q < n1) rout[(gy0 + q) * n0 + gx] = v;
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_wave2d_res(int64_t n0, int64_t n1,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ xo,
+                                                    double *__restrict__ rout,
+                                                    const double *__restrict__ b,
+                                                    const double *__restrict__ wlist,
+                                                    Coef2D<double> k2, int strips_x, int chunks_y,
+                                                    int nblocks)
+{
+    // XCD-aware order as in k_wave2d: each XCD a contiguous range of strips
+    const int per_xcd = (nblocks + 7) / 8;
+    const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int item = logical * 4 + (threadIdx.x >> 6);
+    if (logical >= nblocks || item >= strips_x * chunks_y) return;  // whole wave leaves
+    wave2d_res_run<T>(n0, n1, x, xo, rout, b, wlist, k2, item % strips_x, item / strips_x,
+                      threadIdx.x & 63);
+}
+
+// T (1 or 2) sweeps of a 2D constant-coefficient level from x to xo with
+// factors w_dev[0 .. T), and r = b - A xo.
+hipError_t launch_wave2d_res(const DevProblem &P, int T, const double *x, double *xo, double *r,
+                             const double *w_dev, hipStream_t s)
+{
+    if (P.ndim != 2 || P.face[0] || P.face[1] || P.diag || T < 1 || T > 2)
+        return hipErrorInvalidValue;
+    const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
+    const int OW = 64 - 2 * (T + 1);
+    const int strips_x = (int)((P.n0 + OW - 1) / OW);
+    const int chunks_y = (int)((P.n1 + kResOH - 1) / kResOH);
+    const int64_t items = (int64_t)strips_x * chunks_y;
+    const int nblocks = (int)((items + 3) / 4);
+    const int grid = (nblocks + 7) / 8 * 8;
+    if (T == 1)
+        hipLaunchKernelGGL(k_wave2d_res<1>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, r, P.b,
+                           w_dev, k2, strips_x, chunks_y, nblocks);
+    else
+        hipLaunchKernelGGL(k_wave2d_res<2>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, r, P.b,
+                           w_dev, k2, strips_x, chunks_y, nblocks);
+    return hipGetLastError();
 }
 
 // The coarse end of the V-cycle in three launches: every level from the
@@ -491,6 +649,7 @@ struct srj_mg {
     hipEvent_t ready = nullptr;     // the caller's null-stream work -> own
     std::vector<srj_ctx *> ctx;
     std::vector<double *> xb, bb;   // index 0 unused
+    std::vector<double *> rb;       // 2D: each level's fine residual from its last pre-smoothing launch
     std::vector<int64_t> npts;
     // V-cycles replayed from graphs: one per smoothing level, starting
     // buffer of the finest level and the options the cycle depends on
@@ -521,6 +680,7 @@ srj_status mg_free(srj_mg *g)
     for (srj_ctx *c : g->ctx) srj_destroy(c);
     for (double *p : g->xb) (void)hipFree(p);
     for (double *p : g->bb) (void)hipFree(p);
+    for (double *p : g->rb) (void)hipFree(p);
     for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
     (void)hipFree(g->rec);
     if (g->ready) (void)hipEventDestroy(g->ready);
@@ -578,6 +738,19 @@ srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double 
         hipLaunchKernelGGL(k_mg_restrict<3>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
         break;
     }
+    SRJ_HIP_CHECK(hipGetLastError());
+    return SRJ_OK;
+}
+
+// bc = R r from a fine residual already formed (xc = 0 unless xc is null)
+srj_status launch_restrict_only(const srj_ctx *c, const double *r, double *bc, double *xc,
+                                hipStream_t s)
+{
+    const DevProblem &P = c->P;
+    if (P.ndim != 2) return fail(SRJ_ERR_INVALID, "restriction of a formed residual: 2D only");
+    const int64_t m0 = (P.n0 - 1) / 2, m1 = (P.n1 - 1) / 2, m2 = 1;
+    const unsigned nb = (unsigned)row_grid(m0, m1, m2);
+    hipLaunchKernelGGL(k_mg_restrict<2>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
     SRJ_HIP_CHECK(hipGetLastError());
     return SRJ_OK;
 }
@@ -711,14 +884,28 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         run.cur[l] = cur;
         return SRJ_OK;
     };
-    srj_status st = pair_smooth(run.o->pre);
+    // 2D levels whose cycles have at most two sweeps: the last pre-smoothing
+    // cycle and the fine residual of its result in one launch
+    const int M = (int)c->factors[level].size();
+    const bool fuse = !g->rb.empty() && g->rb[l] && run.o->pre > 0 && M <= 2 && !c->profiling;
+    srj_status st = pair_smooth(fuse ? run.o->pre - 1 : run.o->pre);
     if (st != SRJ_OK) return st;
-    {
+    // the coarse correction starts from zero (the tail starts its own)
+    double *xz = run.graph && l + 1 == run.tail ? nullptr : g->xb[l + 1];
+    if (fuse) {
+        double *a = l == 0 ? x0 : g->xb[l];
+        double *cur = run.cur[l];
+        double *nxt = cur == a ? c->ws : a;
+        SRJ_HIP_CHECK(launch_wave2d_res(c->P, M, cur, nxt, g->rb[l],
+                                        c->omega_dev + c->offsets[level], g->stream));
+        run.cur[l] = nxt;
+        sw += M;
+        if ((st = launch_restrict_only(c, g->rb[l], g->bb[l + 1], xz, g->stream)) != SRJ_OK)
+            return st;
+    } else {
         // the level's other buffer holds nothing live until the post-smoothing
         double *a = l == 0 ? x0 : g->xb[l];
         double *spare = run.cur[l] == a ? c->ws : a;
-        // the coarse correction starts from zero (the tail starts its own)
-        double *xz = run.graph && l + 1 == run.tail ? nullptr : g->xb[l + 1];
         if ((st = launch_restrict(c, run.cur[l], spare, g->bb[l + 1], xz, g->stream)) != SRJ_OK)
             return st;
     }
@@ -936,6 +1123,17 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             sp.occ = 1;
             if (fused_supported(c->P, sp)) g->short_plan[l] = sp;
         }
+    }
+    // 2D: a buffer per level for the fine residual that the last
+    // pre-smoothing launch forms (the level's two iterate buffers are busy then)
+    if (g->ndim == 2) {
+        g->rb.assign(g->L, nullptr);
+        for (int l = 0; l + 1 < g->L; ++l)
+            if (hipMalloc(&g->rb[l], sizeof(double) * (size_t)g->npts[l]) != hipSuccess) {
+                g->rb[l] = nullptr;
+                mg_free(g);
+                return fail(SRJ_ERR_NOMEM, "hipMalloc failed for a multigrid residual buffer");
+            }
     }
     // the tail launches take up to kTailLdsDoubles doubles of dynamic LDS
     const void *tails[2] = {reinterpret_cast<const void *>(&k_mg_tail<true>),
