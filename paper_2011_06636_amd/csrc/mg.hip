@@ -234,28 +234,37 @@ __global__ __launch_bounds__(kMgBlock) void k_prolong_add(const double *__restri
     }
 }
 
-// The last pre-smoothing cycle of a 2D level (T <= 2 sweeps) and the fine
-// residual of its result in one pass: the wavefront strips of k_wave2d with a
-// halo of T + 1 rows and columns, whose extra stage, one row behind the last
-// sweep, forms r = b - A x of every written point from the last sweep's rows
-// (D x, then the axis-0 neighbours' c0 u moved by DPP, then the axis-1
-// neighbours: the fine residual's order; ghost values are zero, so an absent
-// neighbour's term subtracts +0 and changes no bit).  x and r of the strip's
-// 64 - 2 (T + 1) centre columns and OH centre rows are written.
+// The last pre-smoothing cycle of a 2D level (T <= 2 sweeps), the fine
+// residual of its result and the restriction of that residual, in one pass:
+// the wavefront strips of k_wave2d with a halo of T + 2 rows and columns.
+// One stage behind the last sweep forms r = b - A x (D x, then the axis-0
+// neighbours' c0 u moved by DPP, then the axis-1 neighbours: the fine
+// residual's order; ghost values are zero, so an absent neighbour's term
+// subtracts +0 and changes no bit) for the written points and one more row
+// and column around them; a stage behind that forms, at every written point
+// of odd row and column, the full-weighting sum of the coarse point it
+// centres (rows -1, 0, 1 outer, columns -1, 0, 1 inner, the restriction's
+// order) and writes it to the coarse right-hand side, and zero to the coarse
+// correction unless that is null.  The residual itself is never stored.
+// Written: x of the strip's 64 - 2 (T + 2) centre columns and OH centre rows
+// (both even, so each coarse point belongs to exactly one strip and chunk).
 constexpr int kResOH = 8;
 
 template <int T>
-__device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const double *__restrict__ x,
-                                               double *__restrict__ xo, double *__restrict__ rout,
-                                               const double *__restrict__ b,
-                                               const double *__restrict__ wlist, Coef2D<double> k2,
-                                               int tx, int ty, int lane)
+__device__ __forceinline__ void wave2d_rr_run(int64_t n0, int64_t n1, const double *__restrict__ x,
+                                              double *__restrict__ xo, double *__restrict__ bc,
+                                              double *__restrict__ xc0,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ wlist, Coef2D<double> k2,
+                                              int tx, int ty, int lane)
 {
     using A = double;
-    constexpr int H = T + 1;  // halo: T sweeps and the residual
+    constexpr int H = T + 2;  // halo: T sweeps, the residual, the restriction
     constexpr int R = kResOH + 2 * H;
     constexpr int OW = 64 - 2 * H;
     constexpr int PF = kWavePrefetch;
+    static_assert(OW % 2 == 0 && kResOH % 2 == 0, "strips and chunks start at even fine indices");
+    const int64_t m0 = (n0 - 1) / 2;
     const int64_t gx = (int64_t)tx * OW - H + lane;
     const int64_t gy0 = (int64_t)ty * kResOH - H;
     const bool col_in = gx >= 0 && gx < n0;
@@ -265,11 +274,12 @@ __device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const dou
 #pragma unroll
     for (int k = 0; k < T; ++k) w[k] = wlist[k];
     // W[j]: the three latest rows of sweep level j (0: input), WT those of
-    // the last sweep, Bw[m]: b of row i - m
-    A W[T][3], WT[3], Bw[2 * T + 2];
+    // the last sweep, RW those of the residual, Bw[m]: b of row i - m
+    A W[T][3], WT[3], RW[3], Bw[2 * T + 2];
 #pragma unroll
     for (int j = 0; j < T; ++j) W[j][0] = W[j][1] = W[j][2] = A(0);
     WT[0] = WT[1] = WT[2] = A(0);
+    RW[0] = RW[1] = RW[2] = A(0);
 #pragma unroll
     for (int j = 0; j < 2 * T + 2; ++j) Bw[j] = A(0);
     const int64_t cx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx);
@@ -288,6 +298,8 @@ __device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const dou
 #pragma unroll
     for (int j = 0; j < PF; ++j) load_row(j, xq[j], bq[j]);
     const bool lane_out = lane >= H && lane < 64 - H && col_in;
+    // a coarse point centred at this lane's column: odd column, not the last
+    const bool coarse_col = lane_out && (gx & 1) && gx < n0 - 1;
 #pragma unroll
     for (int i = 0; i < R + T; ++i) {
 #pragma unroll
@@ -332,9 +344,8 @@ __device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const dou
         WT[0] = WT[1];
         WT[1] = WT[2];
         WT[2] = nxt[T];
-        // the residual of row q = i - 2 T - 1 of the last sweep's iterate
-        const int q = i - 2 * T - 1;
-        if (q >= H && q < R - H) {
+        // the residual of row i - 2 T - 1 of the last sweep's iterate
+        {
             const A xc = WT[1];
             const A p0 = k2.c0 * xc;
             A s = k2.D * xc;
@@ -342,51 +353,76 @@ __device__ __forceinline__ void wave2d_res_run(int64_t n0, int64_t n1, const dou
             s = s - dpp_next(p0);
             s = s - k2.c1 * WT[0];
             s = s - k2.c1 * WT[2];
-            const A v = Bw[2 * T + 1] - s;
-            if (lane_out && gy0 + q < n1) rout[(gy0 + q) * n0 + gx] = v;
+            RW[0] = RW[1];
+            RW[1] = RW[2];
+            RW[2] = Bw[2 * T + 1] - s;
+        }
+        // full weighting centred at row q = i - 2 T - 2 (residual rows q - 1,
+        // q, q + 1 are RW[0 .. 2])
+        const int q = i - 2 * T - 2;
+        if (q >= H && q < R - H) {
+            A sum = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 < 3; ++a1) {
+                const A row = RW[a1];
+                const A v[3] = {dpp_prev(row), row, dpp_next(row)};
+#pragma unroll
+                for (int a0 = 0; a0 < 3; ++a0) {
+                    const A wt = full_weight(a0 - 1) * full_weight(a1 - 1);
+                    sum = sum + wt * v[a0];
+                }
+            }
+            const int64_t gy = gy0 + q;
+            if (coarse_col && (gy & 1) && gy < n1 - 1) {
+                const int64_t t = (gx - 1) / 2 + m0 * ((gy - 1) / 2);
+                bc[t] = sum;
+                if (xc0) xc0[t] = 0.0;  // the coarse correction starts from zero
+            }
         }
     }
 }
 
 template <int T>
-__global__ __launch_bounds__(256) void k_wave2d_res(int64_t n0, int64_t n1,
-                                                    const double *__restrict__ x,
-                                                    double *__restrict__ xo,
-                                                    double *__restrict__ rout,
-                                                    const double *__restrict__ b,
-                                                    const double *__restrict__ wlist,
-                                                    Coef2D<double> k2, int strips_x, int chunks_y,
-                                                    int nblocks)
+__global__ __launch_bounds__(256) void k_wave2d_rr(int64_t n0, int64_t n1,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ xo, double *__restrict__ bc,
+                                                   double *__restrict__ xc0,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ wlist,
+                                                   Coef2D<double> k2, int strips_x, int chunks_y,
+                                                   int nblocks)
 {
     // XCD-aware order as in k_wave2d: each XCD a contiguous range of strips
     const int per_xcd = (nblocks + 7) / 8;
     const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int item = logical * 4 + (threadIdx.x >> 6);
     if (logical >= nblocks || item >= strips_x * chunks_y) return;  // whole wave leaves
-    wave2d_res_run<T>(n0, n1, x, xo, rout, b, wlist, k2, item % strips_x, item / strips_x,
-                      threadIdx.x & 63);
+    wave2d_rr_run<T>(n0, n1, x, xo, bc, xc0, b, wlist, k2, item % strips_x, item / strips_x,
+                     threadIdx.x & 63);
 }
 
 // T (1 or 2) sweeps of a 2D constant-coefficient level from x to xo with
-// factors w_dev[0 .. T), and r = b - A xo.
-hipError_t launch_wave2d_res(const DevProblem &P, int T, const double *x, double *xo, double *r,
-                             const double *w_dev, hipStream_t s)
+// factors w_dev[0 .. T), then bc = R (b - A xo) on the coarse grid and xc = 0
+// unless xc is null.
+hipError_t launch_wave2d_rr(const DevProblem &P, int T, const double *x, double *xo, double *bc,
+                            double *xc, const double *w_dev, hipStream_t s)
 {
-    if (P.ndim != 2 || P.face[0] || P.face[1] || P.diag || T < 1 || T > 2)
+    if (P.ndim != 2 || P.face[0] || P.face[1] || P.diag || T < 1 || T > 2 || P.n0 % 2 == 0 ||
+        P.n1 % 2 == 0)
         return hipErrorInvalidValue;
     const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
-    const int OW = 64 - 2 * (T + 1);
+    const int OW = 64 - 2 * (T + 2);
     const int strips_x = (int)((P.n0 + OW - 1) / OW);
     const int chunks_y = (int)((P.n1 + kResOH - 1) / kResOH);
     const int64_t items = (int64_t)strips_x * chunks_y;
     const int nblocks = (int)((items + 3) / 4);
     const int grid = (nblocks + 7) / 8 * 8;
     if (T == 1)
-        hipLaunchKernelGGL(k_wave2d_res<1>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, r, P.b,
-                           w_dev, k2, strips_x, chunks_y, nblocks);
+        hipLaunchKernelGGL(k_wave2d_rr<1>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, bc, xc,
+                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
     else
-        hipLaunchKernelGGL(k_wave2d_res<2>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, r, P.b,
-                           w_dev, k2, strips_x, chunks_y, nblocks);
+        hipLaunchKernelGGL(k_wave2d_rr<2>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, bc, xc,
+                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
     return hipGetLastError();
 }
 
@@ -649,7 +685,6 @@ struct srj_mg {
     hipEvent_t ready = nullptr;     // the caller's null-stream work -> own
     std::vector<srj_ctx *> ctx;
     std::vector<double *> xb, bb;   // index 0 unused
-    std::vector<double *> rb;       // 2D: each level's fine residual from its last pre-smoothing launch
     std::vector<int64_t> npts;
     // V-cycles replayed from graphs: one per smoothing level, starting
     // buffer of the finest level and the options the cycle depends on
@@ -680,7 +715,6 @@ srj_status mg_free(srj_mg *g)
     for (srj_ctx *c : g->ctx) srj_destroy(c);
     for (double *p : g->xb) (void)hipFree(p);
     for (double *p : g->bb) (void)hipFree(p);
-    for (double *p : g->rb) (void)hipFree(p);
     for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
     (void)hipFree(g->rec);
     if (g->ready) (void)hipEventDestroy(g->ready);
@@ -742,18 +776,6 @@ srj_status launch_restrict(const srj_ctx *c, const double *x, double *r, double 
     return SRJ_OK;
 }
 
-// bc = R r from a fine residual already formed (xc = 0 unless xc is null)
-srj_status launch_restrict_only(const srj_ctx *c, const double *r, double *bc, double *xc,
-                                hipStream_t s)
-{
-    const DevProblem &P = c->P;
-    if (P.ndim != 2) return fail(SRJ_ERR_INVALID, "restriction of a formed residual: 2D only");
-    const int64_t m0 = (P.n0 - 1) / 2, m1 = (P.n1 - 1) / 2, m2 = 1;
-    const unsigned nb = (unsigned)row_grid(m0, m1, m2);
-    hipLaunchKernelGGL(k_mg_restrict<2>, dim3(nb), dim3(kMgBlock), 0, s, r, bc, xc, P.n0, P.n1, m0, m1, m2);
-    SRJ_HIP_CHECK(hipGetLastError());
-    return SRJ_OK;
-}
 
 srj_status launch_prolong(const srj_ctx *c, const double *ec, double *x, hipStream_t s)
 {
@@ -885,9 +907,9 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         return SRJ_OK;
     };
     // 2D levels whose cycles have at most two sweeps: the last pre-smoothing
-    // cycle and the fine residual of its result in one launch
+    // cycle, the fine residual of its result and its restriction in one launch
     const int M = (int)c->factors[level].size();
-    const bool fuse = !g->rb.empty() && g->rb[l] && run.o->pre > 0 && M <= 2 && !c->profiling;
+    const bool fuse = g->ndim == 2 && run.o->pre > 0 && M <= 2 && !c->profiling;
     srj_status st = pair_smooth(fuse ? run.o->pre - 1 : run.o->pre);
     if (st != SRJ_OK) return st;
     // the coarse correction starts from zero (the tail starts its own)
@@ -896,12 +918,10 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         double *a = l == 0 ? x0 : g->xb[l];
         double *cur = run.cur[l];
         double *nxt = cur == a ? c->ws : a;
-        SRJ_HIP_CHECK(launch_wave2d_res(c->P, M, cur, nxt, g->rb[l],
-                                        c->omega_dev + c->offsets[level], g->stream));
+        SRJ_HIP_CHECK(launch_wave2d_rr(c->P, M, cur, nxt, g->bb[l + 1], xz,
+                                       c->omega_dev + c->offsets[level], g->stream));
         run.cur[l] = nxt;
         sw += M;
-        if ((st = launch_restrict_only(c, g->rb[l], g->bb[l + 1], xz, g->stream)) != SRJ_OK)
-            return st;
     } else {
         // the level's other buffer holds nothing live until the post-smoothing
         double *a = l == 0 ? x0 : g->xb[l];
@@ -1123,17 +1143,6 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             sp.occ = 1;
             if (fused_supported(c->P, sp)) g->short_plan[l] = sp;
         }
-    }
-    // 2D: a buffer per level for the fine residual that the last
-    // pre-smoothing launch forms (the level's two iterate buffers are busy then)
-    if (g->ndim == 2) {
-        g->rb.assign(g->L, nullptr);
-        for (int l = 0; l + 1 < g->L; ++l)
-            if (hipMalloc(&g->rb[l], sizeof(double) * (size_t)g->npts[l]) != hipSuccess) {
-                g->rb[l] = nullptr;
-                mg_free(g);
-                return fail(SRJ_ERR_NOMEM, "hipMalloc failed for a multigrid residual buffer");
-            }
     }
     // the tail launches take up to kTailLdsDoubles doubles of dynamic LDS
     const void *tails[2] = {reinterpret_cast<const void *>(&k_mg_tail<true>),
