@@ -426,6 +426,194 @@ hipError_t launch_wave2d_rr(const DevProblem &P, int T, const double *x, double 
     return hipGetLastError();
 }
 
+// The interpolation of the coarse correction and the first post-smoothing
+// cycle of a 2D level (T <= 2 sweeps) in one pass: the wavefront strips of
+// k_wave2d (halo T + 1) whose input rows are x + P e, formed as the
+// interpolation kernel forms them (axis-1 candidates outer, axis-0 inner,
+// each in increasing order, absent candidates skipped).  Each lane loads,
+// per coarse row it needs, the coarse value of column floor(gx / 2); an even
+// column's other candidate, floor(gx / 2) - 1, is its left lane's value,
+// moved by DPP (lane 0's is wrong, but only ever feeds halo points).
+template <int T>
+__device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const double *__restrict__ x,
+                                              double *__restrict__ xo,
+                                              const double *__restrict__ ec,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ wlist, Coef2D<double> k2,
+                                              int tx, int ty, int lane)
+{
+    using A = double;
+    constexpr int H = T + 1;
+    constexpr int R = kResOH + 2 * H;
+    constexpr int OW = 64 - 2 * H;
+    constexpr int PF = 4;  // rows loaded ahead: four rings of them
+    const int64_t m0 = (n0 - 1) / 2, m1 = (n1 - 1) / 2;
+    const int64_t gx = (int64_t)tx * OW - H + lane;
+    const int64_t gy0 = (int64_t)ty * kResOH - H;
+    const bool col_in = gx >= 0 && gx < n0;
+    const bool interior = (int64_t)tx * OW - H >= 0 && (int64_t)tx * OW - H + 64 <= n0 &&
+                          gy0 >= 0 && gy0 + R <= n1;
+    A w[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) w[k] = wlist[k];
+    A W[T][3], Bw[2 * T + 1];
+#pragma unroll
+    for (int j = 0; j < T; ++j) W[j][0] = W[j][1] = W[j][2] = A(0);
+#pragma unroll
+    for (int j = 0; j <= 2 * T; ++j) Bw[j] = A(0);
+    const int64_t cx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx);
+    // axis 0: this lane's coarse column and the candidates' weights
+    const int64_t I = gx >> 1;  // floor(gx / 2), gx >= -H
+    const int64_t ci = I < 0 ? 0 : (I >= m0 ? m0 - 1 : I);
+    const bool odd = (gx & 1) != 0;
+    const bool has_lo = !odd && I - 1 >= 0;  // even column: candidate I - 1
+    const bool has_hi = odd || I < m0;       // candidate I (the odd column's only one)
+    const A cw0 = odd ? 1.0 : 0.5;
+    // coarse rows of fine row gy: J0 (weight cw1), and for even rows J0 + 1
+    auto crow = [&](int64_t gy, int64_t &j0, int64_t &j1, bool &h0, bool &h1, A &cw1) {
+        if (gy & 1) {
+            j0 = (gy - 1) / 2;
+            j1 = j0;
+            h0 = true;
+            h1 = false;
+            cw1 = 1.0;
+        } else {
+            const int64_t J = gy / 2;
+            j0 = J - 1;
+            j1 = J;
+            h0 = J - 1 >= 0;
+            h1 = J < m1;
+            cw1 = 0.5;
+        }
+    };
+    auto load_row = [&](int i, double &xv, double &bv, double &e0, double &e1) {
+        const int64_t gy = gy0 + i;
+        const int64_t cy = gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy);
+        const int64_t p = cy * n0 + cx;
+        xv = x[p];
+        bv = b[p];
+        int64_t j0, j1;
+        bool h0, h1;
+        A cw1;
+        crow(cy, j0, j1, h0, h1, cw1);
+        const int64_t r0 = j0 < 0 ? 0 : (j0 >= m1 ? m1 - 1 : j0);
+        const int64_t r1 = j1 < 0 ? 0 : (j1 >= m1 ? m1 - 1 : j1);
+        e0 = ec[r0 * m0 + ci];
+        e1 = ec[r1 * m0 + ci];
+    };
+    auto in_grid = [&](int i) {
+        const int64_t gy = gy0 + i;
+        return interior || (col_in && gy >= 0 && gy < n1);
+    };
+    double xq[PF], bq[PF], eq0[PF], eq1[PF];  // raw rows i .. i + PF - 1
+#pragma unroll
+    for (int j = 0; j < PF; ++j) load_row(j, xq[j], bq[j], eq0[j], eq1[j]);
+#pragma unroll
+    for (int i = 0; i < R + T; ++i) {
+#pragma unroll
+        for (int j = 2 * T; j > 0; --j) Bw[j] = Bw[j - 1];
+        const bool ok = i < R && in_grid(i);
+        // x + P e of row i
+        A xin;
+        {
+            const int64_t gy = gy0 + i;
+            const int64_t cy = gy < 0 ? 0 : (gy >= n1 ? n1 - 1 : gy);
+            int64_t j0, j1;
+            bool h0, h1;
+            A cw1;
+            crow(cy, j0, j1, h0, h1, cw1);
+            const A lo0 = dpp_prev(eq0[0]), lo1 = dpp_prev(eq1[0]);  // column I - 1
+            const A wt = cw0 * cw1;
+            A v = 0.0;
+            v = (h0 && has_lo) ? v + wt * lo0 : v;
+            v = (h0 && has_hi) ? v + wt * eq0[0] : v;
+            v = (h1 && has_lo) ? v + wt * lo1 : v;
+            v = (h1 && has_hi) ? v + wt * eq1[0] : v;
+            xin = ok ? xq[0] + v : A(0);
+        }
+        Bw[0] = ok ? bq[0] : A(0);
+#pragma unroll
+        for (int j = 0; j + 1 < PF; ++j) {
+            xq[j] = xq[j + 1];
+            bq[j] = bq[j + 1];
+            eq0[j] = eq0[j + 1];
+            eq1[j] = eq1[j + 1];
+        }
+        load_row(i + PF, xq[PF - 1], bq[PF - 1], eq0[PF - 1], eq1[PF - 1]);
+        A nxt[T + 1];
+#pragma unroll
+        for (int k = 1; k <= T; ++k) {
+            const int r = i - 2 * k;
+            const A xc = W[k - 1][1];
+            const A p0 = k2.c0 * xc;
+            A s = k2.D * xc;
+            s = s - dpp_prev(p0);
+            s = s - dpp_next(p0);
+            s = s - k2.c1 * W[k - 1][0];
+            s = s - k2.c1 * W[k - 1][2];
+            const A rr = Bw[2 * k] - s;
+            const A t = k2.Dinv * rr;
+            A nx = xc + w[k - 1] * t;
+            if (!(r >= 0 && r < R && in_grid(r))) nx = A(0);  // ghosts stay zero
+            nxt[k] = nx;
+            if (k == T && r >= H && r < R - H && lane >= H && lane < 64 - H && col_in &&
+                gy0 + r < n1)
+                xo[(gy0 + r) * n0 + gx] = nx;
+        }
+        W[0][0] = W[0][1];
+        W[0][1] = W[0][2];
+        W[0][2] = xin;
+#pragma unroll
+        for (int k = 1; k < T; ++k) {
+            W[k][0] = W[k][1];
+            W[k][1] = W[k][2];
+            W[k][2] = nxt[k];
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_wave2d_pp(int64_t n0, int64_t n1,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ xo,
+                                                   const double *__restrict__ ec,
+                                                   const double *__restrict__ b,
+                                                   const double *__restrict__ wlist,
+                                                   Coef2D<double> k2, int strips_x, int chunks_y,
+                                                   int nblocks)
+{
+    const int per_xcd = (nblocks + 7) / 8;
+    const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int item = logical * 4 + (threadIdx.x >> 6);
+    if (logical >= nblocks || item >= strips_x * chunks_y) return;  // whole wave leaves
+    wave2d_pp_run<T>(n0, n1, x, xo, ec, b, wlist, k2, item % strips_x, item / strips_x,
+                     threadIdx.x & 63);
+}
+
+// x + P ec, then T (1 or 2) sweeps of a 2D constant-coefficient level into
+// xo with factors w_dev[0 .. T).
+hipError_t launch_wave2d_pp(const DevProblem &P, int T, const double *x, double *xo,
+                            const double *ec, const double *w_dev, hipStream_t s)
+{
+    if (P.ndim != 2 || P.face[0] || P.face[1] || P.diag || T < 1 || T > 2 || P.n0 % 2 == 0 ||
+        P.n1 % 2 == 0 || P.n0 < 3 || P.n1 < 3)
+        return hipErrorInvalidValue;
+    const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
+    const int OW = 64 - 2 * (T + 1);
+    const int strips_x = (int)((P.n0 + OW - 1) / OW);
+    const int chunks_y = (int)((P.n1 + kResOH - 1) / kResOH);
+    const int64_t items = (int64_t)strips_x * chunks_y;
+    const int nblocks = (int)((items + 3) / 4);
+    const int grid = (nblocks + 7) / 8 * 8;
+    if (T == 1)
+        hipLaunchKernelGGL(k_wave2d_pp<1>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, ec,
+                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
+    else
+        hipLaunchKernelGGL(k_wave2d_pp<2>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, ec,
+                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
+    return hipGetLastError();
+}
+
 // The coarse end of the V-cycle in three launches: every level from the
 // first one of at most kTailMaxPoints points down to the coarsest is held in
 // one workgroup's LDS (per level x, its ping-pong partner and b) by
@@ -932,8 +1120,20 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
     double *xc = g->xb[l + 1];
     run.cur[l + 1] = xc;
     if ((st = vcycle(run, l + 1, level, x0)) != SRJ_OK) return st;
-    if ((st = launch_prolong(c, run.cur[l + 1], run.cur[l], g->stream)) != SRJ_OK) return st;
-    if ((st = pair_smooth(run.o->post)) != SRJ_OK) return st;
+    if (g->ndim == 2 && run.o->post > 0 && M <= 2 && !c->profiling) {
+        // the interpolation and the first post-smoothing cycle in one launch
+        double *a = l == 0 ? x0 : g->xb[l];
+        double *cur = run.cur[l];
+        double *nxt = cur == a ? c->ws : a;
+        SRJ_HIP_CHECK(launch_wave2d_pp(c->P, M, cur, nxt, run.cur[l + 1],
+                                       c->omega_dev + c->offsets[level], g->stream));
+        run.cur[l] = nxt;
+        sw += M;
+        if ((st = pair_smooth(run.o->post - 1)) != SRJ_OK) return st;
+    } else {
+        if ((st = launch_prolong(c, run.cur[l + 1], run.cur[l], g->stream)) != SRJ_OK) return st;
+        if ((st = pair_smooth(run.o->post)) != SRJ_OK) return st;
+    }
     if (!run.graph) {
         if (l == 0) run.res->sweeps += sw;
         run.res->work += (double)sw * frac;
