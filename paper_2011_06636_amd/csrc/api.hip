@@ -291,6 +291,19 @@ srj_status residual_norm(srj_ctx *c, const double *x, double *out)
     return collect_profile(c);
 }
 
+srj_status fold_norm(srj_ctx *c, double *partials, int64_t n, double *out)
+{
+    ReduceScratch rs = c->rs;  // its device and pinned scalars
+    rs.partials = partials;
+    rs.capacity = n;
+    SRJ_HIP_CHECK(launch_fold(rs, n, c->stream));
+    SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    *out = sqrt(*c->rs.host_sum);
+    return collect_profile(c);
+}
+
 int next_level(srj_rule rule, int level, double ratio, int max_level)
 {
     int nl = level;

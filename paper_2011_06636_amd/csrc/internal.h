@@ -236,6 +236,9 @@ struct srj_ctx {
 namespace srj {
 srj_status run_sweeps(srj_ctx *c, double **cur, double **nxt, int level);
 srj_status residual_norm(srj_ctx *c, const double *x, double *out);
+// The L2 norm from n partial sums of squares (device) that a kernel left:
+// folded in a fixed order on c's stream, host result, blocking.
+srj_status fold_norm(srj_ctx *c, double *partials, int64_t n, double *out);
 srj_status collect_profile(srj_ctx *c);
 int next_level(srj_rule rule, int level, double ratio, int max_level);
 // Refinement (refine.hip).

@@ -433,17 +433,23 @@ hipError_t launch_wave2d_rr(const DevProblem &P, int T, const double *x, double 
 // each in increasing order, absent candidates skipped).  Each lane loads,
 // per coarse row it needs, the coarse value of column floor(gx / 2); an even
 // column's other candidate, floor(gx / 2) - 1, is its left lane's value,
-// moved by DPP (lane 0's is wrong, but only ever feeds halo points).
-template <int T>
+// moved by DPP.  The halo is odd (T + 1 rounded up to odd) and strips are an
+// even number of columns wide, so lane 0 sits on an odd column and needs no
+// left lane.  With part non-null the pass also sums the squares of
+// r = b - A x of its written points (the residual norm's expression order)
+// into one partial per strip chunk.
+template <int T, bool NORM>
 __device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const double *__restrict__ x,
                                               double *__restrict__ xo,
                                               const double *__restrict__ ec,
                                               const double *__restrict__ b,
                                               const double *__restrict__ wlist, Coef2D<double> k2,
-                                              int tx, int ty, int lane)
+                                              int tx, int ty, int lane, double *__restrict__ part,
+                                              int item)
 {
     using A = double;
-    constexpr int H = T + 1;
+    constexpr int H = (T + 1) | 1;  // odd: lane 0 on an odd column
+    static_assert(H % 2 == 1 && H >= T + 1, "an odd halo of at least T + 1");
     constexpr int R = kResOH + 2 * H;
     constexpr int OW = 64 - 2 * H;
     constexpr int PF = 4;  // rows loaded ahead: four rings of them
@@ -456,11 +462,15 @@ __device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const doub
     A w[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) w[k] = wlist[k];
-    A W[T][3], Bw[2 * T + 1];
+    // W[j]: the three latest rows of sweep level j (0: input), WT those of
+    // the last sweep (NORM), Bw[m]: b of row i - m
+    A W[T][3], WT[3], Bw[2 * T + 2];
 #pragma unroll
     for (int j = 0; j < T; ++j) W[j][0] = W[j][1] = W[j][2] = A(0);
+    WT[0] = WT[1] = WT[2] = A(0);
 #pragma unroll
-    for (int j = 0; j <= 2 * T; ++j) Bw[j] = A(0);
+    for (int j = 0; j < 2 * T + 2; ++j) Bw[j] = A(0);
+    double acc = 0.0;  // NORM: this lane's squared residuals, in row order
     const int64_t cx = gx < 0 ? 0 : (gx >= n0 ? n0 - 1 : gx);
     // axis 0: this lane's coarse column and the candidates' weights
     const int64_t I = gx >> 1;  // floor(gx / 2), gx >= -H
@@ -508,10 +518,11 @@ __device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const doub
     double xq[PF], bq[PF], eq0[PF], eq1[PF];  // raw rows i .. i + PF - 1
 #pragma unroll
     for (int j = 0; j < PF; ++j) load_row(j, xq[j], bq[j], eq0[j], eq1[j]);
+    const bool lane_out = lane >= H && lane < 64 - H && col_in;
 #pragma unroll
     for (int i = 0; i < R + T; ++i) {
 #pragma unroll
-        for (int j = 2 * T; j > 0; --j) Bw[j] = Bw[j - 1];
+        for (int j = 2 * T + 1; j > 0; --j) Bw[j] = Bw[j - 1];
         const bool ok = i < R && in_grid(i);
         // x + P e of row i
         A xin;
@@ -556,8 +567,7 @@ __device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const doub
             A nx = xc + w[k - 1] * t;
             if (!(r >= 0 && r < R && in_grid(r))) nx = A(0);  // ghosts stay zero
             nxt[k] = nx;
-            if (k == T && r >= H && r < R - H && lane >= H && lane < 64 - H && col_in &&
-                gy0 + r < n1)
+            if (k == T && r >= H && r < R - H && lane_out && gy0 + r < n1)
                 xo[(gy0 + r) * n0 + gx] = nx;
         }
         W[0][0] = W[0][1];
@@ -569,10 +579,35 @@ __device__ __forceinline__ void wave2d_pp_run(int64_t n0, int64_t n1, const doub
             W[k][1] = W[k][2];
             W[k][2] = nxt[k];
         }
+        if constexpr (NORM) {
+            // r = b - A x of written row q = i - 2 T - 1 of the last sweep's
+            // iterate, in the residual norm's expression order
+            WT[0] = WT[1];
+            WT[1] = WT[2];
+            WT[2] = nxt[T];
+            const int q = i - 2 * T - 1;
+            if (q >= H && q < R - H) {
+                const A xc = WT[1];
+                const A p0 = k2.c0 * xc;
+                A s = k2.D * xc;
+                s = s - dpp_prev(p0);
+                s = s - dpp_next(p0);
+                s = s - k2.c1 * WT[0];
+                s = s - k2.c1 * WT[2];
+                const A v = Bw[2 * T + 1] - s;
+                acc = (lane_out && gy0 + q < n1) ? acc + v * v : acc;
+            }
+        }
+    }
+    if constexpr (NORM) {
+        // fixed-order sum over the wave, one partial per strip chunk
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) part[item] = acc;
     }
 }
 
-template <int T>
+template <int T, bool NORM>
 __global__ __launch_bounds__(256) void k_wave2d_pp(int64_t n0, int64_t n1,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ xo,
@@ -580,37 +615,52 @@ __global__ __launch_bounds__(256) void k_wave2d_pp(int64_t n0, int64_t n1,
                                                    const double *__restrict__ b,
                                                    const double *__restrict__ wlist,
                                                    Coef2D<double> k2, int strips_x, int chunks_y,
-                                                   int nblocks)
+                                                   int nblocks, double *__restrict__ part)
 {
     const int per_xcd = (nblocks + 7) / 8;
     const int logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int item = logical * 4 + (threadIdx.x >> 6);
     if (logical >= nblocks || item >= strips_x * chunks_y) return;  // whole wave leaves
-    wave2d_pp_run<T>(n0, n1, x, xo, ec, b, wlist, k2, item % strips_x, item / strips_x,
-                     threadIdx.x & 63);
+    wave2d_pp_run<T, NORM>(n0, n1, x, xo, ec, b, wlist, k2, item % strips_x, item / strips_x,
+                           threadIdx.x & 63, part, item);
+}
+
+// Strip chunks of the interpolating pass with T sweeps: one residual-norm
+// partial each when it forms the norm.
+int64_t pp_items(const DevProblem &P, int T)
+{
+    const int64_t OW = 64 - 2 * ((T + 1) | 1);
+    return ((P.n0 + OW - 1) / OW) * ((P.n1 + kResOH - 1) / kResOH);
 }
 
 // x + P ec, then T (1 or 2) sweeps of a 2D constant-coefficient level into
-// xo with factors w_dev[0 .. T).
+// xo with factors w_dev[0 .. T); with part non-null also the sums of squares
+// of b - A xo, one per strip chunk (pp_items(P, T) of them).
 hipError_t launch_wave2d_pp(const DevProblem &P, int T, const double *x, double *xo,
-                            const double *ec, const double *w_dev, hipStream_t s)
+                            const double *ec, const double *w_dev, hipStream_t s,
+                            double *part = nullptr)
 {
     if (P.ndim != 2 || P.face[0] || P.face[1] || P.diag || T < 1 || T > 2 || P.n0 % 2 == 0 ||
         P.n1 % 2 == 0 || P.n0 < 3 || P.n1 < 3)
         return hipErrorInvalidValue;
     const Coef2D<double> k2{P.dconst, P.dinvconst, P.c[0], P.c[1]};
-    const int OW = 64 - 2 * (T + 1);
+    const int OW = 64 - 2 * ((T + 1) | 1);
     const int strips_x = (int)((P.n0 + OW - 1) / OW);
     const int chunks_y = (int)((P.n1 + kResOH - 1) / kResOH);
     const int64_t items = (int64_t)strips_x * chunks_y;
     const int nblocks = (int)((items + 3) / 4);
     const int grid = (nblocks + 7) / 8 * 8;
-    if (T == 1)
-        hipLaunchKernelGGL(k_wave2d_pp<1>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, ec,
-                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
-    else
-        hipLaunchKernelGGL(k_wave2d_pp<2>, dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, ec,
-                           P.b, w_dev, k2, strips_x, chunks_y, nblocks);
+#define SRJ_PP(TT, NN)                                                                          \
+    hipLaunchKernelGGL((k_wave2d_pp<TT, NN>), dim3(grid), dim3(256), 0, s, P.n0, P.n1, x, xo, ec, \
+                       P.b, w_dev, k2, strips_x, chunks_y, nblocks, part)
+    if (T == 1) {
+        if (part) SRJ_PP(1, true);
+        else SRJ_PP(1, false);
+    } else {
+        if (part) SRJ_PP(2, true);
+        else SRJ_PP(2, false);
+    }
+#undef SRJ_PP
     return hipGetLastError();
 }
 
@@ -873,6 +923,8 @@ struct srj_mg {
     hipEvent_t ready = nullptr;     // the caller's null-stream work -> own
     std::vector<srj_ctx *> ctx;
     std::vector<double *> xb, bb;   // index 0 unused
+    double *np = nullptr;           // 2D: residual-norm partials of the finest level's last launch
+    int64_t np_cap = 0;
     std::vector<int64_t> npts;
     // V-cycles replayed from graphs: one per smoothing level, starting
     // buffer of the finest level and the options the cycle depends on
@@ -903,6 +955,7 @@ srj_status mg_free(srj_mg *g)
     for (srj_ctx *c : g->ctx) srj_destroy(c);
     for (double *p : g->xb) (void)hipFree(p);
     for (double *p : g->bb) (void)hipFree(p);
+    (void)hipFree(g->np);
     for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
     (void)hipFree(g->rec);
     if (g->ready) (void)hipEventDestroy(g->ready);
@@ -1042,6 +1095,16 @@ int tail_start(const srj_mg *g, int Lc)
     return -1;
 }
 
+// The V-cycle's closing norm is formed by its last launch (the finest 2D
+// level's interpolation with its only post-smoothing cycle) instead of a
+// pass of its own.
+bool fused_norm(const srj_mg *g, const srj_mg_opts *o, int level)
+{
+    const srj_ctx *c = g->ctx[0];
+    return g->ndim == 2 && g->np && o->post == 1 && c->factors[level].size() <= 2 &&
+           !c->profiling;
+}
+
 srj_status vcycle(MgRun &run, int l, int level, double *x0)
 {
     srj_mg *g = run.g;
@@ -1125,8 +1188,9 @@ srj_status vcycle(MgRun &run, int l, int level, double *x0)
         double *a = l == 0 ? x0 : g->xb[l];
         double *cur = run.cur[l];
         double *nxt = cur == a ? c->ws : a;
+        double *part = l == 0 && fused_norm(g, run.o, level) ? g->np : nullptr;
         SRJ_HIP_CHECK(launch_wave2d_pp(c->P, M, cur, nxt, run.cur[l + 1],
-                                       c->omega_dev + c->offsets[level], g->stream));
+                                       c->omega_dev + c->offsets[level], g->stream, part));
         run.cur[l] = nxt;
         sw += M;
         if ((st = pair_smooth(run.o->post - 1)) != SRJ_OK) return st;
@@ -1344,6 +1408,15 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
             if (fused_supported(c->P, sp)) g->short_plan[l] = sp;
         }
     }
+    if (g->ndim == 2) {
+        const DevProblem &P0 = g->ctx[0]->P;
+        g->np_cap = std::max(pp_items(P0, 1), pp_items(P0, 2));
+        if (hipMalloc(&g->np, sizeof(double) * (size_t)g->np_cap) != hipSuccess) {
+            g->np = nullptr;
+            mg_free(g);
+            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the multigrid norm partials");
+        }
+    }
     // the tail launches take up to kTailLdsDoubles doubles of dynamic LDS
     const void *tails[2] = {reinterpret_cast<const void *>(&k_mg_tail<true>),
                             reinterpret_cast<const void *>(&k_mg_tail<false>)};
@@ -1435,7 +1508,12 @@ static srj_status mg_solve_run(srj_mg *g, double *x, const srj_mg_opts *o, srj_m
             if (st != SRJ_OK) return st;
             vlevels.push_back(lv);
             double norm = 0.0;
-            if ((st = residual_norm(c0, run.cur[0], &norm)) != SRJ_OK) return st;
+            if (fused_norm(g, o, lv)) {
+                const int64_t n = pp_items(c0->P, (int)c0->factors[lv].size());
+                if ((st = fold_norm(c0, g->np, n, &norm)) != SRJ_OK) return st;
+            } else if ((st = residual_norm(c0, run.cur[0], &norm)) != SRJ_OK) {
+                return st;
+            }
             if (levels_out) levels_out[v] = lv;
             if (norms_out) norms_out[v + 1] = norm;
             res->vcycles = v + 1;
