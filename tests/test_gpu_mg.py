@@ -36,6 +36,9 @@ CASES = [
     ("2d_c2_recipe_127", lambda: workloads.c2(n=127), dict()),
     ("2d_95x47_fixed2", lambda: _rand([95, 47], 1), dict(rule="fixed", start_level=2)),
     ("2d_63_pre2_post0", lambda: _rand([63, 63], 2), dict(pre=2, post=0, max_level=5)),
+    # two post-smoothing cycles: the interpolating pass, then a plain cycle,
+    # and the closing norm in a pass of its own
+    ("2d_255_pre1_post2", lambda: _rand([255, 255], 6), dict(pre=1, post=2)),
     ("2d_255_3levels", lambda: _rand([255, 255], 3), dict(max_levels=3, coarse_tol=1e-6)),
     ("3d_31", lambda: _rand([31, 31, 31], 4), dict()),
     ("3d_aniso_63x31x15", lambda: workloads.anisotropic([63, 31, 15], [1.0, 0.3, 0.05],
