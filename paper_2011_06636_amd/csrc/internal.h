@@ -267,6 +267,12 @@ struct ResidentRecord {
     int32_t cap = 0;
 };
 srj_status resident_prepare(srj_ctx *c, int max_cycles);
+// The options of a resident solve of c's grid as the kernels take them, and
+// the device tables of level sizes and factor offsets that resident_prepare
+// made (for solves run by other kernels, such as the multigrid tail's).
+struct ResidentArgs;
+srj_status resident_tables(srj_ctx *c, const srj_solve_opts *o, ResidentArgs *a,
+                           const int32_t **level_m, const int32_t **offsets);
 srj_status resident_launch_recorded(srj_ctx *c, double *x, const srj_solve_opts *o,
                                     const ResidentRecord &rec);
 // Autotuner cache (tune.hip): key -> plan and time per sweep.

@@ -667,11 +667,13 @@ hipError_t launch_wave2d_pp(const DevProblem &P, int T, const double *x, double 
 // The coarse end of the V-cycle in three launches: every level from the
 // first one of at most kTailMaxPoints points down to the coarsest is held in
 // one workgroup's LDS (per level x, its ping-pong partner and b) by
-// k_mg_tail<true> (pre-smoothing, fine residual and restriction level by
-// level down), the coarsest grid is solved by the resident solver, and
-// k_mg_tail<false> interpolates and post-smooths level by level up.  The
-// operations are those of the kernels above and of the sweep kernels, in
-// their order, so the values are the same bits.  Thread p takes points p,
+// k_mg_tail<kTailDown> (pre-smoothing, fine residual and restriction level
+// by level down), the coarsest grid is solved by the resident solver, and
+// k_mg_tail<kTailUp> interpolates and post-smooths level by level up; a
+// one-point coarsest grid is solved inside a single launch instead
+// (k_mg_tail<kTailWhole>).  The operations are those of the kernels above,
+// of the sweep kernels and of the resident solver, in their order, so the
+// values are the same bits.  Thread p takes points p,
 // p + kThreads, ... of a level (every tail grid has at most kTailPerThread
 // kThreads points); the workgroup synchronises after every pass.
 constexpr int kTailMaxLevels = 12;
@@ -697,7 +699,16 @@ struct TailArgs {
     TailLevel lv[kTailMaxLevels];
     double *xg[kTailMaxLevels];  // each level's correction in global memory
     double *bg[kTailMaxLevels];  // and its right-hand side
+    // kTailWhole: the coarsest grid's solve (one point) inside the launch
+    ResidentArgs ra;             // its options
+    const double *omega;         // the factor table
+    const int32_t *level_m, *offsets;
+    ResidentRecord rec;          // where its sweep count goes
 };
+
+// What a tail launch runs: down to the coarsest grid, back up from it, or
+// both around a one-point coarsest grid solved in the launch.
+constexpr int kTailDown = 0, kTailUp = 1, kTailWhole = 2;
 
 // Per-level values of the tail, copied into LDS once: every pass reads its
 // level's sizes and constants from there.
@@ -707,11 +718,67 @@ struct TailTab {
     const double *w;
 };
 
-// DOWN: from the first tail level's b (in bg[0]) down to the coarsest
+// The solve of a one-point coarsest grid, A u = b with A = D, as the
+// single-wave resident kernel runs it for that grid: from u, cycles of the
+// scheme Algorithm 1 picks (section 3) with the factors of Eq. (17) in the
+// library's order, u <- u + w (1/D) (b - D u), the norm |b - D u| (the
+// square root of the one square) after each cycle, the same stop tests and
+// the same level arithmetic, so every value and count is the same.  Returns
+// the status; sweeps counts the sweeps run.
+__device__ int point_solve(double &u, double bv, double D, double Dinv,
+                           const double *__restrict__ omega, const int32_t *__restrict__ level_m,
+                           const int32_t *__restrict__ offsets, const ResidentArgs &a,
+                           int64_t &sweeps)
+{
+    auto norm_of = [&]() {
+        const double r = bv - D * u;
+        return sqrt(r * r);
+    };
+    const double norm0 = norm_of();
+    const double r0 = a.r0_given > 0.0 ? a.r0_given : norm0;
+    const double target = a.tol_mode == SRJ_TOL_RELATIVE ? a.tol * r0 : a.tol;
+    int status = SRJ_ERR_NOT_CONVERGED, level = a.start_level;
+    double prev = norm0;
+    sweeps = 0;
+    if (!isfinite(norm0)) return SRJ_ERR_NONFINITE;
+    if (norm0 == 0.0 || norm0 < target) return SRJ_OK;
+    for (int cycle = 0; cycle < a.max_cycles; ++cycle) {
+        const int lv = a.rule == SRJ_RULE_FIXED ? a.fixed_level : level;
+        const int M = level_m[lv];
+        if (sweeps + M > a.max_sweeps) break;
+        const double *w = omega + offsets[lv];
+        for (int j = 0; j < M; ++j) {
+            const double r = bv - D * u;
+            const double tt = Dinv * r;
+            u = u + w[j] * tt;
+        }
+        sweeps += M;
+        const double norm = norm_of();
+        if (!isfinite(norm)) return SRJ_ERR_NONFINITE;
+        if (norm < target) return SRJ_OK;
+        const double ratio = norm / prev;
+        prev = norm;
+        int nl = level;
+        if (a.rule == SRJ_RULE_HEURISTIC) {
+            if (ratio > 0.4)
+                nl = level + 1;
+            else if (ratio < 0.4 && ratio > 0.2)
+                nl = level - 1;
+        } else if (a.rule == SRJ_RULE_INCREASING) {
+            nl = level + 1;
+        }
+        level = nl < 0 ? 0 : (nl > a.max_level ? a.max_level : nl);
+    }
+    return status;
+}
+
+// kTailDown: from the first tail level's b (in bg[0]) down to the coarsest
 // grid's b, leaving every level's pre-smoothed correction and b in xg / bg
-// (the coarsest correction zero); !DOWN: from those and the coarsest
-// solution back up, the first level's correction to xg[0].
-template <bool DOWN>
+// (the coarsest correction zero); kTailUp: from those and the coarsest
+// solution back up, the first level's correction to xg[0]; kTailWhole: both
+// without the round trip through xg / bg, around the solve of a one-point
+// coarsest grid (point_solve).
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
 {
     extern __shared__ double lds[];
@@ -789,7 +856,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
             }
         }
     };
-    if constexpr (DOWN) {
+    if constexpr (MODE != kTailUp) {
         for (int q = p; q < tab[0].N; q += kThreads) {
             bbuf(0)[q] = t.bg[0][q];
             xbuf(0)[q] = 0.0;
@@ -827,18 +894,41 @@ __global__ __launch_bounds__(kThreads) void k_mg_tail(TailArgs t)
             }
             __syncthreads();
         }
-        for (int l = 0; l < t.count; ++l)
-            for (int q = p; q < tab[l].N; q += kThreads) {
-                t.xg[l][q] = xbuf(l)[q];
-                if (l > 0) t.bg[l][q] = bbuf(l)[q];
-            }
-    } else {
-        for (int l = 0; l < t.count; ++l)
-            for (int q = p; q < tab[l].N; q += kThreads) {
-                xbuf(l)[q] = t.xg[l][q];
-                if (l + 1 < t.count) bbuf(l)[q] = t.bg[l][q];
-            }
+        if constexpr (MODE == kTailDown)
+            for (int l = 0; l < t.count; ++l)
+                for (int q = p; q < tab[l].N; q += kThreads) {
+                    t.xg[l][q] = xbuf(l)[q];
+                    if (l > 0) t.bg[l][q] = bbuf(l)[q];
+                }
+    }
+    if constexpr (MODE == kTailWhole) {
+        // every thread runs the same scalar solve on the same LDS values
+        const int lc = t.count - 1;
+        const TailTab e = tab[lc];
+        double u = xbuf(lc)[0];
+        const double bv = bbuf(lc)[0];
+        int64_t sweeps = 0;
+        const int status = point_solve(u, bv, e.D, e.Dinv, t.omega, t.level_m, t.offsets, t.ra,
+                                       sweeps);
+        __syncthreads();  // every thread has read the coarsest values
+        if (p == 0) {
+            xbuf(lc)[0] = u;
+            const int32_t i = *t.rec.count;
+            if (i < t.rec.cap) t.rec.sweeps[i] = sweeps;
+            *t.rec.count = i + 1;
+            if (status != SRJ_OK && status != SRJ_ERR_NOT_CONVERGED) *t.rec.bad = status;
+        }
         __syncthreads();
+    }
+    if constexpr (MODE != kTailDown) {
+        if constexpr (MODE == kTailUp) {
+            for (int l = 0; l < t.count; ++l)
+                for (int q = p; q < tab[l].N; q += kThreads) {
+                    xbuf(l)[q] = t.xg[l][q];
+                    if (l + 1 < t.count) bbuf(l)[q] = t.bg[l][q];
+                }
+            __syncthreads();
+        }
         for (int l = t.count - 2; l >= 0; --l) {
             // x += P e: per axis the candidates in increasing order
             const TailTab e = tab[l], ec = tab[l + 1];
@@ -1060,9 +1150,6 @@ srj_status launch_tail(MgRun &run, int level)
         off += (int32_t)(3 * g->npts[Ls + k]);
     }
     const size_t shmem = sizeof(double) * (size_t)off;
-    hipLaunchKernelGGL(k_mg_tail<true>, dim3(1), dim3(kThreads), shmem, g->stream, t);
-    SRJ_HIP_CHECK(hipGetLastError());
-    // the coarsest grid, from the zero correction the first launch left
     ResidentRecord rec;
     char *base = static_cast<char *>(g->rec);
     rec.count = reinterpret_cast<int32_t *>(base);
@@ -1071,10 +1158,22 @@ srj_status launch_tail(MgRun &run, int level)
     rec.cap = g->rec_cap;
     srj_ctx *cc = g->ctx[run.Lc];
     const srj_solve_opts so = coarse_opts(cc, run.o);
-    srj_status st = resident_launch_recorded(cc, g->xb[run.Lc], &so, rec);
-    if (st != SRJ_OK) return st;
-    hipLaunchKernelGGL(k_mg_tail<false>, dim3(1), dim3(kThreads), shmem, g->stream, t);
-    SRJ_HIP_CHECK(hipGetLastError());
+    srj_status st = SRJ_OK;
+    if (g->npts[run.Lc] == 1) {
+        // a one-point coarsest grid is solved inside the one launch
+        if ((st = resident_tables(cc, &so, &t.ra, &t.level_m, &t.offsets)) != SRJ_OK) return st;
+        t.omega = cc->omega_dev;
+        t.rec = rec;
+        hipLaunchKernelGGL(k_mg_tail<kTailWhole>, dim3(1), dim3(kThreads), shmem, g->stream, t);
+        SRJ_HIP_CHECK(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(k_mg_tail<kTailDown>, dim3(1), dim3(kThreads), shmem, g->stream, t);
+        SRJ_HIP_CHECK(hipGetLastError());
+        // the coarsest grid, from the zero correction the first launch left
+        if ((st = resident_launch_recorded(cc, g->xb[run.Lc], &so, rec)) != SRJ_OK) return st;
+        hipLaunchKernelGGL(k_mg_tail<kTailUp>, dim3(1), dim3(kThreads), shmem, g->stream, t);
+        SRJ_HIP_CHECK(hipGetLastError());
+    }
     run.cur[Ls] = g->xb[Ls];
     return SRJ_OK;
 }
@@ -1418,8 +1517,9 @@ srj_status srj_mg_setup(const srj_problem *p, void *hip_stream, srj_mg **out)
         }
     }
     // the tail launches take up to kTailLdsDoubles doubles of dynamic LDS
-    const void *tails[2] = {reinterpret_cast<const void *>(&k_mg_tail<true>),
-                            reinterpret_cast<const void *>(&k_mg_tail<false>)};
+    const void *tails[3] = {reinterpret_cast<const void *>(&k_mg_tail<kTailDown>),
+                            reinterpret_cast<const void *>(&k_mg_tail<kTailUp>),
+                            reinterpret_cast<const void *>(&k_mg_tail<kTailWhole>)};
     for (const void *f : tails) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)(sizeof(double) * kTailLdsDoubles));

@@ -386,6 +386,18 @@ srj_status resident_prepare(srj_ctx *c, int max_cycles)
     return SRJ_OK;
 }
 
+srj_status resident_tables(srj_ctx *c, const srj_solve_opts *o, ResidentArgs *a,
+                           const int32_t **level_m, const int32_t **offsets)
+{
+    if (o->tol_mode == SRJ_TOL_UPDATE_INF || o->max_cycles > c->rs_cap || !c->rs_fixed)
+        return fail(SRJ_ERR_INVALID, "resident tables: buffers not prepared for these options");
+    const char *fixed = static_cast<const char *>(c->rs_fixed);
+    *level_m = reinterpret_cast<const int32_t *>(fixed + kOutBytes);
+    *offsets = reinterpret_cast<const int32_t *>(fixed + kOutBytes + kLmBytes);
+    *a = resident_args(o);
+    return SRJ_OK;
+}
+
 srj_status resident_launch_recorded(srj_ctx *c, double *x, const srj_solve_opts *o,
                                     const ResidentRecord &rec)
 {
