@@ -154,7 +154,10 @@ __global__ __launch_bounds__(64) void k_resident_wave1d(DevProblem P, double *__
                         const double r = bv[k] - row(u, k, left, right);
                         const double t = Dinv * r;
                         const double xn = u[k] + wj * t;
-                        un[k] = in[k] ? xn : 0.0;
+                        // points past N are never read by a point of the grid (its
+                        // neighbour terms beyond N - 1 are omitted), so whatever
+                        // the sweep makes of them stays unused: no select
+                        un[k] = xn;
                         if (UPD && in[k]) {
                             const unsigned long long d =
                                 (unsigned long long)__double_as_longlong(fabs(xn - u[k]));
