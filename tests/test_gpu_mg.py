@@ -6,9 +6,10 @@ iterate must be bit-identical, the smoothing scheme of every V-cycle the
 same, the counters (fine sweeps, coarsest-solve sweeps, work) equal, and the
 V-cycle norms equal to 1e-12 (sums in another order; on grids of more than
 about 9000 points to the error bound of the oracle's sequential sum).  Grids: 1D, 2D with
-unequal sides that stop coarsening at an even size, 3D, a hierarchy cut by
-max_levels, fixed and heuristic smoothing schemes, pre/post counts, and the
-benchmark's full 2047^2 and 255^3 problems."""
+unequal sides that stop coarsening at an even size, thin 2D and 3D grids
+whose coarse levels have one row, 3D, a hierarchy cut by max_levels, fixed
+and heuristic smoothing schemes, pre/post counts, and the benchmark's full
+2047^2 and 255^3 problems."""
 import numpy as np
 import pytest
 
@@ -46,6 +47,14 @@ CASES = [
      dict(rule="fixed", start_level=3)),
     # rows of at least 64 per plane are dealt to the XCDs in bands (3D)
     ("3d_127x127x7", lambda: _rand([127, 127, 7], 9), dict()),
+    # thin grids: strips and chunks mostly outside the grid in the fused 2D
+    # passes, coarse grids of one row or column, a tail whose coarsest grid
+    # has 1023 points, 3D levels of one or three rows and planes
+    ("2d_255x7", lambda: _rand([255, 7], 10), dict()),
+    ("2d_7x255", lambda: _rand([7, 255], 11), dict()),
+    ("2d_2047x3", lambda: _rand([2047, 3], 12), dict()),
+    ("3d_1023x3x3", lambda: _rand([1023, 3, 3], 13), dict()),
+    ("3d_3x1023x3", lambda: _rand([3, 1023, 3], 14), dict()),
     # the benchmark's grids, as bench.py solves them (graph replays, the
     # one-workgroup tail, the single-wave coarsest solve)
     ("2d_c2_recipe_2047_full", lambda: workloads.c2(n=2047), dict(tol=2e-9)),
