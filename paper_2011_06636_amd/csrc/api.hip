@@ -284,9 +284,7 @@ srj_status collect_profile(srj_ctx *c)
 srj_status residual_norm(srj_ctx *c, const double *x, double *out)
 {
     SRJ_HIP_CHECK(launch_residual_sumsq(c->P, x, c->rs, c->stream));
-    SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
-    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));  // the fold wrote *rs.host_sum
     *out = sqrt(*c->rs.host_sum);
     return collect_profile(c);
 }
@@ -297,9 +295,7 @@ srj_status fold_norm(srj_ctx *c, double *partials, int64_t n, double *out)
     rs.partials = partials;
     rs.capacity = n;
     SRJ_HIP_CHECK(launch_fold(rs, n, c->stream));
-    SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
-    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));  // the fold wrote *rs.host_sum
     *out = sqrt(*c->rs.host_sum);
     return collect_profile(c);
 }
@@ -373,8 +369,7 @@ srj_status srj_destroy(srj_ctx *c)
     (void)hipFree(c->omega_dev);
     (void)hipFree(c->omega32_dev);
     (void)hipFree(c->rs.partials);
-    (void)hipFree(c->rs.sum);
-    (void)hipHostFree(c->rs.host_sum);
+    (void)hipHostFree(c->rs.host_sum);  // rs.sum is its device mapping
     delete c;
     return SRJ_OK;
 }
@@ -478,9 +473,11 @@ static srj_status ctx_finish(srj_ctx *c)
     c->rs.capacity = residual_blocks(P);
     if (e == hipSuccess && hipMalloc(&c->rs.partials, sizeof(double) * c->rs.capacity) != hipSuccess)
         return nomem("reduction partials");
-    if (e == hipSuccess && hipMalloc(&c->rs.sum, sizeof(double)) != hipSuccess) return nomem("sum");
     if (e == hipSuccess && hipHostMalloc(&c->rs.host_sum, sizeof(double), 0) != hipSuccess)
         return nomem("pinned scalar");
+    // the fold writes the sum straight into the pinned scalar through its
+    // device mapping: no copy launch after each norm
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->rs.sum, c->rs.host_sum, 0);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         srj_destroy(c);

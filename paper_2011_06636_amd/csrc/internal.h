@@ -96,8 +96,8 @@ struct DevProblem32 {
 struct ReduceScratch {
     double *partials = nullptr;
     int64_t capacity = 0;
-    double *sum = nullptr;       // device scalar
-    double *host_sum = nullptr;  // pinned host scalar
+    double *sum = nullptr;       // the device's address of host_sum, where the fold writes
+    double *host_sum = nullptr;  // pinned host scalar, valid after the stream is synchronized
 };
 
 // ---------------------------------------------------------------------------

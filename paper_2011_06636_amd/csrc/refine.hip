@@ -668,9 +668,7 @@ srj_status solve_t(srj_ctx *c, double *x, const srj_solve_opts *o, srj_solve_res
             SRJ_HIP_CHECK(launch_outer<St>(true, c->P, cur, da, 1.0 / s, nxt, R->rhat, s_next,
                                            c->rs.partials, c->stream));
             std::swap(cur, nxt);
-            SRJ_HIP_CHECK(launch_fold(c->rs, nb, c->stream));
-            SRJ_HIP_CHECK(hipMemcpyAsync(c->rs.host_sum, c->rs.sum, sizeof(double),
-                                         hipMemcpyDeviceToHost, c->stream));
+            SRJ_HIP_CHECK(launch_fold(c->rs, nb, c->stream));  // into *rs.host_sum
             SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));
             st = collect_profile(c);
             if (st != SRJ_OK) return st;
