@@ -359,6 +359,7 @@ srj_status srj_destroy(srj_ctx *c)
     (void)hipFree(c->rs_fixed);
     (void)hipFree(c->rs_levels);
     (void)hipFree(c->rs_norms);
+    (void)hipHostFree(c->rs_host);
     for (void *q : {(void *)c->csr_diag, (void *)c->csr_b, (void *)c->csr_val, (void *)c->csr_len,
                     (void *)c->csr_col})
         (void)hipFree(q);

@@ -222,6 +222,12 @@ struct srj_ctx {
     int32_t *rs_levels = nullptr;
     double *rs_norms = nullptr;
     int64_t rs_cap = 0;
+    // what the tables of rs_fixed hold (level sizes, then offsets; empty
+    // before the first upload), and a pinned host mirror of the record and
+    // the histories that one launch fills after each solve (rs_host_dev: its
+    // device mapping)
+    std::vector<int32_t> rs_tables;
+    void *rs_host = nullptr, *rs_host_dev = nullptr;
     // library copies of a general sparse matrix (srj_setup_csr)
     double *csr_diag = nullptr, *csr_b = nullptr, *csr_val = nullptr;
     int32_t *csr_len = nullptr, *csr_col = nullptr;

@@ -12,6 +12,7 @@
 // binary64 expression of the other kernels, so iterates are bit-identical;
 // the norms differ from the multi-kernel path only in summation order.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <string>
@@ -293,8 +294,29 @@ ResidentArgs resident_args(const srj_solve_opts *o)
     return a;
 }
 
+// Layout of the pinned mirror: the record, then the norms (cap + 1), then
+// the levels (cap).
+size_t mirror_bytes(int64_t cap) { return kOutBytes + sizeof(double) * (size_t)(cap + 1) + sizeof(int32_t) * (size_t)cap; }
+
+// After a solve: the record and its cycles' levels and norms into the mirror
+// (host memory, written through its device mapping).
+__global__ __launch_bounds__(256) void k_resident_publish(const ResidentOut *__restrict__ dout,
+                                                          const int32_t *__restrict__ lh,
+                                                          const double *__restrict__ nh,
+                                                          char *__restrict__ mirror, int64_t cap)
+{
+    const ResidentOut h = *dout;
+    const int64_t nc = h.cycles < 0 ? 0 : (h.cycles > cap ? cap : h.cycles);
+    double *mn = reinterpret_cast<double *>(mirror + kOutBytes);
+    int32_t *ml = reinterpret_cast<int32_t *>(mirror + kOutBytes + sizeof(double) * (cap + 1));
+    for (int64_t k = threadIdx.x; k <= nc; k += blockDim.x) mn[k] = nh[k];
+    for (int64_t k = threadIdx.x; k < nc; k += blockDim.x) ml[k] = lh[k];
+    if (threadIdx.x == 0) *reinterpret_cast<ResidentOut *>(mirror) = h;
+}
+
 // Device buffers kept by the context from one solve to the next: the result
-// record, the level sizes and offsets (fixed size), the histories.
+// record, the level sizes and offsets (fixed size), the histories, and the
+// pinned mirror of the record and histories.
 srj_status resident_buffers(srj_ctx *c, int max_cycles)
 {
     static_assert(sizeof(ResidentOut) <= kOutBytes, "result record");
@@ -309,26 +331,46 @@ srj_status resident_buffers(srj_ctx *c, int max_cycles)
     if (c->rs_cap < max_cycles) {
         (void)hipFree(c->rs_levels);
         (void)hipFree(c->rs_norms);
+        (void)hipHostFree(c->rs_host);
         c->rs_levels = nullptr;
         c->rs_norms = nullptr;
+        c->rs_host = c->rs_host_dev = nullptr;
         c->rs_cap = 0;
         if (hipMalloc(&c->rs_levels, sizeof(int32_t) * (size_t)max_cycles) != hipSuccess ||
-            hipMalloc(&c->rs_norms, sizeof(double) * ((size_t)max_cycles + 1)) != hipSuccess) {
+            hipMalloc(&c->rs_norms, sizeof(double) * ((size_t)max_cycles + 1)) != hipSuccess ||
+            hipHostMalloc(&c->rs_host, mirror_bytes(max_cycles), 0) != hipSuccess ||
+            hipHostGetDevicePointer(&c->rs_host_dev, c->rs_host, 0) != hipSuccess) {
             (void)hipFree(c->rs_levels);
+            (void)hipFree(c->rs_norms);
+            (void)hipHostFree(c->rs_host);
             c->rs_levels = nullptr;
             c->rs_norms = nullptr;
-            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for resident solve");
+            c->rs_host = c->rs_host_dev = nullptr;
+            return fail(SRJ_ERR_NOMEM, "allocation failed for resident solve");
         }
         c->rs_cap = max_cycles;
     }
     return SRJ_OK;
 }
 
-std::vector<int32_t> level_sizes(const srj_ctx *c)
+// The level sizes and the offsets of c's scheme family into the tables of
+// rs_fixed, on c's stream, when they differ from what the tables hold.
+srj_status resident_upload_tables(srj_ctx *c)
 {
-    std::vector<int32_t> lmh(SRJ_NUM_LEVELS);
-    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) lmh[l] = l < c->nlevels ? c->levelM[l] : 0;
-    return lmh;
+    std::vector<int32_t> t(SRJ_NUM_LEVELS);
+    for (int l = 0; l < SRJ_NUM_LEVELS; ++l) t[l] = l < c->nlevels ? c->levelM[l] : 0;
+    t.insert(t.end(), c->offsets.begin(), c->offsets.end());
+    if (t == c->rs_tables) return SRJ_OK;
+    c->rs_tables.clear();
+    char *fixed = static_cast<char *>(c->rs_fixed);
+    SRJ_HIP_CHECK(hipMemcpyAsync(fixed + kOutBytes, t.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
+                                 hipMemcpyHostToDevice, c->stream));
+    SRJ_HIP_CHECK(hipMemcpyAsync(fixed + kOutBytes + kLmBytes, t.data() + SRJ_NUM_LEVELS,
+                                 sizeof(int32_t) * c->offsets.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+    SRJ_HIP_CHECK(hipStreamSynchronize(c->stream));  // t is a local buffer
+    c->rs_tables = std::move(t);
+    return SRJ_OK;
 }
 
 size_t resident_shmem(int64_t N) { return sizeof(double) * (size_t)(2 * N + kThreads / 64 + 1); }
@@ -380,13 +422,7 @@ srj_status resident_prepare(srj_ctx *c, int max_cycles)
 {
     srj_status st = resident_buffers(c, max_cycles);
     if (st != SRJ_OK) return st;
-    char *fixed = static_cast<char *>(c->rs_fixed);
-    const std::vector<int32_t> lmh = level_sizes(c);
-    SRJ_HIP_CHECK(hipMemcpy(fixed + kOutBytes, lmh.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
-                            hipMemcpyHostToDevice));
-    SRJ_HIP_CHECK(hipMemcpy(fixed + kOutBytes + kLmBytes, c->offsets.data(),
-                            sizeof(int32_t) * c->offsets.size(), hipMemcpyHostToDevice));
-    return SRJ_OK;
+    return resident_upload_tables(c);
 }
 
 srj_status resident_tables(srj_ctx *c, const srj_solve_opts *o, ResidentArgs *a,
@@ -419,10 +455,9 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
                           int32_t *levels_out, double *norms_out)
 {
     const ResidentArgs a = resident_args(o);
-    const int64_t N = c->npoints;
-    const std::vector<int32_t> lmh = level_sizes(c);
     {
-        const srj_status sb = resident_buffers(c, o->max_cycles);
+        srj_status sb = resident_buffers(c, o->max_cycles);
+        if (sb == SRJ_OK) sb = resident_upload_tables(c);
         if (sb != SRJ_OK) return sb;
     }
     int32_t *lh = c->rs_levels;
@@ -433,13 +468,9 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
     int32_t *offs = reinterpret_cast<int32_t *>(fixed + kOutBytes + kLmBytes);
     srj_status st = SRJ_OK;
     ResidentOut h{};
-    if (st == SRJ_OK) {
-        hipError_t e = hipMemcpyAsync(lm, lmh.data(), sizeof(int32_t) * SRJ_NUM_LEVELS,
-                                      hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(offs, c->offsets.data(), sizeof(int32_t) * c->offsets.size(),
-                               hipMemcpyHostToDevice, c->stream);
-        if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
+    {
+        hipError_t e = hipSuccess;
+        if (c->profiling) e = hipEventRecord(c->ev0, c->stream);
         if (e == hipSuccess) {
             if (a.tol_mode == SRJ_TOL_UPDATE_INF)
                 launch_resident<true>(c, x, offs, lm, a, lh, nh, dout, ResidentRecord{});
@@ -448,15 +479,21 @@ srj_status resident_solve(srj_ctx *c, double *x, const srj_solve_opts *o, srj_so
             e = hipGetLastError();
         }
         if (c->profiling && e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&h, dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_resident_publish, dim3(1), dim3(256), 0, c->stream, dout, lh, nh,
+                               static_cast<char *>(c->rs_host_dev), c->rs_cap);
+            e = hipGetLastError();
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e == hipSuccess && levels_out && o->max_cycles > 0)
-            e = hipMemcpy(levels_out, lh, sizeof(int32_t) * (size_t)o->max_cycles,
-                          hipMemcpyDeviceToHost);
-        if (e == hipSuccess && norms_out)
-            e = hipMemcpy(norms_out, nh, sizeof(double) * ((size_t)h.cycles + 1),
-                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            const char *m = static_cast<const char *>(c->rs_host);
+            memcpy(&h, m, sizeof(h));
+            const int64_t nc = std::min<int64_t>(std::max(h.cycles, 0), c->rs_cap);
+            if (norms_out) memcpy(norms_out, m + kOutBytes, sizeof(double) * (size_t)(nc + 1));
+            if (levels_out)
+                memcpy(levels_out, m + kOutBytes + sizeof(double) * (size_t)(c->rs_cap + 1),
+                       sizeof(int32_t) * (size_t)nc);
+        }
         if (e == hipSuccess && c->profiling) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
