@@ -1029,6 +1029,9 @@ struct srj_mg {
     // device record of the coarsest solves: count, bad status, sweeps[rec_cap]
     void *rec = nullptr;
     int32_t rec_cap = 0;
+    // pinned host mirror of the record, filled by one launch after a solve
+    // (rec_host_dev: its device mapping)
+    void *rec_host = nullptr, *rec_host_dev = nullptr;
     std::vector<int> prepared;      // per level: resident buffers made for this many cycles
     // per level: the plan for smoothing cycles of at most two sweeps (2D
     // grids whose default plan fuses many sweeps per launch), kind 0 if none
@@ -1036,6 +1039,13 @@ struct srj_mg {
 };
 
 namespace {
+
+// words 8-byte words of the device record into its pinned host mirror
+__global__ __launch_bounds__(256) void k_mg_publish(const int64_t *__restrict__ rec,
+                                                    int64_t *__restrict__ mirror, int64_t words)
+{
+    for (int64_t k = threadIdx.x; k < words; k += blockDim.x) mirror[k] = rec[k];
+}
 
 srj_status mg_free(srj_mg *g)
 {
@@ -1048,6 +1058,7 @@ srj_status mg_free(srj_mg *g)
     (void)hipFree(g->np);
     for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
     (void)hipFree(g->rec);
+    (void)hipHostFree(g->rec_host);
     if (g->ready) (void)hipEventDestroy(g->ready);
     if (g->own) (void)hipStreamDestroy(g->own);
     delete g;
@@ -1370,11 +1381,16 @@ srj_status prepare_graphs(srj_mg *g, const srj_mg_opts *o, int Lc)
         for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
         g->graphs.clear();
         (void)hipFree(g->rec);
-        g->rec = nullptr;
+        (void)hipHostFree(g->rec_host);
+        g->rec = g->rec_host = g->rec_host_dev = nullptr;
         g->rec_cap = 0;
-        if (hipMalloc(&g->rec, 8 + sizeof(int64_t) * (size_t)o->max_vcycles) != hipSuccess) {
-            g->rec = nullptr;
-            return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the multigrid record");
+        const size_t bytes = 8 + sizeof(int64_t) * (size_t)o->max_vcycles;
+        if (hipMalloc(&g->rec, bytes) != hipSuccess || hipHostMalloc(&g->rec_host, bytes, 0) != hipSuccess ||
+            hipHostGetDevicePointer(&g->rec_host_dev, g->rec_host, 0) != hipSuccess) {
+            (void)hipFree(g->rec);
+            (void)hipHostFree(g->rec_host);
+            g->rec = g->rec_host = g->rec_host_dev = nullptr;
+            return fail(SRJ_ERR_NOMEM, "allocation failed for the multigrid record");
         }
         g->rec_cap = o->max_vcycles;
     }
@@ -1637,17 +1653,25 @@ static srj_status mg_solve_run(srj_mg *g, double *x, const srj_mg_opts *o, srj_m
     if (run.cur[0] != x)
         SRJ_HIP_CHECK(hipMemcpyAsync(x, run.cur[0], sizeof(double) * (size_t)g->npts[0],
                                      hipMemcpyDeviceToDevice, g->stream));
+    const bool recorded = run.graph && !vlevels.empty();
+    if (recorded) {
+        // the record's head and one count per V-cycle into the pinned mirror
+        const int64_t words = 1 + (int64_t)std::min<size_t>(vlevels.size(), (size_t)g->rec_cap);
+        hipLaunchKernelGGL(k_mg_publish, dim3(1), dim3(256), 0, g->stream,
+                           static_cast<const int64_t *>(g->rec),
+                           static_cast<int64_t *>(g->rec_host_dev), words);
+        SRJ_HIP_CHECK(hipGetLastError());
+    }
     SRJ_HIP_CHECK(hipStreamSynchronize(g->stream));
-    if (run.graph && !vlevels.empty()) {
+    if (recorded) {
         // the counters in the order the launches made them: per V-cycle the
         // coarsest solve, then the levels from the coarsest up
         int32_t head[2] = {0, 0};
-        SRJ_HIP_CHECK(hipMemcpy(head, g->rec, sizeof(head), hipMemcpyDeviceToHost));
+        memcpy(head, g->rec_host, sizeof(head));
         if (head[0] != (int32_t)vlevels.size())
             return fail(SRJ_ERR_HIP, "multigrid record holds a different number of coarsest solves");
         std::vector<int64_t> cs(vlevels.size());
-        SRJ_HIP_CHECK(hipMemcpy(cs.data(), static_cast<char *>(g->rec) + 8,
-                                sizeof(int64_t) * cs.size(), hipMemcpyDeviceToHost));
+        memcpy(cs.data(), static_cast<const char *>(g->rec_host) + 8, sizeof(int64_t) * cs.size());
         for (size_t v = 0; v < vlevels.size(); ++v) {
             res->coarse_sweeps += cs[v];
             res->work += (double)cs[v] * ((double)g->npts[run.Lc] / (double)g->npts[0]);
