@@ -558,6 +558,33 @@ def test_resident_solve(torch_cuda, orc, case):
     s.close()
 
 
+def test_resident_buffers_and_tables_across_solves(torch_cuda, orc):
+    # the record and histories come back through a pinned mirror sized by the
+    # largest cycle cap seen so far, and the level tables are sent only when
+    # the scheme family changed: one solver runs a shrinking, then a growing
+    # cap, a family of the paper's first six levels and the paper's family
+    # restored, each against the oracle
+    prob = workloads.c1()
+    s = _solver(prob)
+    fam = [orc.scheme(l) for l in range(6)]
+    steps = [(None, dict(tol=1e-10)), (None, dict(tol=1e-10, max_cycles=5)),
+             (None, dict(tol=1e-11, max_cycles=20000)), (fam, dict(tol=1e-10, max_level=5)),
+             ("paper", dict(tol=1e-10)), (None, dict(tol=1e-10, max_cycles=5))]
+    for i, (family, kw) in enumerate(steps):
+        if family is not None:
+            s.set_scheme_family(None if family == "paper" else family)
+        assert s.set_resident(True) == 0
+        print(f"resident step {i}: {kw}", flush=True)
+        a = s.solve(**kw)
+        ref = orc.solve(prob, **kw)
+        assert a["status"] == ref["status"], i
+        np.testing.assert_array_equal(a["levels"], ref["levels"])
+        assert a["sweeps"] == ref["sweeps"] and a["cycles"] == ref["cycles"], i
+        np.testing.assert_allclose(a["norms"], ref["norms"], rtol=1e-12, atol=0)
+        assert _close(a["x"].cpu().numpy(), ref["x"]), i
+    s.close()
+
+
 def test_resident_rejects_large(torch_cuda):
     from paper_2011_06636_amd import abi
     s = _solver(workloads.poisson([80, 80]))
