@@ -527,6 +527,8 @@ struct srj_batch {
     int32_t *levels_hist = nullptr;
     double *norms_hist = nullptr;
     int64_t hist_cap = 0;
+    // instances finished, counted on the device into pinned host memory
+    // (done_dev: the device mapping of done_host)
     int32_t *done_dev = nullptr, *done_host = nullptr;
     // plan
     int tile_rows = 24, halo = 4, T2 = 4, waves = 1, steps_per_graph = 16;
@@ -546,10 +548,9 @@ void batch_free(srj_batch *B)
     for (void *p : {(void *)B->desc, (void *)B->state, (void *)B->b, (void *)B->xa, (void *)B->xb,
                     B->ua, B->ub, B->rhat, (void *)B->items2, (void *)B->items3, (void *)B->oitems,
                     (void *)B->partials, (void *)B->levelM, (void *)B->offsets, (void *)B->omega64,
-                    (void *)B->omega32, (void *)B->levels_hist, (void *)B->norms_hist,
-                    (void *)B->done_dev})
+                    (void *)B->omega32, (void *)B->levels_hist, (void *)B->norms_hist})
         (void)hipFree(p);
-    (void)hipHostFree(B->done_host);
+    (void)hipHostFree(B->done_host);  // done_dev is its device mapping
     if (B->stream) (void)hipStreamDestroy(B->stream);
     delete B;
 }
@@ -844,9 +845,8 @@ srj_status batch_solve_t(srj_batch *B, double *const *xs, const srj_solve_opts *
             hipLaunchKernelGGL(k_count_done, dim3(1), dim3(256), 0, B->stream, B->state, n,
                                B->done_dev);
         }
-        hipError_t e = hipMemcpyAsync(B->done_host, B->done_dev, sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, B->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+        // k_count_done wrote the count straight into the pinned done_host
+        hipError_t e = hipStreamSynchronize(B->stream);
         if (e != hipSuccess) {
             status = fail(SRJ_ERR_HIP, std::string("batch step: ") + hipGetErrorString(e));
             break;
@@ -1031,8 +1031,8 @@ srj_status srj_batch_setup(int32_t count, const srj_problem *probs, void *hip_st
                            B->stream);
     if (hipMalloc(&B->state, sizeof(BState) * count) != hipSuccess ||
         hipMalloc(&B->desc, sizeof(BDesc) * count) != hipSuccess ||
-        hipMalloc(&B->done_dev, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(&B->done_host, sizeof(int32_t), 0) != hipSuccess)
+        hipHostMalloc(&B->done_host, sizeof(int32_t), 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&B->done_dev, B->done_host, 0) != hipSuccess)
         return nomem("batch state");
     if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) {
