@@ -356,6 +356,7 @@ srj_status srj_destroy(srj_ctx *c)
     refine_free(c);
     (void)hipFree(c->upd);
     (void)hipFree(c->updf);
+    (void)hipHostFree(c->updf_pub);
     (void)hipFree(c->rs_fixed);
     (void)hipFree(c->rs_levels);
     (void)hipFree(c->rs_norms);
@@ -731,8 +732,19 @@ static srj_status solve_update_inf_fused(srj_ctx *c, double *x, const srj_solve_
         c->updf = nullptr;
         return fail(SRJ_ERR_NOMEM, "hipMalloc failed for the update test state");
     }
+    if (!c->updf_pub) {
+        if (hipHostMalloc((void **)&c->updf_pub, 2 * sizeof(int64_t), 0) != hipSuccess) {
+            c->updf_pub = nullptr;
+            return fail(SRJ_ERR_NOMEM, "pinned allocation failed for the update test flag");
+        }
+        if (hipHostGetDevicePointer((void **)&c->updf_pub_dev, c->updf_pub, 0) != hipSuccess) {
+            (void)hipHostFree(c->updf_pub);
+            c->updf_pub = c->updf_pub_dev = nullptr;
+            return fail(SRJ_ERR_HIP, "no device mapping of the update test flag");
+        }
+    }
     SRJ_HIP_CHECK(hipMemsetAsync(c->updf, 0, sizeof(UpdFState), c->stream));
-    SRJ_HIP_CHECK(launch_upd_check(c->updf, 1, 0, 0, o->tol, c->stream));  // clears ring 0
+    SRJ_HIP_CHECK(launch_upd_check(c->updf, 1, 0, 0, o->tol, c->updf_pub_dev, c->stream));  // clears ring 0
     double norm0 = 0.0;
     srj_status st = residual_norm(c, x, &norm0);
     if (st != SRJ_OK) return st;
@@ -768,7 +780,7 @@ static srj_status solve_update_inf_fused(srj_ctx *c, double *x, const srj_solve_
             const int ring = (int)(nl & 1);
             SRJ_HIP_CHECK(launch_sweep_fused_upd(c->P, c->plan, cur, nxt, wdev + done, T, c->updf,
                                                  ring, c->stream, c->reverse));
-            SRJ_HIP_CHECK(launch_upd_check(c->updf, ring, T, g, o->tol, c->stream));
+            SRJ_HIP_CHECK(launch_upd_check(c->updf, ring, T, g, o->tol, c->updf_pub_dev, c->stream));
             c->reverse = !c->reverse;
             launches.push_back({g, T, done, cur, nxt});
             std::swap(cur, nxt);
@@ -778,10 +790,9 @@ static srj_status solve_update_inf_fused(srj_ctx *c, double *x, const srj_solve_
         double norm = 0.0;
         st = residual_norm(c, cur, &norm);  // synchronises the stream
         if (st != SRJ_OK) return st;
-        int32_t flag = 0;
-        int64_t stop = -1;
-        SRJ_HIP_CHECK(hipMemcpy(&flag, &c->updf->flag, sizeof(flag), hipMemcpyDeviceToHost));
-        if (flag) SRJ_HIP_CHECK(hipMemcpy(&stop, &c->updf->stop, sizeof(stop), hipMemcpyDeviceToHost));
+        // the cycle's last k_upd_check left flag and stop in pinned memory
+        const int32_t flag = (int32_t)c->updf_pub[0];
+        const int64_t stop = flag ? c->updf_pub[1] : -1;
         res->cycles = cycle + 1;
         res->final_level = lv;
         if (levels_out) levels_out[cycle] = lv;

@@ -149,8 +149,10 @@ hipError_t launch_sweep_fused_upd(const DevProblem &P, const SweepPlan &plan, co
 bool fused_upd_supported(const DevProblem &P, const SweepPlan &plan);
 // Folds the T sweeps of the launch that used `ring` (first global index g0),
 // sets flag/stop on the first below tol, and clears the other ring.  T = 0
-// only clears.
-hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, hipStream_t s);
+// only clears.  With pub non-null, also writes flag and stop to pub[0] and
+// pub[1] (pinned host memory, through its device mapping).
+hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, int64_t *pub,
+                            hipStream_t s);
 // Fused sweeps: applies w[0..T-1] (device pointer into the scheme table).
 // reverse alternates the block order of the block kernels (callers flip it
 // every launch); results do not depend on it.
@@ -216,6 +218,8 @@ struct srj_ctx {
     struct srj::Refine *refine = nullptr;  // refinement workspaces (lazily allocated)
     srj::UpdState *upd = nullptr;          // per-sweep update test (lazily allocated)
     srj::UpdFState *updf = nullptr;        // the same for fused sweeps (lazily allocated)
+    int64_t *updf_pub = nullptr;           // its flag and stop in pinned host memory
+    int64_t *updf_pub_dev = nullptr;       // (the device mapping of updf_pub)
     // one-workgroup solves: result record and level/offset tables (fixed
     // size), level and norm histories (grown to the largest max_cycles seen)
     void *rs_fixed = nullptr;

@@ -212,7 +212,7 @@ hipError_t launch_sweep_generic(const DevProblem &P, const double *x, double *xo
 // flag and stop.  Then the slots of the other ring are cleared for the next
 // launch.  Does nothing but the clearing once flag is set.
 __global__ __launch_bounds__(64) void k_upd_check(UpdFState *st, int ring, int T, int64_t g0,
-                                                  double tol)
+                                                  double tol, int64_t *pub)
 {
     const int lane = threadIdx.x;
     if (!st->flag && T > 0) {
@@ -231,14 +231,19 @@ __global__ __launch_bounds__(64) void k_upd_check(UpdFState *st, int ring, int T
             st->stop = g0 + (__builtin_ctzll(mask));
         }
     }
+    if (pub && lane == 0) {  // flag and stop for the host, in pinned memory
+        pub[0] = st->flag;
+        pub[1] = st->stop;
+    }
     for (int i = lane; i < kUpdFMaxT * kUpdFStripes; i += 64)
         st->maxbits[ring ^ 1][i / kUpdFStripes][(i % kUpdFStripes) * kUpdStride] = 0ull;
 }
 
-hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, hipStream_t s)
+hipError_t launch_upd_check(UpdFState *st, int ring, int T, int64_t g0, double tol, int64_t *pub,
+                            hipStream_t s)
 {
     if (!st || ring < 0 || ring > 1 || T < 0 || T > kUpdFMaxT) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_upd_check, dim3(1), dim3(64), 0, s, st, ring, T, g0, tol);
+    hipLaunchKernelGGL(k_upd_check, dim3(1), dim3(64), 0, s, st, ring, T, g0, tol, pub);
     return hipGetLastError();
 }
 
